@@ -1,0 +1,135 @@
+"""CPU oracle for the exact multi-objective shortest-path search.
+
+TEST INFRASTRUCTURE ONLY: imported by the test suite, by the smoke check and
+by the CPU-baseline leg of the benchmark, never by the product library.  It
+shares no code with the GPU path.
+
+``solve`` runs sequential NAMOA* as laid out in the paper's Algorithm 1 (see
+``namoa.cpp``); ``heuristic`` runs the per-objective reverse Dijkstra that
+supplies its admissible heuristic (paper, Section 4).
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "namoa.cpp")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+ZERO_H = 1
+WEAK_P = 2
+LAZY_PRUNEOPEN = 4
+
+STATUS = {0: "ok", 1: "bad input", 2: "label limit", 3: "time limit"}
+STAT_NAMES = ["pops", "goal_pops", "candidates", "unreachable", "frontier_pairs", "p_pairs",
+              "open_pairs", "inserted", "pruned", "killed", "max_open", "max_alpha"]
+INF = np.iinfo(np.int64).max
+
+
+def build(force: bool = False) -> str:
+    """Compile namoa.cpp with g++ into liboracle.so (next to this file)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-o", tmp, _SRC])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        lib = ctypes.CDLL(build())
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        i32p = ctypes.POINTER(ctypes.c_int32)
+        lib.oracle_namoa.restype = ctypes.c_void_p
+        lib.oracle_namoa.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_int, i64p, i32p, i32p,
+                                     ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                     ctypes.c_int64, ctypes.c_double]
+        lib.oracle_status.argtypes = [ctypes.c_void_p]
+        lib.oracle_size.restype = ctypes.c_int64
+        lib.oracle_size.argtypes = [ctypes.c_void_p]
+        lib.oracle_costs.argtypes = [ctypes.c_void_p, i64p]
+        lib.oracle_path_len.restype = ctypes.c_int64
+        lib.oracle_path_len.argtypes = [ctypes.c_void_p, ctypes.c_int64]
+        lib.oracle_path.argtypes = [ctypes.c_void_p, ctypes.c_int64, i32p]
+        lib.oracle_stats.argtypes = [ctypes.c_void_p, i64p, ctypes.POINTER(ctypes.c_double)]
+        lib.oracle_free.argtypes = [ctypes.c_void_p]
+        lib.oracle_heuristic.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_int, i64p, i32p,
+                                         i32p, ctypes.c_int, ctypes.c_int, i64p]
+        lib.oracle_dijkstra.argtypes = [ctypes.c_int, i64p, i32p, i64p, ctypes.c_int, i64p]
+        _lib = lib
+    return _lib
+
+
+def _ptr(a, t):
+    return a.ctypes.data_as(ctypes.POINTER(t))
+
+
+@dataclasses.dataclass
+class Front:
+    status: str
+    costs: np.ndarray          # int64[size, d], lexicographically ascending
+    paths: list                # list of int32 arc-id arrays
+    stats: dict
+
+
+def _arrays(g):
+    rp = np.ascontiguousarray(g.row_ptr, dtype=np.int64)
+    col = np.ascontiguousarray(g.col, dtype=np.int32)
+    cost = np.ascontiguousarray(g.cost, dtype=np.int32)
+    return rp, col, cost
+
+
+def solve(g, s: int, t: int, d: int | None = None, flags: int = 0, label_limit: int = 0,
+          time_limit: float = 0.0) -> Front:
+    """Exact Pareto front of s->t costs over the first d objectives of g."""
+    lib = _load()
+    d = g.D if d is None else d
+    rp, col, cost = _arrays(g)
+    r = lib.oracle_namoa(g.n, g.n_arcs, g.D, _ptr(rp, ctypes.c_int64), _ptr(col, ctypes.c_int32),
+                         _ptr(cost, ctypes.c_int32), int(s), int(t), int(d), int(flags),
+                         int(label_limit), float(time_limit))
+    try:
+        st = STATUS[lib.oracle_status(r)]
+        n = lib.oracle_size(r)
+        costs = np.zeros((n, d), dtype=np.int64)
+        if n:
+            lib.oracle_costs(r, _ptr(costs, ctypes.c_int64))
+        paths = []
+        for i in range(n):
+            ln = lib.oracle_path_len(r, i)
+            p = np.zeros(ln, dtype=np.int32)
+            if ln:
+                lib.oracle_path(r, i, _ptr(p, ctypes.c_int32))
+            paths.append(p)
+        sv = np.zeros(len(STAT_NAMES), dtype=np.int64)
+        secs = ctypes.c_double()
+        lib.oracle_stats(r, _ptr(sv, ctypes.c_int64), ctypes.byref(secs))
+        stats = dict(zip(STAT_NAMES, (int(x) for x in sv)))
+        stats["search_seconds"] = secs.value
+        stats["front"] = int(n)
+    finally:
+        lib.oracle_free(r)
+    return Front(st, costs, paths, stats)
+
+
+def heuristic(g, goal: int, d: int | None = None) -> np.ndarray:
+    """h[k, v] = shortest v->goal distance under objective k (INT64 max if unreachable)."""
+    lib = _load()
+    d = g.D if d is None else d
+    rp, col, cost = _arrays(g)
+    h = np.zeros((d, g.n), dtype=np.int64)
+    rc = lib.oracle_heuristic(g.n, g.n_arcs, g.D, _ptr(rp, ctypes.c_int64),
+                              _ptr(col, ctypes.c_int32), _ptr(cost, ctypes.c_int32), int(goal),
+                              int(d), _ptr(h, ctypes.c_int64))
+    if rc:
+        raise ValueError("bad heuristic input")
+    return h

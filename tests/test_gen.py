@@ -1,0 +1,52 @@
+"""Seeded generators: same bytes per seed, and the shapes the workloads specify."""
+import numpy as np
+
+import gen
+
+
+def test_config1_shape_and_determinism():
+    g, s, t = gen.config1(0)
+    assert (g.n, g.n_arcs, g.D, s, t) == (1024, 3968, 3, 0, 1023)
+    assert g.cost.min() >= 1 and g.cost.max() <= 10
+    assert np.diff(g.row_ptr).max() == 4
+    assert g.digest() == gen.config1(0)[0].digest()
+    assert g.digest() != gen.config1(1)[0].digest()
+    assert gen.overflow_bound_ok(g)
+
+
+def test_config2_shape():
+    g, s, t = gen.config2(0)
+    assert (g.n, g.n_arcs, g.D, s, t) == (65536, 521220, 3, 0, 65535)
+    assert g.cost.min() >= 100 and g.cost.max() <= 424
+    assert np.diff(g.row_ptr).max() == 8
+
+
+def test_symmetric_arcs_share_costs():
+    g, _, _ = gen.config1(3)
+    src = g.arc_sources()
+    fwd = {(int(a), int(b)): tuple(c) for a, b, c in zip(src, g.col, g.cost)}
+    for (a, b), c in fwd.items():
+        assert fwd[(b, a)] == c
+
+
+def test_config3_recipe_counts():
+    g, s, t = gen.config3(0)
+    assert g.n == 200_000 and g.n_arcs == 1_411_190 and g.D == 4
+    assert int(((g.cost == 0).all(1)).sum()) // 2 == 155
+    assert np.diff(g.row_ptr).max() == 14
+    assert np.linalg.norm(g.coords[s] - g.coords[t]) >= 0.7
+    assert gen.overflow_bound_ok(g)
+
+
+def test_config4_queries():
+    g, S, T = gen.config4(0, nq=64)
+    rr, cc = np.divmod(np.arange(g.n), 256)
+    D = np.abs(rr[S] - rr[T]) + np.abs(cc[S] - cc[T])
+    assert D.min() >= 10 and D.max() <= 400
+    S2, T2 = gen.config4(0, nq=64)[1:]
+    assert np.array_equal(S, S2) and np.array_equal(T, T2)
+
+
+def test_diamond_chain_structure():
+    g, s, t = gen.diamond_chain(4)
+    assert (s, t) == (0, 8) and g.n == 13 and g.n_arcs == 16

@@ -1,0 +1,258 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle itself.
+
+The oracle (sequential NAMOA*, paper Algorithm 1) is checked against:
+  * brute force: every simple start->goal path enumerated by DFS, then the
+    minimal distinct cost set (the definition of the problem, paper Section 3);
+  * d = 1: the single shortest-path distance (scipy's Dijkstra);
+  * the ideal point: per objective, the front's minimum equals the
+    single-objective shortest distance;
+  * lexicographic extreme points: for every objective order, the
+    lexicographically smallest front vector equals a lexicographic Dijkstra
+    written here with tuple keys;
+  * supported points: for positive weights w, min over the front of w.y equals
+    Dijkstra on the scalarised costs w.c;
+  * closed forms (diamond chains, identical objectives);
+  * metamorphic relations (zero heuristic, node relabelling, objective
+    permutation, reversal, scaling, a redundant objective) and the readings of
+    the paper's ambiguous points (strict vs weak P tests, eager vs lazy PruneOPEN).
+A mistake such as a dropped prune, a flipped comparison, a wrong heuristic
+direction or an off-by-one in cost accumulation breaks at least one of these.
+"""
+import heapq
+import itertools
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+from scipy.sparse.csgraph import dijkstra
+
+import gen
+import oracle
+from helpers import check_paths, is_antichain, sort_lex
+
+MODES = [0, oracle.WEAK_P, oracle.LAZY_PRUNEOPEN, oracle.WEAK_P | oracle.LAZY_PRUNEOPEN,
+         oracle.ZERO_H]
+
+
+# ------------------------------------------------------------ independent refs
+def brute_front(g, s, t, d):
+    """Minimal distinct costs over all simple s->t paths (DFS)."""
+    rp, col, cost = g.row_ptr, g.col, g.cost[:, :d].astype(np.int64)
+    costs = set()
+    if s == t:
+        return np.zeros((1, d), dtype=np.int64)
+    onpath = np.zeros(g.n, dtype=bool)
+
+    def dfs(u, acc):
+        if u == t:
+            costs.add(tuple(acc))
+            return
+        onpath[u] = True
+        for e in range(rp[u], rp[u + 1]):
+            v = int(col[e])
+            if not onpath[v]:
+                dfs(v, acc + cost[e])
+        onpath[u] = False
+
+    dfs(s, np.zeros(d, dtype=np.int64))
+    arr = np.array(sorted(costs), dtype=np.int64).reshape(-1, d)
+    keep = []
+    for i, y in enumerate(arr):
+        dom = np.all(arr <= y, axis=1) & np.any(arr < y, axis=1)
+        if not dom.any():
+            keep.append(y)
+    return sort_lex(np.array(keep, dtype=np.int64).reshape(-1, d))
+
+
+def scipy_dist(g, w, s):
+    """Dijkstra distances from s with arc weights w (float64; exact for small ints)."""
+    src = g.arc_sources()
+    # parallel arcs: keep the cheapest (csr_matrix would add duplicates)
+    order = np.lexsort((w, g.col, src))
+    src_o, dst_o, w_o = src[order], g.col[order], w[order]
+    first = np.ones(src_o.size, dtype=bool)
+    first[1:] = (src_o[1:] != src_o[:-1]) | (dst_o[1:] != dst_o[:-1])
+    # zero weights vanish in sparse matrices: shift by a tiny epsilon scaled out later
+    eps = 1e-9
+    m = sp.csr_matrix((w_o[first].astype(np.float64) + eps, (src_o[first], dst_o[first])),
+                      shape=(g.n, g.n))
+    dist = dijkstra(m, indices=s)
+    return dist
+
+
+def lex_dijkstra(g, s, t, perm):
+    """Lexicographically smallest s->t cost under objective order `perm` (tuple keys)."""
+    rp, col = g.row_ptr, g.col
+    cost = g.cost[:, list(perm)].astype(np.int64)
+    best = {s: tuple([0] * len(perm))}
+    pq = [(best[s], s)]
+    done = set()
+    while pq:
+        key, u = heapq.heappop(pq)
+        if u in done:
+            continue
+        done.add(u)
+        if u == t:
+            return key
+        for e in range(rp[u], rp[u + 1]):
+            v = int(col[e])
+            nk = tuple(a + int(b) for a, b in zip(key, cost[e]))
+            if v not in best or nk < best[v]:
+                best[v] = nk
+                heapq.heappush(pq, (nk, v))
+    return None
+
+
+# ------------------------------------------------------------------- tests
+@pytest.mark.parametrize("seed", range(16))
+def test_brute_force_random(seed):
+    d = 1 + seed % 4
+    g = gen.random_small(8, 20, d, seed=seed)
+    for s, t in [(0, 7), (2, 5), (4, 4), (6, 1)]:
+        ref = brute_front(g, s, t, d)
+        for mode in MODES:
+            r = oracle.solve(g, s, t, d, flags=mode)
+            assert r.status == "ok"
+            assert np.array_equal(r.costs, ref), (seed, s, t, mode)
+            check_paths(g, s, t, r.costs, r.paths, d)
+
+
+@pytest.mark.parametrize("rows,cols,d", [(2, 2, 2), (3, 3, 3), (3, 4, 2), (4, 4, 3), (4, 5, 2)])
+def test_brute_force_grids(rows, cols, d):
+    g = gen.grid_uniform(rows, cols, d, 0, 5, seed=rows * 10 + cols)
+    ref = brute_front(g, 0, g.n - 1, d)
+    for mode in MODES:
+        r = oracle.solve(g, 0, g.n - 1, d, flags=mode)
+        assert np.array_equal(r.costs, ref), mode
+
+
+def test_single_objective_is_dijkstra():
+    for seed in range(4):
+        g, s, t = gen.config1(seed)
+        g1 = gen.with_costs(g, g.cost[:, :1])
+        r = oracle.solve(g1, s, t, 1)
+        dist = scipy_dist(g1, g1.cost[:, 0].astype(np.int64), s)
+        assert r.costs.shape == (1, 1)
+        assert r.costs[0, 0] == int(round(dist[t]))
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_extreme_and_supported_points_config1(seed):
+    g, s, t = gen.config1(seed)
+    r = oracle.solve(g, s, t, flags=oracle.WEAK_P | oracle.LAZY_PRUNEOPEN)
+    f = r.costs
+    assert is_antichain(f)
+    assert np.array_equal(f, sort_lex(f))
+    # ideal point
+    for k in range(3):
+        dist = scipy_dist(g, g.cost[:, k].astype(np.int64), s)
+        assert f[:, k].min() == int(round(dist[t]))
+    # lexicographic extreme for every objective order
+    for perm in itertools.permutations(range(3)):
+        key = lex_dijkstra(g, s, t, perm)
+        fp = f[:, list(perm)]
+        assert tuple(int(x) for x in sort_lex(fp)[0]) == key, perm
+    # supported points
+    rng = np.random.default_rng(seed)
+    for _ in range(5):
+        w = rng.integers(1, 20, 3)
+        dist = scipy_dist(g, (g.cost.astype(np.int64) * w).sum(1), s)
+        assert (f * w).sum(1).min() == int(round(dist[t]))
+    check_paths(g, s, t, f, r.paths, 3)
+
+
+def test_extreme_points_ship_grid():
+    g, s, t = gen.config2(0, size=64)
+    r = oracle.solve(g, s, t)
+    f = r.costs
+    for perm in itertools.permutations(range(3)):
+        key = lex_dijkstra(g, s, t, perm)
+        assert tuple(int(x) for x in sort_lex(f[:, list(perm)])[0]) == key
+    check_paths(g, s, t, f, r.paths, 3)
+
+
+@pytest.mark.parametrize("k", [1, 3, 6, 9])
+def test_diamond_chain_closed_form(k):
+    g, s, t = gen.diamond_chain(k)
+    W = 2 ** k - 1
+    r = oracle.solve(g, s, t)
+    expect = np.array([[x, W - x] for x in range(2 ** k)], dtype=np.int64)
+    assert np.array_equal(r.costs, expect)
+    check_paths(g, s, t, r.costs, r.paths, 2)
+
+
+def test_diamond_chain_unit_weights():
+    g, s, t = gen.diamond_chain(7, weights=[1] * 7)
+    r = oracle.solve(g, s, t)
+    expect = np.array([[x, 7 - x] for x in range(8)], dtype=np.int64)
+    assert np.array_equal(r.costs, expect)
+
+
+def test_identical_objectives_singleton():
+    g, s, t = gen.config1(2)
+    g3 = gen.with_costs(g, np.repeat(g.cost[:, :1], 3, axis=1))
+    r = oracle.solve(g3, s, t)
+    dist = scipy_dist(g, g.cost[:, 0].astype(np.int64), s)
+    assert r.costs.shape == (1, 3) and np.all(r.costs == int(round(dist[t])))
+
+
+def test_metamorphic_relations():
+    g = gen.grid_uniform(9, 9, 3, 1, 10, seed=11)
+    s, t = 0, g.n - 1
+    base = oracle.solve(g, s, t).costs
+    # every reading/mode gives the same cost set
+    for mode in MODES:
+        assert np.array_equal(oracle.solve(g, s, t, flags=mode).costs, base)
+    # node relabelling
+    perm = np.random.default_rng(0).permutation(g.n)
+    gp = gen.permute_nodes(g, perm)
+    assert np.array_equal(oracle.solve(gp, perm[s], perm[t]).costs, base)
+    # objective permutation permutes columns
+    for p in itertools.permutations(range(3)):
+        r = oracle.solve(gen.with_costs(g, g.cost[:, list(p)]), s, t).costs
+        assert np.array_equal(r, sort_lex(base[:, list(p)]))
+    # reversal on a symmetric graph with swapped endpoints
+    assert np.array_equal(oracle.solve(g.reversed(), t, s).costs, base)
+    assert np.array_equal(oracle.solve(g, t, s).costs, base)
+    # scaling by an integer
+    assert np.array_equal(oracle.solve(gen.with_costs(g, g.cost * 3), s, t).costs, base * 3)
+    # redundant objective c1 + c2 appended
+    c4 = np.concatenate([g.cost, (g.cost[:, 0] + g.cost[:, 1])[:, None]], axis=1)
+    r4 = oracle.solve(gen.with_costs(g, c4), s, t).costs
+    assert np.array_equal(r4, np.concatenate([base, (base[:, 0] + base[:, 1])[:, None]], 1))
+    # the first-n objectives rule: d=2 solves the graph restricted to columns 0, 1
+    r2 = oracle.solve(g, s, t, 2).costs
+    assert np.array_equal(r2, oracle.solve(gen.with_costs(g, g.cost[:, :2]), s, t).costs)
+    assert is_antichain(r2)
+
+
+def test_edge_cases():
+    g = gen.random_small(6, 10, 2, seed=3)
+    # start == goal: the single zero vector, empty path
+    r = oracle.solve(g, 2, 2)
+    assert r.costs.tolist() == [[0, 0]] and len(r.paths[0]) == 0
+    # unreachable goal: empty front
+    g2 = gen.from_arcs(4, [0, 1], [1, 0], np.ones((2, 2), dtype=np.int64))
+    assert oracle.solve(g2, 0, 3).costs.shape == (0, 2)
+    # zero-cost cycle and self-loops do not loop forever, parallel arcs pick the best
+    g3 = gen.from_arcs(3, [0, 1, 1, 0, 1, 1], [1, 0, 1, 1, 2, 2],
+                       np.array([[0, 0], [0, 0], [0, 0], [2, 1], [1, 3], [3, 1]]))
+    r3 = oracle.solve(g3, 0, 2)
+    assert r3.costs.tolist() == [[1, 3], [3, 1]]
+    check_paths(g3, 0, 2, r3.costs, r3.paths, 2)
+    # negative costs are rejected
+    g4 = gen.from_arcs(2, [0], [1], np.array([[1, 1]]))
+    g4.cost[0, 0] = -1
+    assert oracle.solve(g4, 0, 1).status == "bad input"
+
+
+def test_heuristic_is_reverse_dijkstra():
+    g, s, t = gen.config1(0)
+    h = oracle.heuristic(g, t)
+    for k in range(3):
+        dist = scipy_dist(g.reversed(), g.reversed().cost[:, k].astype(np.int64), t)
+        assert np.array_equal(h[k], np.rint(dist).astype(np.int64))
+    # directed: unreachable nodes get the INT64 max marker
+    g2 = gen.from_arcs(3, [0, 1], [1, 2], np.ones((2, 1), dtype=np.int64))
+    h2 = oracle.heuristic(g2, 0)
+    assert h2[0, 0] == 0 and h2[0, 1] == oracle.INF and h2[0, 2] == oracle.INF
