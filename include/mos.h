@@ -1,0 +1,178 @@
+/* mos.h -- exact multi-objective shortest paths on one AMD Instinct MI355X (gfx950).
+ *
+ * ABI version 1.  C interface; every id is 0-based; objectives are int32 and
+ * non-negative.
+ *
+ * The problem (paper, Section 3): a directed graph G = (V, E, c) whose arcs
+ * carry non-negative cost vectors c(e) of length D; given a start node v_s and
+ * a goal node v_g, find the cost-unique set of Pareto-optimal v_s -> v_g path
+ * costs (no returned vector is dominated by, or equal to, the cost of another
+ * v_s -> v_g path) and one witness path per cost.  a dominates b when
+ * a[k] <= b[k] for every k and a[k] < b[k] for some k.
+ *
+ * The search is the paper's ordered label-setting method (Algorithm 1,
+ * NAMOA*, run in batches as in Algorithm 2, OPMOS): each step pops the B
+ * lexicographically smallest open labels (ordered by F = g + h), expands their
+ * out-arcs, filters the candidates against the goal front and against each
+ * target node's frontier, prunes the frontier labels they dominate, resolves
+ * dominance among candidates of the same step, and inserts the survivors.  The
+ * heuristic h_k(v) is the exact shortest v -> v_g distance under objective k
+ * (Section 4), computed on the GPU.  Only the expansion order depends on B;
+ * the returned cost set does not.
+ *
+ * Memory: every array argument is HOST memory.  mos_graph_create copies the
+ * graph to device memory; results are copied back to host memory and owned by
+ * the mos_result handle.  Every destroy function accepts NULL.
+ *
+ * Errors: no call aborts.  Every call that can fail returns a mos_status;
+ * out-parameters are written only on MOS_OK.  Argument validation happens
+ * before any device call.  mos_last_error() gives a thread-local message for
+ * the last failing call on the calling thread.
+ */
+#ifndef MOS_H_
+#define MOS_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MOS_ABI_VERSION 1
+#define MOS_MAX_OBJECTIVES 8 /* largest D accepted by mos_graph_create */
+
+typedef struct mos_graph mos_graph;
+typedef struct mos_result mos_result;
+typedef struct mos_server mos_server;
+
+typedef enum {
+  MOS_OK = 0,
+  MOS_E_INVALID_ARG = 1,   /* bad id, size, pointer or option */
+  MOS_E_NEGATIVE_COST = 2, /* an arc cost is < 0 */
+  MOS_E_OVERFLOW_RISK = 3, /* 2*sum_e c_k(e) + max_e c_k(e) > INT32_MAX for some k */
+  MOS_E_NO_DEVICE = 4,     /* no visible HIP device */
+  MOS_E_DEVICE = 5,        /* a HIP runtime call failed */
+  MOS_E_OUT_OF_MEMORY = 6, /* device or host allocation failed */
+  MOS_E_LABEL_LIMIT = 7,   /* the search outgrew label_limit / the memory budget;
+                              no partial front is ever reported as complete */
+  MOS_E_CANCELLED = 8,     /* a served query was cancelled */
+  MOS_E_NOT_READY = 9      /* a served query has not finished yet */
+} mos_status;
+
+/* Options for one solve.  Zero-initialise, set struct_size = sizeof(mos_options),
+ * then override fields.  NULL options means all defaults. */
+typedef struct {
+  uint32_t struct_size;
+  int32_t n_objectives; /* 0 = all D; else use the first n objectives (the
+                           paper's Table 1 rule: "the first n are used") */
+  int32_t batch_width;  /* B, labels popped per step (paper: NUM_POP); 0 = default */
+  int32_t max_slots;    /* mos_solve_batch: queries resident at once; 0 = auto */
+  int64_t label_limit;  /* per query; 0 = bounded only by mem_budget */
+  int64_t mem_budget;   /* bytes of device memory for search state; 0 = auto */
+  void* stream;         /* hipStream_t to run on, or NULL for the library's own */
+  int32_t costs_only;   /* 0 (default) = also reconstruct witness paths; 1 = costs only */
+  int32_t steps_per_poll; /* device steps between host status polls; 0 = default */
+} mos_options;
+
+/* Counters of one query (paper, Section 6: label extractions, candidate
+ * labels explored, solutions found; plus the dominance-check work).  A
+ * "pair" is one (candidate vector, stored vector) comparison the method has to
+ * make: against the goal front P, against another candidate of the same step
+ * and target node, or against a live label of the target node's frontier. */
+typedef struct {
+  int64_t pops;            /* labels taken from OPEN and processed */
+  int64_t goal_pops;       /* of which at the goal */
+  int64_t candidates;      /* arcs expanded (candidate labels generated) */
+  int64_t p_pairs;         /* candidate x goal-front pairs */
+  int64_t group_pairs;     /* candidate x same-group candidate pairs */
+  int64_t frontier_pairs;  /* candidate x frontier-label pairs */
+  int64_t inserted;        /* labels inserted (incl. the start label) */
+  int64_t pruned;          /* frontier labels removed by a dominating candidate */
+  int64_t steps;           /* batched label steps run */
+  int64_t front;           /* size of the returned front */
+  int64_t frontier_bytes;  /* algorithmic bytes of frontier reads: 4*d per frontier pair-row */
+  double search_ms;        /* device time of the label steps */
+  double heuristic_ms;     /* device time of the heuristic (reverse SSSP) */
+} mos_stats;
+
+/* Graph: n_nodes nodes, n_arcs arcs in CSR form.  row_ptr[n_nodes+1] (int64,
+ * non-decreasing, row_ptr[0] = 0, row_ptr[n] = n_arcs), col[n_arcs] (arc
+ * targets), cost[n_arcs * D] arc-major (cost[e*D + k] = objective k of arc e),
+ * 1 <= D <= MOS_MAX_OBJECTIVES.  Parallel arcs, self-loops and zero costs are
+ * allowed.  Fails with MOS_E_NEGATIVE_COST for a negative cost and with
+ * MOS_E_OVERFLOW_RISK when int32 sums could overflow (every accepted label is
+ * a simple path, so g_k <= sum of c_k and F_k <= 2*sum + max).  The arrays are
+ * copied; the caller keeps ownership.  The graph is immutable afterwards and
+ * may be shared by several threads and streams. */
+mos_status mos_graph_create(int32_t n_nodes, int64_t n_arcs, int32_t D, const int64_t* row_ptr,
+                            const int32_t* col, const int32_t* cost, mos_graph** out);
+void mos_graph_destroy(mos_graph* g);
+
+/* Exact front for one start/goal pair.  An unreachable goal gives MOS_OK with
+ * an empty front; start == goal gives the single all-zero vector and an empty
+ * path.  On success *out owns the result. */
+mos_status mos_solve(const mos_graph* g, int32_t start, int32_t goal, const mos_options* opt,
+                     mos_result** out);
+
+/* nq queries solved together: queries are admitted into device-resident slots
+ * as memory allows and all resident queries advance in the same fused step
+ * launches.  n_objectives may be NULL (then opt->n_objectives applies to all).
+ * out[i] and st[i] receive each query's result and status; a query's result
+ * (paths included) does not depend on the other queries.  Returns MOS_OK if
+ * every query succeeded, else the first failing status. */
+mos_status mos_solve_batch(const mos_graph* g, int32_t nq, const int32_t* starts,
+                           const int32_t* goals, const int32_t* n_objectives,
+                           const mos_options* opt, mos_result** out, mos_status* st);
+
+int64_t mos_result_size(const mos_result* r); /* number of front entries (0 for NULL) */
+int32_t mos_result_dim(const mos_result* r);  /* d (0 for NULL) */
+/* out[size*d]: the front, lexicographically ascending. */
+mos_status mos_result_costs(const mos_result* r, int32_t* out);
+/* Arc ids of the witness path of entry i.  *len receives the length; at most
+ * cap ids are written to arcs (arcs may be NULL when cap == 0). */
+mos_status mos_result_path(const mos_result* r, int64_t i, int32_t* arcs, int64_t cap,
+                           int64_t* len);
+mos_status mos_result_stats(const mos_result* r, mos_stats* out);
+void mos_result_destroy(mos_result* r);
+
+/* Device memory hooks (e.g. a framework's caching allocator).  alloc returns
+ * device memory of at least the given size or NULL; release frees it.  Pass
+ * NULL functions to restore hipMalloc/hipFree.  Affects later allocations. */
+mos_status mos_set_allocator(void* (*alloc)(size_t bytes, void* stream, void* ctx),
+                             void (*release)(void* ptr, void* ctx), void* ctx);
+
+/* Continuous-batching server over one graph.  Requests are queued by
+ * mos_server_submit and admitted into free slots when their search-state
+ * reservation fits into mem_budget_bytes; admitted queries share every step
+ * launch with the queries already on the device, and finished ones leave at
+ * once.  A query that outgrows its reservation is re-admitted alone with a
+ * larger one (or fails with MOS_E_LABEL_LIMIT); other queries are unaffected. */
+mos_status mos_server_create(const mos_graph* g, int64_t mem_budget_bytes, int32_t max_slots,
+                             mos_server** out);
+mos_status mos_server_submit(mos_server* s, int32_t start, int32_t goal, int32_t n_objectives,
+                             uint64_t* ticket);
+/* MOS_E_NOT_READY until the query is done; then MOS_OK and *out (owned by the
+ * caller), or the query's error.  A ticket can be collected once. */
+mos_status mos_server_poll(mos_server* s, uint64_t ticket, mos_result** out);
+/* Blocks until the ticket is done (or timeout_ms elapses: MOS_E_NOT_READY). */
+mos_status mos_server_wait(mos_server* s, uint64_t ticket, int64_t timeout_ms, mos_result** out);
+mos_status mos_server_cancel(mos_server* s, uint64_t ticket);
+/* Server counters: [0] submitted, [1] finished, [2] resident now, [3] queued now,
+ * [4] ticks run, [5] re-admissions after overflow. */
+mos_status mos_server_counters(mos_server* s, int64_t* out6);
+void mos_server_destroy(mos_server* s);
+
+const char* mos_status_string(mos_status s);
+const char* mos_last_error(void);
+
+/* Heuristic only (the search's prerequisite step): h[k*n + v] = shortest
+ * v -> goal distance under objective k for k < n_objectives (0 = D), or
+ * INT32_MAX when the goal cannot be reached from v.  h is host memory of
+ * n_objectives * n_nodes int32. */
+mos_status mos_heuristic(const mos_graph* g, int32_t goal, int32_t n_objectives, int32_t* h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MOS_H_ */

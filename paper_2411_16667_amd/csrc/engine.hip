@@ -1,0 +1,1159 @@
+// Host runtime of the library: C ABI, graph upload, device-resident query
+// slots, admission by memory reservation, the step loop, batch and server.
+//
+// One Engine owns a device arena and a table of slots.  Every tick it
+//   1. admits queued queries into free slots whose reservation fits the arena
+//      (first fit), computes their heuristics and seeds their start labels,
+//   2. replays a captured hipGraph of K batched label steps over all slots,
+//   3. reads the slot table back and harvests finished queries (results and
+//      witness paths are copied to host memory; the reservation is released).
+// mos_solve is a one-query batch; mos_solve_batch feeds a queue of queries
+// through the same engine (continuous batching); the server runs the same
+// ticks on a thread fed by a request queue.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <stdexcept>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "kernels.h"
+#include "mos.h"
+
+using namespace mos;
+
+// ------------------------------------------------------------------ errors
+static thread_local std::string g_last_error;
+
+struct MosError : std::runtime_error {
+  mos_status st;
+  MosError(mos_status s, const std::string& m) : std::runtime_error(m), st(s) {}
+};
+
+static void hip_check(hipError_t e, const char* what, int line) {
+  if (e != hipSuccess) {
+    hipGetLastError();
+    throw MosError(e == hipErrorOutOfMemory ? MOS_E_OUT_OF_MEMORY : MOS_E_DEVICE,
+                   std::string(what) + " failed at engine line " + std::to_string(line) + ": " +
+                       hipGetErrorString(e));
+  }
+}
+#define HIPCHK(x) hip_check((x), #x, __LINE__)
+
+static mos_status set_err(mos_status s, const std::string& m) {
+  g_last_error = m;
+  return s;
+}
+
+template <class F>
+static mos_status guarded(F&& f) {
+  try {
+    return f();
+  } catch (const MosError& e) {
+    return set_err(e.st, e.what());
+  } catch (const std::bad_alloc&) {
+    return set_err(MOS_E_OUT_OF_MEMORY, "host allocation failed");
+  } catch (const std::exception& e) {
+    return set_err(MOS_E_DEVICE, e.what());
+  }
+}
+
+// ------------------------------------------------------------- allocation
+struct AllocHooks {
+  void* (*alloc)(size_t, void*, void*) = nullptr;
+  void (*release)(void*, void*) = nullptr;
+  void* ctx = nullptr;
+};
+static std::mutex g_hooks_mu;
+static AllocHooks g_hooks;
+
+// Device buffer that remembers which allocator made it.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  AllocHooks h;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  void alloc(size_t n, hipStream_t st) {
+    reset();
+    if (n == 0) n = 256;
+    {
+      std::lock_guard<std::mutex> lk(g_hooks_mu);
+      h = g_hooks;
+    }
+    if (h.alloc) {
+      p = h.alloc(n, (void*)st, h.ctx);
+      if (!p) throw MosError(MOS_E_OUT_OF_MEMORY, "allocator hook returned NULL");
+    } else {
+      hipError_t e = hipMalloc(&p, n);
+      if (e != hipSuccess) {
+        hipGetLastError();
+        p = nullptr;
+        throw MosError(MOS_E_OUT_OF_MEMORY,
+                       "hipMalloc of " + std::to_string(n) + " bytes failed");
+      }
+    }
+    bytes = n;
+  }
+  void reset() {
+    if (p) {
+      if (h.release) h.release(p, h.ctx);
+      else hipFree(p);
+    }
+    p = nullptr;
+    bytes = 0;
+  }
+  ~DevBuf() { reset(); }
+  template <class T>
+  T* as() const { return (T*)p; }
+};
+
+static int ensure_device() {
+  int n = 0;
+  hipError_t e = hipGetDeviceCount(&n);
+  if (e != hipSuccess || n <= 0) {
+    hipGetLastError();
+    throw MosError(MOS_E_NO_DEVICE, "no HIP device is visible");
+  }
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  return dev;
+}
+
+// ------------------------------------------------------------------ graph
+struct mos_graph {
+  int32_t n = 0, D = 0, maxdeg = 0, device = 0;
+  int64_t m = 0;
+  DevBuf row_ptr, col, cost, rrow, rsrc, rarc;
+  GraphDev view() const {
+    GraphDev g;
+    g.n = n;
+    g.m = (int32_t)m;
+    g.D = D;
+    g.maxdeg = maxdeg;
+    g.row_ptr = row_ptr.as<int32_t>();
+    g.col = col.as<int32_t>();
+    g.cost = cost.as<int32_t>();
+    g.rrow = rrow.as<int32_t>();
+    g.rsrc = rsrc.as<int32_t>();
+    g.rarc = rarc.as<int32_t>();
+    return g;
+  }
+};
+
+// ----------------------------------------------------------------- result
+struct mos_result {
+  int32_t d = 0;
+  int64_t size = 0;
+  std::vector<int32_t> costs;     // size*d, lexicographically ascending
+  std::vector<int64_t> path_off;  // size+1 (empty when paths were not requested)
+  std::vector<int32_t> arcs;
+  mos_stats stats{};
+};
+
+// --------------------------------------------------------- range allocator
+// First-fit allocator over [0, total) of the arena (256-byte units).
+struct RangeAlloc {
+  std::map<int64_t, int64_t> free_;  // offset -> length
+  int64_t total = 0;
+  void init(int64_t t) {
+    total = t;
+    free_.clear();
+    free_[0] = t;
+  }
+  bool take(int64_t len, int64_t* off) {
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= len) {
+        *off = it->first;
+        int64_t rest = it->second - len;
+        int64_t noff = it->first + len;
+        free_.erase(it);
+        if (rest > 0) free_[noff] = rest;
+        return true;
+      }
+    }
+    return false;
+  }
+  void give(int64_t off, int64_t len) {
+    auto it = free_.emplace(off, len).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+  int64_t largest() const {
+    int64_t b = 0;
+    for (auto& kv : free_) b = std::max(b, kv.second);
+    return b;
+  }
+};
+
+// ----------------------------------------------------------- slot layout
+struct Layout {
+  int32_t B, batch_cap, cand_cap, tie_cap, pool_cap, open_cap, P_cap;
+  int64_t fw_cap;
+  int64_t bytes;
+};
+
+static inline int64_t al(int64_t x) { return (x + 255) & ~int64_t(255); }
+
+static int64_t fixed_bytes(int64_t n, int d, int batch_cap, int cand_cap, int tie_cap) {
+  int64_t b = 0;
+  b += al(4 * d * n) + al(16 * n) + 2 * al(4 * n);                   // h, node, grp
+  b += 3 * al(4 * (int64_t)batch_cap) + al(4 * ((int64_t)batch_cap + 1));  // batch, reg, goal, reg_off
+  b += 2 * al(4 * (int64_t)tie_cap);                                 // tie
+  b += 10 * al(4 * (int64_t)cand_cap) + al(4 * (int64_t)d * cand_cap) + al(8 * (int64_t)cand_cap);
+  return b + 64 * 256;
+}
+
+// Split a reservation of `budget` bytes: fixed per-query regions, then label
+// pool, OPEN (double buffered), goal front (double buffered) and frontier
+// words in proportion to the pool size.
+static bool plan_layout(const mos_graph* g, int d, int B, int64_t budget, int64_t label_limit,
+                        Layout* L) {
+  L->B = B;
+  L->batch_cap = std::min(2 * B, BATCH_SORT);
+  L->cand_cap = L->batch_cap * std::max(1, g->maxdeg);
+  L->tie_cap = TIECAP;
+  const int64_t fixed = fixed_bytes(g->n, d, L->batch_cap, L->cand_cap, L->tie_cap);
+  if (budget <= fixed) return false;
+  // bytes per pooled label: pool (node, parent, arc, g, state) + OPEN 2x(F1,
+  // lab) + frontier 3*(d+1) words + goal front share 2*(d+1) words / 8 + scratch
+  const double per = (12.0 + 4.0 * d + 1.0) + 16.0 + 12.0 * (d + 1) + (8.0 * (d + 1) + 8.0) / 8.0;
+  int64_t pool = (int64_t)((double)(budget - fixed - 32 * 256) / per);
+  pool = std::min<int64_t>(pool, (int64_t)1 << 30);
+  if (label_limit > 0) pool = std::min<int64_t>(pool, label_limit);
+  if (pool < 16) return false;
+  L->pool_cap = (int32_t)pool;
+  L->open_cap = (int32_t)pool;
+  L->P_cap = (int32_t)std::max<int64_t>(std::min<int64_t>(pool, 1024), pool / 8);
+  L->fw_cap = 3 * (int64_t)(d + 1) * pool + (int64_t)MINCAP * (d + 1);
+  int64_t b = fixed;
+  b += 3 * al(4 * pool) + al(4 * (int64_t)d * pool) + al(pool);  // pool
+  b += 4 * al(4 * pool);                                          // OPEN
+  b += 2 * (al(4 * (int64_t)d * L->P_cap) + al(4 * (int64_t)L->P_cap)) + al(8 * ((int64_t)L->P_cap + 1));
+  b += al(4 * L->fw_cap);
+  L->bytes = al(b);
+  return L->bytes <= budget;
+}
+
+// Carve the reservation at `base` into the regions of a Slot.
+static void carve(Slot& s, char* base, const Layout& L, int64_t n, int d) {
+  char* p = base;
+  auto take = [&](int64_t bytes) {
+    char* r = p;
+    p += al(bytes);
+    return r;
+  };
+  s.h = (int32_t*)take(4 * d * n);
+  s.node = (NodeRec*)take(16 * n);
+  s.grp_cnt = (int32_t*)take(4 * n);
+  s.grp_id = (int32_t*)take(4 * n);
+  s.batch = (int32_t*)take(4 * (int64_t)L.batch_cap);
+  s.reg = (int32_t*)take(4 * (int64_t)L.batch_cap);
+  s.goal_lab = (int32_t*)take(4 * (int64_t)L.batch_cap);
+  s.reg_off = (int32_t*)take(4 * ((int64_t)L.batch_cap + 1));
+  s.tie_f1 = (int32_t*)take(4 * (int64_t)L.tie_cap);
+  s.tie_lab = (int32_t*)take(4 * (int64_t)L.tie_cap);
+  const int64_t cc = L.cand_cap;
+  s.c_node = (int32_t*)take(4 * cc);
+  s.c_par = (int32_t*)take(4 * cc);
+  s.c_arc = (int32_t*)take(4 * cc);
+  s.c_keep = (int32_t*)take(4 * cc);
+  s.c_rank = (int32_t*)take(4 * cc);
+  s.c_rej = (int32_t*)take(4 * cc);
+  s.c_acc = (int32_t*)take(4 * cc);
+  s.order = (int32_t*)take(4 * cc);
+  s.grp_node = (int32_t*)take(4 * cc);
+  s.grp_off = (int32_t*)take(4 * cc);
+  s.c_g = (int32_t*)take(4 * (int64_t)d * cc);
+  s.c_fslot = (int64_t*)take(8 * cc);
+  const int64_t pc = L.pool_cap;
+  s.Lnode = (int32_t*)take(4 * pc);
+  s.Lpar = (int32_t*)take(4 * pc);
+  s.Larc = (int32_t*)take(4 * pc);
+  s.Lg = (int32_t*)take(4 * (int64_t)d * pc);
+  s.Lstate = (uint8_t*)take(pc);
+  for (int b = 0; b < 2; ++b) {
+    s.open_f1[b] = (int32_t*)take(4 * (int64_t)L.open_cap);
+    s.open_lab[b] = (int32_t*)take(4 * (int64_t)L.open_cap);
+  }
+  for (int b = 0; b < 2; ++b) {
+    s.Pg[b] = (int32_t*)take(4 * (int64_t)d * L.P_cap);
+    s.Plab[b] = (int32_t*)take(4 * (int64_t)L.P_cap);
+  }
+  s.pscr = (int32_t*)take(8 * ((int64_t)L.P_cap + 1));
+  s.fw = (int32_t*)take(4 * L.fw_cap);
+  if (p - base > L.bytes) throw MosError(MOS_E_DEVICE, "slot layout overrun");
+}
+
+// ------------------------------------------------------------------ engine
+struct QueryReq {
+  int64_t id = 0;
+  int32_t start = 0, goal = 0, d = 0;
+  int64_t reserve = 0;  // bytes of the next admission attempt
+  int attempts = 0;
+};
+
+struct Finished {
+  int64_t id;
+  mos_status st;
+  mos_result* res;
+  std::string msg;
+};
+
+struct SlotHost {
+  bool busy = false;
+  QueryReq q;
+  int64_t off = 0, len = 0;
+  Layout L{};
+  double search_ms = 0, heur_ms = 0;
+  bool cancel = false;
+};
+
+class Engine {
+ public:
+  Engine(const mos_graph* g, int nslots, int64_t budget, hipStream_t user_stream, int B,
+         int64_t label_limit, bool want_paths, int steps_per_poll)
+      : g_(g), S_(nslots), B_(B), label_limit_(label_limit), want_paths_(want_paths),
+        K_(steps_per_poll) {
+    HIPCHK(hipSetDevice(g->device));
+    if (user_stream) {
+      st_ = user_stream;
+    } else {
+      HIPCHK(hipStreamCreateWithFlags(&st_, hipStreamNonBlocking));
+      own_stream_ = true;
+    }
+    budget = std::max<int64_t>(budget, 1 << 20);
+    arena_.alloc((size_t)budget, st_);
+    ra_.init(budget / 256);
+    slots_.alloc(sizeof(Slot) * S_, st_);
+    HIPCHK(hipHostMalloc((void**)&hslots_, sizeof(Slot) * S_, hipHostMallocDefault));
+    std::memset(hslots_, 0, sizeof(Slot) * S_);
+    HIPCHK(hipMemcpyAsync(slots_.p, hslots_, sizeof(Slot) * S_, hipMemcpyHostToDevice, st_));
+    hist_.alloc((size_t)S_ * NB * 4, st_);
+    HIPCHK(hipMemsetAsync(hist_.p, 0, (size_t)S_ * NB * 4, st_));
+    sh_.resize(S_);
+    gx_ = std::max(1, 2048 / S_);
+    HIPCHK(hipEventCreate(&ev0_));
+    HIPCHK(hipEventCreate(&ev1_));
+    HIPCHK(hipStreamSynchronize(st_));
+  }
+
+  ~Engine() {
+    if (graph_exec_) hipGraphExecDestroy(graph_exec_);
+    if (hslots_) hipHostFree(hslots_);
+    hipEventDestroy(ev0_);
+    hipEventDestroy(ev1_);
+    hipStreamSynchronize(st_);
+    arena_.reset();
+    slots_.reset();
+    hist_.reset();
+    hscr_.reset();
+    hcnt_.reset();
+    hjob_.reset();
+    if (own_stream_) hipStreamDestroy(st_);
+  }
+
+  int64_t arena_bytes() const { return ra_.total * 256; }
+  int busy_count() const {
+    int c = 0;
+    for (auto& s : sh_) c += s.busy;
+    return c;
+  }
+  int slots() const { return S_; }
+
+  // Default reservation for a query: an equal share of the arena.
+  int64_t default_reserve() const { return std::max<int64_t>(arena_bytes() / S_, 1 << 20); }
+
+  void cancel_query(int64_t id) {
+    for (int s = 0; s < S_; ++s)
+      if (sh_[s].busy && sh_[s].q.id == id) sh_[s].cancel = true;
+  }
+
+  // Admit, step, harvest.  Returns finished queries through `done`.
+  void tick(std::deque<QueryReq>& pending, std::vector<Finished>& done) {
+    // ---- cancellations of resident queries
+    for (int s = 0; s < S_; ++s) {
+      if (sh_[s].busy && sh_[s].cancel) {
+        int32_t idle = S_IDLE;
+        HIPCHK(hipMemcpyAsync((char*)slots_.p + (size_t)s * sizeof(Slot) + offsetof(Slot, status),
+                              &idle, sizeof(idle), hipMemcpyHostToDevice, st_));
+        HIPCHK(hipStreamSynchronize(st_));
+        release(s);
+        done.push_back({sh_[s].q.id, MOS_E_CANCELLED, nullptr, "cancelled"});
+      }
+    }
+    // ---- admission (first fit, in queue order)
+    std::vector<int> fresh;
+    while (!pending.empty()) {
+      int free_slot = -1;
+      for (int s = 0; s < S_; ++s)
+        if (!sh_[s].busy) {
+          free_slot = s;
+          break;
+        }
+      if (free_slot < 0) break;
+      QueryReq q = pending.front();
+      q.reserve = std::min<int64_t>(q.reserve, arena_bytes());
+      Layout L;
+      if (!plan_layout(g_, q.d, B_, q.reserve, label_limit_, &L)) {
+        pending.pop_front();
+        done.push_back({q.id, MOS_E_LABEL_LIMIT, nullptr,
+                        "memory budget too small for one query of this graph"});
+        continue;
+      }
+      int64_t off;
+      if (!ra_.take((L.bytes + 255) / 256, &off)) {
+        if (busy_count() == 0 && ra_.largest() * 256 < L.bytes) {
+          pending.pop_front();
+          done.push_back({q.id, MOS_E_LABEL_LIMIT, nullptr, "reservation exceeds the arena"});
+          continue;
+        }
+        break;  // wait for resident queries to leave
+      }
+      pending.pop_front();
+      SlotHost& h = sh_[free_slot];
+      h.busy = true;
+      h.cancel = false;
+      h.q = q;
+      h.off = off;
+      h.len = (L.bytes + 255) / 256;
+      h.L = L;
+      h.search_ms = h.heur_ms = 0;
+      Slot& s = hslots_[free_slot];
+      std::memset(&s, 0, sizeof(Slot));
+      s.status = S_IDLE;
+      s.start = q.start;
+      s.goal = q.goal;
+      s.d = q.d;
+      s.B = L.B;
+      s.batch_cap = L.batch_cap;
+      s.cand_cap = L.cand_cap;
+      s.tie_cap = L.tie_cap;
+      s.pool_cap = L.pool_cap;
+      s.open_cap = L.open_cap;
+      s.P_cap = L.P_cap;
+      s.fw_cap = L.fw_cap;
+      s.query_id = (int32_t)q.id;
+      carve(s, arena_.as<char>() + off * 256, L, g_->n, q.d);
+      HIPCHK(hipMemcpyAsync((char*)slots_.p + (size_t)free_slot * sizeof(Slot), &s, sizeof(Slot),
+                            hipMemcpyHostToDevice, st_));
+      fresh.push_back(free_slot);
+    }
+    if (!fresh.empty()) run_heuristics(fresh);
+    // ---- steps
+    if (busy_count() > 0) {
+      HIPCHK(hipEventRecord(ev0_, st_));
+      run_steps();
+      HIPCHK(hipEventRecord(ev1_, st_));
+      HIPCHK(hipMemcpyAsync(hslots_, slots_.p, sizeof(Slot) * S_, hipMemcpyDeviceToHost, st_));
+      HIPCHK(hipStreamSynchronize(st_));
+      float ms = 0;
+      HIPCHK(hipEventElapsedTime(&ms, ev0_, ev1_));
+      for (int s = 0; s < S_; ++s)
+        if (sh_[s].busy) sh_[s].search_ms += ms;
+      for (int s = 0; s < S_; ++s) {
+        if (!sh_[s].busy) continue;
+        const Slot& d = hslots_[s];
+        if (d.status == S_RUN) continue;
+        if (d.status == S_DONE) {
+          Finished f{sh_[s].q.id, MOS_OK, nullptr, ""};
+          f.res = harvest(s);
+          release(s);
+          done.push_back(f);
+        } else {
+          QueryReq q = sh_[s].q;
+          const Layout L = sh_[s].L;
+          release(s);
+          if (d.status == S_TIE) {
+            done.push_back({q.id, MOS_E_DEVICE, nullptr,
+                            "a tie set exceeded the exact-selection capacity"});
+          } else if ((label_limit_ > 0 && L.pool_cap >= label_limit_) ||
+                     q.reserve >= arena_bytes()) {
+            done.push_back({q.id, MOS_E_LABEL_LIMIT, nullptr,
+                            "search state outgrew the label limit or memory budget"});
+          } else {
+            q.reserve = std::min<int64_t>(arena_bytes(), q.reserve * 4);
+            q.attempts++;
+            readmissions_++;
+            pending.push_front(q);
+          }
+        }
+      }
+    }
+  }
+
+  int64_t readmissions() const { return readmissions_; }
+
+  // Heuristic only: h planes of one goal (used by mos_heuristic).
+  void heuristic_only(int32_t goal, int d, int32_t* out) {
+    Layout L;
+    if (!plan_layout(g_, d, B_, arena_bytes(), 16, &L))
+      throw MosError(MOS_E_OUT_OF_MEMORY, "arena too small");
+    int64_t off;
+    if (!ra_.take((L.bytes + 255) / 256, &off)) throw MosError(MOS_E_OUT_OF_MEMORY, "arena full");
+    Slot& s = hslots_[0];
+    std::memset(&s, 0, sizeof(Slot));
+    s.goal = goal;
+    s.start = goal;
+    s.d = d;
+    s.pool_cap = L.pool_cap;
+    carve(s, arena_.as<char>() + off * 256, L, g_->n, d);
+    HIPCHK(hipMemcpyAsync(slots_.p, &s, sizeof(Slot), hipMemcpyHostToDevice, st_));
+    sh_[0].busy = true;
+    std::vector<int> one{0};
+    run_heuristics(one, /*seed=*/false);
+    HIPCHK(hipMemcpyAsync(out, s.h, sizeof(int32_t) * (size_t)d * g_->n, hipMemcpyDeviceToHost,
+                          st_));
+    HIPCHK(hipStreamSynchronize(st_));
+    sh_[0].busy = false;
+    ra_.give(off, (L.bytes + 255) / 256);
+  }
+
+ private:
+  void release(int s) {
+    ra_.give(sh_[s].off, sh_[s].len);
+    sh_[s].busy = false;
+    sh_[s].cancel = false;
+  }
+
+  void run_heuristics(const std::vector<int>& fresh, bool seed = true) {
+    const int nj = (int)fresh.size();
+    const size_t per = (size_t)MAXD * 3 * g_->n * 4;
+    if (hscr_.bytes < per * nj) hscr_.alloc(per * nj, st_);
+    if (hcnt_.bytes < (size_t)nj * MAXD * 3 * 4) hcnt_.alloc((size_t)nj * MAXD * 3 * 4, st_);
+    if (hjob_.bytes < (size_t)nj * 4) hjob_.alloc((size_t)nj * 4, st_);
+    HIPCHK(hipMemcpyAsync(hjob_.p, fresh.data(), nj * 4, hipMemcpyHostToDevice, st_));
+    const GraphDev G = g_->view();
+    HIPCHK(hipEventRecord(ev0_, st_));
+    launch_heur_init(slots_.as<Slot>(), hjob_.as<int32_t>(), nj, G, hscr_.as<int32_t>(),
+                     hcnt_.as<int32_t>(), st_);
+    HIPCHK(hipGetLastError());
+    std::vector<int32_t> cnt((size_t)nj * MAXD * 3);
+    const int gx = std::max(1, std::min(512, (g_->n / 8 + 255) / 256));
+    for (int r = 0;; ++r) {
+      launch_heur_round(slots_.as<Slot>(), hjob_.as<int32_t>(), nj, G, hscr_.as<int32_t>(),
+                        hcnt_.as<int32_t>(), r, gx, st_);
+      if ((r & 7) == 7) {
+        HIPCHK(hipMemcpyAsync(cnt.data(), hcnt_.p, cnt.size() * 4, hipMemcpyDeviceToHost, st_));
+        HIPCHK(hipStreamSynchronize(st_));
+        // after round r the worklist of round r+1 is in counter (r+1)%3
+        bool any = false;
+        for (int j = 0; j < nj && !any; ++j)
+          for (int k = 0; k < MAXD && !any; ++k) any = cnt[((size_t)j * MAXD + k) * 3 + (r + 1) % 3] > 0;
+        if (!any) break;
+      }
+      if (r > 4 * g_->n + 64) throw MosError(MOS_E_DEVICE, "heuristic did not converge");
+    }
+    if (seed)
+      for (int s : fresh) launch_slot_init(slots_.as<Slot>(), s, G, st_);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipEventRecord(ev1_, st_));
+    HIPCHK(hipStreamSynchronize(st_));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, ev0_, ev1_));
+    for (int s : fresh) sh_[s].heur_ms += ms;
+  }
+
+  void run_steps() {
+    StepArgs a;
+    a.slots = slots_.as<Slot>();
+    a.hist = hist_.as<int32_t>();
+    a.G = g_->view();
+    a.nslots = S_;
+    a.gx = gx_;
+    if (!graph_exec_ && !graph_failed_) {
+      hipGraph_t gr = nullptr;
+      if (hipStreamBeginCapture(st_, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+        for (int k = 0; k < K_; ++k) launch_step(a, st_);
+        if (hipStreamEndCapture(st_, &gr) == hipSuccess && gr &&
+            hipGraphInstantiate(&graph_exec_, gr, nullptr, nullptr, 0) == hipSuccess) {
+        } else {
+          graph_exec_ = nullptr;
+          graph_failed_ = true;
+        }
+        if (gr) hipGraphDestroy(gr);
+      } else {
+        graph_failed_ = true;
+      }
+      hipGetLastError();
+    }
+    if (graph_exec_) {
+      HIPCHK(hipGraphLaunch(graph_exec_, st_));
+    } else {
+      for (int k = 0; k < K_; ++k) launch_step(a, st_);
+      HIPCHK(hipGetLastError());
+    }
+  }
+
+  mos_result* harvest(int s) {
+    const Slot& d = hslots_[s];
+    std::unique_ptr<mos_result> r(new mos_result());
+    const int dd = d.d;
+    const int64_t np = d.P_n;
+    r->d = dd;
+    r->size = np;
+    r->costs.resize((size_t)np * dd);
+    if (np > 0) {
+      std::vector<int32_t> planes((size_t)np * dd);
+      for (int k = 0; k < dd; ++k)
+        HIPCHK(hipMemcpyAsync(planes.data() + (size_t)k * np, d.Pg[d.P_sel] + (size_t)k * d.P_cap,
+                              np * 4, hipMemcpyDeviceToHost, st_));
+      HIPCHK(hipStreamSynchronize(st_));
+      for (int64_t i = 0; i < np; ++i)
+        for (int k = 0; k < dd; ++k) r->costs[(size_t)i * dd + k] = planes[(size_t)k * np + i];
+      if (want_paths_) {
+        DevBuf len, off, arcs;
+        len.alloc(np * 4, st_);
+        launch_path_len(slots_.as<Slot>(), s, (int)np, len.as<int32_t>(), st_);
+        std::vector<int32_t> hl(np);
+        HIPCHK(hipMemcpyAsync(hl.data(), len.p, np * 4, hipMemcpyDeviceToHost, st_));
+        HIPCHK(hipStreamSynchronize(st_));
+        r->path_off.assign(np + 1, 0);
+        for (int64_t i = 0; i < np; ++i) r->path_off[i + 1] = r->path_off[i] + hl[i];
+        const int64_t tot = r->path_off[np];
+        r->arcs.resize(tot);
+        if (tot > 0) {
+          off.alloc((np + 1) * 8, st_);
+          arcs.alloc(tot * 4, st_);
+          HIPCHK(hipMemcpyAsync(off.p, r->path_off.data(), (np + 1) * 8, hipMemcpyHostToDevice, st_));
+          launch_path_write(slots_.as<Slot>(), s, (int)np, off.as<int64_t>(), arcs.as<int32_t>(),
+                            st_);
+          HIPCHK(hipMemcpyAsync(r->arcs.data(), arcs.p, tot * 4, hipMemcpyDeviceToHost, st_));
+        }
+        HIPCHK(hipStreamSynchronize(st_));
+      }
+    } else if (want_paths_) {
+      r->path_off.assign(1, 0);
+    }
+    mos_stats& o = r->stats;
+    o.pops = d.st[ST_POPS];
+    o.goal_pops = d.st[ST_GOAL_POPS];
+    o.candidates = d.st[ST_CANDS];
+    o.p_pairs = d.st[ST_PPAIRS];
+    o.group_pairs = d.st[ST_GPAIRS];
+    o.frontier_pairs = d.st[ST_FPAIRS];
+    o.inserted = d.st[ST_INSERTED];
+    o.pruned = d.st[ST_PRUNED];
+    o.steps = d.st[ST_STEPS];
+    o.front = np;
+    o.frontier_bytes = d.st[ST_FBYTES];
+    o.search_ms = sh_[s].search_ms;
+    o.heuristic_ms = sh_[s].heur_ms;
+    return r.release();
+  }
+
+  const mos_graph* g_;
+  int S_, B_;
+  int64_t label_limit_;
+  bool want_paths_;
+  int K_;
+  hipStream_t st_ = nullptr;
+  bool own_stream_ = false;
+  DevBuf arena_, slots_, hist_, hscr_, hcnt_, hjob_;
+  Slot* hslots_ = nullptr;
+  RangeAlloc ra_;
+  std::vector<SlotHost> sh_;
+  int gx_ = 1;
+  hipEvent_t ev0_ = nullptr, ev1_ = nullptr;
+  hipGraphExec_t graph_exec_ = nullptr;
+  bool graph_failed_ = false;
+  int64_t readmissions_ = 0;
+};
+
+// ------------------------------------------------------------ option helpers
+struct Opts {
+  int n_objectives = 0, B = 256, max_slots = 0, want_paths = 1, steps = 8;
+  int64_t label_limit = 0, mem_budget = 0;
+  hipStream_t stream = nullptr;
+};
+
+static mos_status read_opts(const mos_options* o, Opts* out) {
+  Opts r;
+  if (o) {
+    if (o->struct_size < offsetof(mos_options, costs_only))
+      return set_err(MOS_E_INVALID_ARG, "mos_options.struct_size too small");
+    r.n_objectives = o->n_objectives;
+    if (o->batch_width) r.B = o->batch_width;
+    r.max_slots = o->max_slots;
+    r.label_limit = o->label_limit;
+    r.mem_budget = o->mem_budget;
+    r.stream = (hipStream_t)o->stream;
+    if (o->struct_size >= offsetof(mos_options, steps_per_poll)) r.want_paths = o->costs_only ? 0 : 1;
+    if (o->struct_size >= sizeof(mos_options) && o->steps_per_poll > 0) r.steps = o->steps_per_poll;
+  }
+  if (r.B < 1 || r.B > BATCH_SORT / 2)
+    return set_err(MOS_E_INVALID_ARG, "batch_width must lie in [1, 4096]");
+  if (r.max_slots < 0 || r.label_limit < 0 || r.mem_budget < 0 || r.n_objectives < 0)
+    return set_err(MOS_E_INVALID_ARG, "negative option");
+  if (r.steps > 1024) return set_err(MOS_E_INVALID_ARG, "steps_per_poll too large");
+  *out = r;
+  return MOS_OK;
+}
+
+static int64_t default_budget(int64_t want) {
+  size_t fr = 0, tot = 0;
+  HIPCHK(hipMemGetInfo(&fr, &tot));
+  int64_t cap = (int64_t)(fr * 0.7);
+  if (want > 0) {
+    if (want > cap) throw MosError(MOS_E_OUT_OF_MEMORY, "mem_budget exceeds free device memory");
+    return want;
+  }
+  return std::min<int64_t>(cap, (int64_t)48 << 30);
+}
+
+// ------------------------------------------------------------------ C ABI
+extern "C" {
+
+const char* mos_status_string(mos_status s) {
+  switch (s) {
+    case MOS_OK: return "ok";
+    case MOS_E_INVALID_ARG: return "invalid argument";
+    case MOS_E_NEGATIVE_COST: return "negative cost";
+    case MOS_E_OVERFLOW_RISK: return "int32 overflow risk";
+    case MOS_E_NO_DEVICE: return "no device";
+    case MOS_E_DEVICE: return "device error";
+    case MOS_E_OUT_OF_MEMORY: return "out of memory";
+    case MOS_E_LABEL_LIMIT: return "label limit";
+    case MOS_E_CANCELLED: return "cancelled";
+    case MOS_E_NOT_READY: return "not ready";
+  }
+  return "unknown status";
+}
+
+const char* mos_last_error(void) { return g_last_error.c_str(); }
+
+mos_status mos_set_allocator(void* (*alloc)(size_t, void*, void*), void (*release)(void*, void*),
+                             void* ctx) {
+  if ((alloc == nullptr) != (release == nullptr))
+    return set_err(MOS_E_INVALID_ARG, "alloc and release must both be set or both be NULL");
+  std::lock_guard<std::mutex> lk(g_hooks_mu);
+  g_hooks.alloc = alloc;
+  g_hooks.release = release;
+  g_hooks.ctx = ctx;
+  return MOS_OK;
+}
+
+mos_status mos_graph_create(int32_t n, int64_t m, int32_t D, const int64_t* row_ptr,
+                            const int32_t* col, const int32_t* cost, mos_graph** out) {
+  // ---- validation (no device call before it passes)
+  if (!out) return set_err(MOS_E_INVALID_ARG, "out is NULL");
+  if (n < 1 || m < 0 || m >= ((int64_t)1 << 31) - 1)
+    return set_err(MOS_E_INVALID_ARG, "n_nodes must be >= 1 and n_arcs in [0, 2^31-1)");
+  if (D < 1 || D > MOS_MAX_OBJECTIVES) return set_err(MOS_E_INVALID_ARG, "D must lie in [1, 8]");
+  if (!row_ptr || (m > 0 && (!col || !cost))) return set_err(MOS_E_INVALID_ARG, "NULL array");
+  if (row_ptr[0] != 0 || row_ptr[n] != m) return set_err(MOS_E_INVALID_ARG, "row_ptr ends");
+  int32_t maxdeg = 0;
+  for (int32_t v = 0; v < n; ++v) {
+    const int64_t a = row_ptr[v], b = row_ptr[v + 1];
+    if (b < a) return set_err(MOS_E_INVALID_ARG, "row_ptr not non-decreasing");
+    maxdeg = (int32_t)std::max<int64_t>(maxdeg, b - a);
+  }
+  for (int64_t e = 0; e < m; ++e)
+    if (col[e] < 0 || col[e] >= n) return set_err(MOS_E_INVALID_ARG, "arc target out of range");
+  for (int32_t k = 0; k < D; ++k) {
+    int64_t sum = 0, mx = 0;
+    for (int64_t e = 0; e < m; ++e) {
+      const int64_t c = cost[e * D + k];
+      if (c < 0) return set_err(MOS_E_NEGATIVE_COST, "negative arc cost");
+      sum += c;
+      mx = std::max(mx, c);
+    }
+    if (2 * sum + mx > (int64_t)INT32_MAX)
+      return set_err(MOS_E_OVERFLOW_RISK, "2*sum+max of an objective exceeds INT32_MAX");
+  }
+  return guarded([&]() -> mos_status {
+    const int dev = ensure_device();
+    std::unique_ptr<mos_graph> g(new mos_graph());
+    g->n = n;
+    g->m = m;
+    g->D = D;
+    g->maxdeg = maxdeg;
+    g->device = dev;
+    std::vector<int32_t> rp(n + 1), planes((size_t)D * std::max<int64_t>(m, 1));
+    for (int32_t v = 0; v <= n; ++v) rp[v] = (int32_t)row_ptr[v];
+    for (int64_t e = 0; e < m; ++e)
+      for (int k = 0; k < D; ++k) planes[(size_t)k * m + e] = cost[e * D + k];
+    // reverse CSR
+    std::vector<int32_t> rrow(n + 1, 0), rsrc(std::max<int64_t>(m, 1)), rarc(std::max<int64_t>(m, 1));
+    for (int64_t e = 0; e < m; ++e) rrow[col[e] + 1]++;
+    for (int32_t v = 0; v < n; ++v) rrow[v + 1] += rrow[v];
+    std::vector<int32_t> fill(rrow.begin(), rrow.end() - 1);
+    for (int32_t u = 0; u < n; ++u)
+      for (int64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
+        const int32_t p = fill[col[e]]++;
+        rsrc[p] = u;
+        rarc[p] = (int32_t)e;
+      }
+    hipStream_t st = nullptr;
+    g->row_ptr.alloc((n + 1) * 4, st);
+    g->col.alloc(std::max<int64_t>(m, 1) * 4, st);
+    g->cost.alloc(planes.size() * 4, st);
+    g->rrow.alloc((n + 1) * 4, st);
+    g->rsrc.alloc(rsrc.size() * 4, st);
+    g->rarc.alloc(rarc.size() * 4, st);
+    HIPCHK(hipMemcpy(g->row_ptr.p, rp.data(), (n + 1) * 4, hipMemcpyHostToDevice));
+    if (m > 0) HIPCHK(hipMemcpy(g->col.p, col, m * 4, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(g->cost.p, planes.data(), planes.size() * 4, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(g->rrow.p, rrow.data(), (n + 1) * 4, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(g->rsrc.p, rsrc.data(), rsrc.size() * 4, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(g->rarc.p, rarc.data(), rarc.size() * 4, hipMemcpyHostToDevice));
+    *out = g.release();
+    return MOS_OK;
+  });
+}
+
+void mos_graph_destroy(mos_graph* g) { delete g; }
+
+static mos_status check_query(const mos_graph* g, int32_t s, int32_t t, int32_t nobj, int* d) {
+  if (s < 0 || s >= g->n || t < 0 || t >= g->n)
+    return set_err(MOS_E_INVALID_ARG, "start or goal out of range");
+  if (nobj < 0 || nobj > g->D) return set_err(MOS_E_INVALID_ARG, "n_objectives out of range");
+  *d = nobj == 0 ? g->D : nobj;
+  return MOS_OK;
+}
+
+mos_status mos_solve_batch(const mos_graph* g, int32_t nq, const int32_t* starts,
+                           const int32_t* goals, const int32_t* n_objectives,
+                           const mos_options* opt, mos_result** out, mos_status* st) {
+  if (!g || nq < 0 || (nq > 0 && (!starts || !goals || !out || !st)))
+    return set_err(MOS_E_INVALID_ARG, "NULL argument or negative count");
+  Opts o;
+  mos_status rs = read_opts(opt, &o);
+  if (rs != MOS_OK) return rs;
+  std::vector<int> dq(nq);
+  for (int32_t i = 0; i < nq; ++i) {
+    int32_t nobj = n_objectives ? n_objectives[i] : o.n_objectives;
+    rs = check_query(g, starts[i], goals[i], nobj, &dq[i]);
+    if (rs != MOS_OK) return rs;
+  }
+  if (nq == 0) return MOS_OK;
+  return guarded([&]() -> mos_status {
+    HIPCHK(hipSetDevice(g->device));
+    const int S = o.max_slots > 0 ? std::min(o.max_slots, nq) : std::min(nq, 256);
+    Engine eng(g, S, default_budget(o.mem_budget), o.stream, o.B, o.label_limit, o.want_paths != 0,
+               o.steps);
+    std::deque<QueryReq> pending;
+    for (int32_t i = 0; i < nq; ++i) {
+      QueryReq q;
+      q.id = i;
+      q.start = starts[i];
+      q.goal = goals[i];
+      q.d = dq[i];
+      q.reserve = eng.default_reserve();
+      pending.push_back(q);
+      out[i] = nullptr;
+      st[i] = MOS_E_NOT_READY;
+    }
+    std::vector<Finished> done;
+    int64_t left = nq;
+    mos_status first_bad = MOS_OK;
+    std::string msg;
+    while (left > 0) {
+      done.clear();
+      eng.tick(pending, done);
+      for (auto& f : done) {
+        out[f.id] = f.res;
+        st[f.id] = f.st;
+        if (f.st != MOS_OK && first_bad == MOS_OK) {
+          first_bad = f.st;
+          msg = f.msg;
+        }
+        --left;
+      }
+      if (pending.empty() && eng.busy_count() == 0 && left > 0)
+        throw MosError(MOS_E_DEVICE, "engine stalled");
+    }
+    if (first_bad != MOS_OK) return set_err(first_bad, msg);
+    return MOS_OK;
+  });
+}
+
+mos_status mos_solve(const mos_graph* g, int32_t start, int32_t goal, const mos_options* opt,
+                     mos_result** out) {
+  if (!g || !out) return set_err(MOS_E_INVALID_ARG, "NULL argument");
+  Opts o;
+  mos_status rs = read_opts(opt, &o);
+  if (rs != MOS_OK) return rs;
+  int d;
+  rs = check_query(g, start, goal, o.n_objectives, &d);
+  if (rs != MOS_OK) return rs;
+  mos_options o1{};
+  if (opt) std::memcpy(&o1, opt, std::min<size_t>(opt->struct_size, sizeof(mos_options)));
+  o1.struct_size = sizeof(mos_options);
+  o1.max_slots = 1;
+  mos_status st1 = MOS_E_NOT_READY;
+  mos_result* r = nullptr;
+  rs = mos_solve_batch(g, 1, &start, &goal, nullptr, &o1, &r, &st1);
+  if (rs != MOS_OK) return rs;
+  *out = r;
+  return MOS_OK;
+}
+
+int64_t mos_result_size(const mos_result* r) { return r ? r->size : 0; }
+int32_t mos_result_dim(const mos_result* r) { return r ? r->d : 0; }
+
+mos_status mos_result_costs(const mos_result* r, int32_t* out) {
+  if (!r || (!out && r->size > 0)) return set_err(MOS_E_INVALID_ARG, "NULL argument");
+  if (!r->costs.empty()) std::memcpy(out, r->costs.data(), r->costs.size() * 4);
+  return MOS_OK;
+}
+
+mos_status mos_result_path(const mos_result* r, int64_t i, int32_t* arcs, int64_t cap,
+                           int64_t* len) {
+  if (!r || !len || i < 0 || i >= r->size || cap < 0 || (cap > 0 && !arcs))
+    return set_err(MOS_E_INVALID_ARG, "bad path request");
+  if (r->path_off.empty()) return set_err(MOS_E_INVALID_ARG, "paths were not requested");
+  const int64_t a = r->path_off[i], b = r->path_off[i + 1];
+  *len = b - a;
+  const int64_t c = std::min(cap, b - a);
+  if (c > 0) std::memcpy(arcs, r->arcs.data() + a, c * 4);
+  return MOS_OK;
+}
+
+mos_status mos_result_stats(const mos_result* r, mos_stats* out) {
+  if (!r || !out) return set_err(MOS_E_INVALID_ARG, "NULL argument");
+  *out = r->stats;
+  return MOS_OK;
+}
+
+void mos_result_destroy(mos_result* r) { delete r; }
+
+mos_status mos_heuristic(const mos_graph* g, int32_t goal, int32_t n_objectives, int32_t* h) {
+  if (!g || !h) return set_err(MOS_E_INVALID_ARG, "NULL argument");
+  int d;
+  mos_status rs = check_query(g, goal, goal, n_objectives, &d);
+  if (rs != MOS_OK) return rs;
+  return guarded([&]() -> mos_status {
+    HIPCHK(hipSetDevice(g->device));
+    Layout L;
+    int64_t need = 0;
+    for (int64_t b = 1 << 22;; b *= 2) {
+      if (plan_layout(g, d, 1, b, 16, &L)) {
+        need = b;
+        break;
+      }
+      if (b > ((int64_t)1 << 40)) throw MosError(MOS_E_OUT_OF_MEMORY, "graph too large");
+    }
+    Engine eng(g, 1, need, nullptr, 1, 16, false, 1);
+    eng.heuristic_only(goal, d, h);
+    return MOS_OK;
+  });
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ server
+struct mos_server {
+  const mos_graph* g = nullptr;
+  std::unique_ptr<Engine> eng;
+  std::thread th;
+  std::mutex mu;
+  std::condition_variable cv, cv_done;
+  std::deque<QueryReq> inbox;
+  std::map<uint64_t, Finished> finished;
+  std::map<uint64_t, bool> known;  // ticket -> collected
+  bool stop = false;
+  uint64_t next = 1;
+  int64_t submitted = 0, nfinished = 0, ticks = 0;
+  std::atomic<int64_t> resident{0}, queued{0};
+  std::vector<uint64_t> cancels;
+  std::string fatal;
+  mos_status fatal_st = MOS_OK;
+
+  void loop() {
+    hipSetDevice(g->device);
+    std::deque<QueryReq> pending;
+    std::vector<Finished> done;
+    for (;;) {
+      std::vector<uint64_t> cs;
+      {
+        std::unique_lock<std::mutex> lk(mu);
+        cv.wait(lk, [&] { return stop || !inbox.empty() || !pending.empty() || eng->busy_count() > 0 || !cancels.empty(); });
+        if (stop) return;
+        while (!inbox.empty()) {
+          pending.push_back(inbox.front());
+          inbox.pop_front();
+        }
+        cs.swap(cancels);
+      }
+      for (uint64_t t : cs) {
+        bool was_pending = false;
+        for (auto it = pending.begin(); it != pending.end(); ++it)
+          if ((uint64_t)it->id == t) {
+            pending.erase(it);
+            was_pending = true;
+            break;
+          }
+        if (was_pending) {
+          std::lock_guard<std::mutex> lk(mu);
+          finished[t] = Finished{(int64_t)t, MOS_E_CANCELLED, nullptr, "cancelled"};
+          nfinished++;
+          cv_done.notify_all();
+        } else {
+          eng->cancel_query((int64_t)t);
+        }
+      }
+      done.clear();
+      try {
+        eng->tick(pending, done);
+      } catch (const MosError& e) {
+        std::lock_guard<std::mutex> lk(mu);
+        fatal = e.what();
+        fatal_st = e.st;
+        for (auto& q : pending) finished[q.id] = Finished{q.id, e.st, nullptr, e.what()};
+        pending.clear();
+        stop = true;
+        cv_done.notify_all();
+        return;
+      }
+      {
+        std::lock_guard<std::mutex> lk(mu);
+        ticks++;
+        for (auto& f : done) {
+          finished[(uint64_t)f.id] = f;
+          nfinished++;
+        }
+        resident = eng->busy_count();
+        queued = (int64_t)pending.size() + (int64_t)inbox.size();
+        if (!done.empty()) cv_done.notify_all();
+      }
+    }
+  }
+};
+
+extern "C" {
+
+mos_status mos_server_create(const mos_graph* g, int64_t mem_budget, int32_t max_slots,
+                             mos_server** out) {
+  if (!g || !out || mem_budget < 0 || max_slots < 0)
+    return set_err(MOS_E_INVALID_ARG, "bad server arguments");
+  return guarded([&]() -> mos_status {
+    HIPCHK(hipSetDevice(g->device));
+    std::unique_ptr<mos_server> s(new mos_server());
+    s->g = g;
+    const int S = max_slots > 0 ? max_slots : 64;
+    s->eng.reset(new Engine(g, S, default_budget(mem_budget), nullptr, 256, 0, true, 4));
+    s->th = std::thread([p = s.get()] { p->loop(); });
+    *out = s.release();
+    return MOS_OK;
+  });
+}
+
+mos_status mos_server_submit(mos_server* s, int32_t start, int32_t goal, int32_t n_objectives,
+                             uint64_t* ticket) {
+  if (!s || !ticket) return set_err(MOS_E_INVALID_ARG, "NULL argument");
+  int d;
+  mos_status rs = check_query(s->g, start, goal, n_objectives, &d);
+  if (rs != MOS_OK) return rs;
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (s->stop) return set_err(s->fatal_st == MOS_OK ? MOS_E_DEVICE : s->fatal_st, "server stopped: " + s->fatal);
+  QueryReq q;
+  q.id = (int64_t)s->next++;
+  q.start = start;
+  q.goal = goal;
+  q.d = d;
+  q.reserve = s->eng->default_reserve();
+  s->inbox.push_back(q);
+  s->known[(uint64_t)q.id] = false;
+  s->submitted++;
+  *ticket = (uint64_t)q.id;
+  s->cv.notify_all();
+  return MOS_OK;
+}
+
+static mos_status collect(mos_server* s, uint64_t ticket, mos_result** out) {
+  auto it = s->finished.find(ticket);
+  if (it == s->finished.end()) return MOS_E_NOT_READY;
+  Finished f = it->second;
+  s->finished.erase(it);
+  s->known[ticket] = true;
+  if (f.st != MOS_OK) return set_err(f.st, f.msg);
+  *out = f.res;
+  return MOS_OK;
+}
+
+mos_status mos_server_poll(mos_server* s, uint64_t ticket, mos_result** out) {
+  if (!s || !out) return set_err(MOS_E_INVALID_ARG, "NULL argument");
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto k = s->known.find(ticket);
+  if (k == s->known.end() || k->second) return set_err(MOS_E_INVALID_ARG, "unknown ticket");
+  return collect(s, ticket, out);
+}
+
+mos_status mos_server_wait(mos_server* s, uint64_t ticket, int64_t timeout_ms, mos_result** out) {
+  if (!s || !out) return set_err(MOS_E_INVALID_ARG, "NULL argument");
+  std::unique_lock<std::mutex> lk(s->mu);
+  auto k = s->known.find(ticket);
+  if (k == s->known.end() || k->second) return set_err(MOS_E_INVALID_ARG, "unknown ticket");
+  auto ready = [&] { return s->finished.count(ticket) > 0; };
+  if (timeout_ms < 0) s->cv_done.wait(lk, ready);
+  else if (!s->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), ready))
+    return MOS_E_NOT_READY;
+  return collect(s, ticket, out);
+}
+
+mos_status mos_server_cancel(mos_server* s, uint64_t ticket) {
+  if (!s) return set_err(MOS_E_INVALID_ARG, "NULL argument");
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto k = s->known.find(ticket);
+  if (k == s->known.end() || k->second) return set_err(MOS_E_INVALID_ARG, "unknown ticket");
+  if (s->finished.count(ticket)) return MOS_OK;  // already done: nothing to cancel
+  for (auto it = s->inbox.begin(); it != s->inbox.end(); ++it)
+    if ((uint64_t)it->id == ticket) {
+      s->inbox.erase(it);
+      s->finished[ticket] = Finished{(int64_t)ticket, MOS_E_CANCELLED, nullptr, "cancelled"};
+      s->nfinished++;
+      s->cv_done.notify_all();
+      return MOS_OK;
+    }
+  s->cancels.push_back(ticket);
+  s->cv.notify_all();
+  return MOS_OK;
+}
+
+mos_status mos_server_counters(mos_server* s, int64_t* out6) {
+  if (!s || !out6) return set_err(MOS_E_INVALID_ARG, "NULL argument");
+  std::lock_guard<std::mutex> lk(s->mu);
+  out6[0] = s->submitted;
+  out6[1] = s->nfinished;
+  out6[2] = s->resident;
+  out6[3] = s->queued;
+  out6[4] = s->ticks;
+  out6[5] = s->eng ? s->eng->readmissions() : 0;
+  return MOS_OK;
+}
+
+void mos_server_destroy(mos_server* s) {
+  if (!s) return;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+    s->cv.notify_all();
+  }
+  if (s->th.joinable()) s->th.join();
+  for (auto& kv : s->finished) delete kv.second.res;
+  s->eng.reset();
+  delete s;
+}
+
+}  // extern "C"

@@ -1,0 +1,183 @@
+// Per-query set-up and tear-down kernels: heuristic, slot initialisation, result paths.
+//
+// Heuristic (paper, Section 4: an admissible heuristic computed by
+// single-source shortest paths for each objective): h_k(v) is the exact
+// shortest v -> goal distance under objective k, found by label-correcting
+// relaxation over the reversed arcs from the goal.  Each round relaxes the
+// arcs entering the nodes improved in the previous round; a round stamp per
+// node keeps every worklist duplicate-free.  All (query, objective) instances
+// of an admission wave run in the same launches.
+#include "kernels.h"
+
+namespace mos {
+
+constexpr int NT_H = 256;
+
+// job j: slot slot_of[j]; instance (j, k) uses scratch hs + (j*MAXD + k) * 3n:
+//   [0, n) worklist A, [n, 2n) worklist B, [2n, 3n) round stamps;
+// counts at cnt + (j*MAXD + k) * 3 (three rotating counters).
+__global__ void k_heur_init(Slot* slots, const int32_t* slot_of, GraphDev G, int32_t* hs,
+                            int32_t* cnt) {
+  const int j = blockIdx.z, k = blockIdx.y;
+  Slot* S = &slots[slot_of[j]];
+  const bool used = k < S->d;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    // every counter of the job is initialised: the host polls all MAXD of them
+    int32_t* c = cnt + ((size_t)j * MAXD + k) * 3;
+    c[0] = used ? 1 : 0;
+    c[1] = 0;
+    c[2] = 0;
+  }
+  if (!used) return;
+  const int n = G.n;
+  int32_t* h = S->h + (size_t)k * n;
+  int32_t* base = hs + ((size_t)j * MAXD + k) * 3 * n;
+  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+    h[v] = (v == S->goal) ? 0 : UNREACH;
+    base[2 * n + v] = 0;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) base[0] = S->goal;
+}
+
+__global__ void k_heur_round(Slot* slots, const int32_t* slot_of, GraphDev G, int32_t* hs,
+                             int32_t* cnt, int r) {
+  const int j = blockIdx.z, k = blockIdx.y;
+  Slot* S = &slots[slot_of[j]];
+  if (k >= S->d) return;
+  const int n = G.n;
+  int32_t* h = S->h + (size_t)k * n;
+  int32_t* base = hs + ((size_t)j * MAXD + k) * 3 * n;
+  const int32_t* cur = base + (size_t)(r & 1) * n;
+  int32_t* nxt = base + (size_t)((r + 1) & 1) * n;
+  int32_t* stamp = base + 2 * (size_t)n;
+  int32_t* c = cnt + ((size_t)j * MAXD + k) * 3;
+  const int ncur = c[r % 3];
+  int32_t* ncnt = &c[(r + 1) % 3];
+  if (blockIdx.x == 0 && threadIdx.x == 0) c[(r + 2) % 3] = 0;
+  const int32_t* cost = G.cost + (size_t)k * G.m;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < ncur; i += gridDim.x * blockDim.x) {
+    const int v = cur[i];
+    const int dv = h[v];
+    for (int p = G.rrow[v]; p < G.rrow[v + 1]; ++p) {
+      const int u = G.rsrc[p];
+      const int nd = dv + cost[G.rarc[p]];
+      if (nd < h[u]) {
+        const int old = atomicMin(&h[u], nd);
+        if (nd < old && atomicMax(&stamp[u], r + 1) < r + 1) {
+          const int pos = atomicAdd(ncnt, 1);
+          nxt[pos] = u;
+        }
+      }
+    }
+  }
+}
+
+// Reset the per-node structures of a slot and seed the start label
+// (Algorithm 1 lines 3-4).  A start that cannot reach the goal finishes the
+// query at once with an empty front.
+__global__ void k_slot_init(Slot* slots, int s, GraphDev G) {
+  Slot* S = &slots[s];
+  const int n = G.n;
+  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+    NodeRec z;
+    z.off = 0;
+    z.cap = 0;
+    z.count = 0;
+    S->node[v] = z;
+    S->grp_cnt[v] = 0;
+    S->grp_id[v] = -1;
+  }
+}
+
+__global__ void k_slot_seed(Slot* slots, int s, GraphDev G) {
+  Slot* S = &slots[s];
+  const int d = S->d, st = S->start, n = G.n;
+  bool reach = true;
+  for (int k = 0; k < d; ++k) reach = reach && S->h[(size_t)k * n + st] != UNREACH;
+  S->P_n = 0;
+  S->P_sel = 0;
+  S->cur_min = INT32_MAX;
+  S->lo_next = INT32_MAX;
+  if (!reach) {
+    S->n_labels = 0;
+    S->open_n = 0;
+    S->status = S_DONE;
+    return;
+  }
+  S->Lnode[0] = st;
+  S->Lpar[0] = -1;
+  S->Larc[0] = -1;
+  S->Lstate[0] = L_OPEN;
+  for (int k = 0; k < d; ++k) S->Lg[(size_t)k * S->pool_cap] = 0;
+  S->n_labels = 1;
+  NodeRec r;
+  r.off = 0;
+  r.cap = MINCAP;
+  r.count = 1;
+  for (int k = 0; k < d; ++k) S->fw[(size_t)k * MINCAP] = 0;
+  S->fw[(size_t)d * MINCAP] = 0;
+  S->node[st] = r;
+  S->fw_top = (int64_t)MINCAP * (d + 1);
+  S->open_f1[0][0] = S->h[st];
+  S->open_lab[0][0] = 0;
+  S->open_n = 1;
+  S->open_sel = 0;
+  S->lo = S->h[st];
+  S->st[ST_INSERTED] = 1;
+  S->status = S_RUN;
+}
+
+// Witness paths (paper, Section 3: parent pointers allow path reconstruction).
+__global__ void k_path_len(const Slot* slots, int s, int32_t* len) {
+  const Slot* S = &slots[s];
+  const int np = S->P_n;
+  const int32_t* Pl = S->Plab[S->P_sel];
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < np; i += gridDim.x * blockDim.x) {
+    int c = 0;
+    for (int x = Pl[i]; S->Lpar[x] >= 0; x = S->Lpar[x]) ++c;
+    len[i] = c;
+  }
+}
+
+__global__ void k_path_write(const Slot* slots, int s, const int64_t* off, int32_t* arcs) {
+  const Slot* S = &slots[s];
+  const int np = S->P_n;
+  const int32_t* Pl = S->Plab[S->P_sel];
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < np; i += gridDim.x * blockDim.x) {
+    int64_t pos = off[i + 1];
+    for (int x = Pl[i]; S->Lpar[x] >= 0; x = S->Lpar[x]) arcs[--pos] = S->Larc[x];
+  }
+}
+
+// ---------------------------------------------------------------- launchers
+void launch_heur_init(Slot* slots, const int32_t* slot_of, int njobs, const GraphDev& G,
+                      int32_t* hs, int32_t* cnt, hipStream_t st) {
+  const int gx = std::min(1024, (G.n + NT_H - 1) / NT_H);
+  hipLaunchKernelGGL(k_heur_init, dim3(gx, MAXD, njobs), dim3(NT_H), 0, st, slots, slot_of, G, hs,
+                     cnt);
+}
+
+void launch_heur_round(Slot* slots, const int32_t* slot_of, int njobs, const GraphDev& G,
+                       int32_t* hs, int32_t* cnt, int r, int gx, hipStream_t st) {
+  hipLaunchKernelGGL(k_heur_round, dim3(gx, MAXD, njobs), dim3(NT_H), 0, st, slots, slot_of, G,
+                     hs, cnt, r);
+}
+
+void launch_slot_init(Slot* slots, int s, const GraphDev& G, hipStream_t st) {
+  const int gx = std::min(2048, (G.n + 255) / 256);
+  hipLaunchKernelGGL(k_slot_init, dim3(gx), dim3(256), 0, st, slots, s, G);
+  hipLaunchKernelGGL(k_slot_seed, dim3(1), dim3(1), 0, st, slots, s, G);
+}
+
+void launch_path_len(const Slot* slots, int s, int np, int32_t* len, hipStream_t st) {
+  const int gx = std::max(1, std::min(1024, (np + 255) / 256));
+  hipLaunchKernelGGL(k_path_len, dim3(gx), dim3(256), 0, st, slots, s, len);
+}
+
+void launch_path_write(const Slot* slots, int s, int np, const int64_t* off, int32_t* arcs,
+                       hipStream_t st) {
+  const int gx = std::max(1, std::min(1024, (np + 255) / 256));
+  hipLaunchKernelGGL(k_path_write, dim3(gx), dim3(256), 0, st, slots, s, off, arcs);
+}
+
+}  // namespace mos

@@ -1,0 +1,171 @@
+// Shared definitions of the GPU search: slot descriptors, graph view, device helpers.
+//
+// A "slot" is one query resident on the device.  All search state of a slot
+// lives in one contiguous reservation of the engine's device arena; the host
+// carves it into the regions below when the query is admitted and stores typed
+// pointers in the Slot descriptor.  Every step kernel takes the whole slot
+// table (blockIdx.y = slot for the tiled kernels), so one launch advances
+// every resident query.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mos {
+
+constexpr int MAXD = 8;           // objectives supported by the kernels
+constexpr int NB = 4096;          // OPEN histogram bins: exact F1 values lo..lo+NB-2, then overflow
+constexpr int TIECAP = 1024;      // largest threshold-bin (tie) set ordered in LDS
+constexpr int MINCAP = 8;         // smallest frontier block, in entries
+constexpr int BATCH_SORT = 8192;  // largest popped batch (LDS sort by label id)
+constexpr int32_t UNREACH = INT32_MAX;  // heuristic of a node that cannot reach the goal
+constexpr int WAVE = 64;
+
+enum SlotStatus : int32_t {
+  S_IDLE = 0,
+  S_RUN = 1,
+  S_DONE = 2,
+  S_OVERFLOW = 3,  // a capacity of the reservation was exceeded
+  S_TIE = 4,       // a tie set too large to order exactly (not expected)
+};
+
+enum LabelState : uint8_t { L_OPEN = 0, L_CLOSED = 1, L_DEAD = 2 };
+
+// Per-slot statistics counters (int64 each).
+enum Stat {
+  ST_POPS = 0,
+  ST_GOAL_POPS,
+  ST_CANDS,
+  ST_PPAIRS,
+  ST_GPAIRS,
+  ST_FPAIRS,
+  ST_INSERTED,
+  ST_PRUNED,
+  ST_STEPS,
+  ST_FBYTES,
+  ST_GROUPS,
+  NSTAT = 16
+};
+
+// Frontier record of one node: the node's live labels are entries [0, count)
+// of a block of `cap` entries at word offset `off` of the slot's frontier
+// region; the block holds d int32 planes (objective k at off + k*cap) followed
+// by a plane of pool label ids.
+struct NodeRec {
+  int64_t off;
+  int32_t cap;
+  int32_t count;
+};
+
+struct GraphDev {
+  int32_t n, m, D, maxdeg;
+  const int32_t* row_ptr;  // n+1
+  const int32_t* col;      // m
+  const int32_t* cost;     // D planes of m: cost[k*m + e]
+  const int32_t* rrow;     // reverse CSR: arcs entering v are rrow[v]..rrow[v+1]-1
+  const int32_t* rsrc;     //   source node of each entering arc
+  const int32_t* rarc;     //   forward arc id of each entering arc
+};
+
+struct Slot {
+  // ---------------- set at admission
+  int32_t status;
+  int32_t start, goal, d;
+  int32_t B, batch_cap, cand_cap, tie_cap;
+  int32_t pool_cap, open_cap, P_cap, query_id;
+  int64_t fw_cap;  // words of the frontier region
+
+  int32_t* h;          // d planes of n: heuristic
+  NodeRec* node;       // n
+  int32_t* grp_cnt;    // n: candidates of this step per node (0 outside a step)
+  int32_t* grp_id;     // n: group id of the node in this step (-1 outside)
+  int32_t* Lnode;      // pool_cap: node of each label
+  int32_t* Lpar;       //   parent label (-1 for the start label)
+  int32_t* Larc;       //   arc that created the label (-1 for the start label)
+  int32_t* Lg;         //   d planes of pool_cap: g vectors
+  uint8_t* Lstate;     //   LabelState
+  int32_t* open_f1[2]; // open_cap each: F1 of the open entry
+  int32_t* open_lab[2];//   label id of the open entry
+  int32_t* Pg[2];      // d planes of P_cap each: goal front, lexicographically ascending
+  int32_t* Plab[2];    //   label id of each goal-front entry
+  int32_t* pscr;       // 2*(P_cap+1): goal-merge scratch (prune flags, survivor prefix)
+  int32_t* batch;      // batch_cap: popped labels
+  int32_t* reg;        // batch_cap: popped regular labels (ascending label id)
+  int32_t* reg_off;    // batch_cap+1: exclusive prefix of their out-degrees
+  int32_t* goal_lab;   // batch_cap: popped goal labels
+  int32_t* tie_f1;     // tie_cap
+  int32_t* tie_lab;    // tie_cap
+  int32_t* c_node;     // cand_cap: candidate target node
+  int32_t* c_par;      //   parent label
+  int32_t* c_arc;      //   arc
+  int32_t* c_g;        //   d planes of cand_cap
+  int32_t* c_keep;     //   survived the goal-front filter
+  int32_t* c_rank;     //   rank within its group, later rank among accepted
+  int32_t* c_rej;      //   rejected inside its group or by the frontier
+  int32_t* c_acc;      //   accepted (inserted)
+  int64_t* c_fslot;    //   word offset of the frontier label-id slot it was given
+  int32_t* order;      // cand_cap: candidates grouped by node
+  int32_t* grp_node;   // cand_cap: node of each group
+  int32_t* grp_off;    // cand_cap: first position of each group in `order`
+  int32_t* fw;         // frontier words
+
+  // ---------------- dynamic (device-updated)
+  int32_t n_labels, open_n, open_sel, P_n;
+  int32_t P_sel, lo, lo_next, cur_min;
+  int64_t fw_top;
+  int32_t t_star, r_tie, tie_mode, rebase;
+  int32_t batch_n, goal_n, reg_n, cand_n;
+  int32_t ngroups, tie_n, keep_n, accept_n;
+  int32_t err_line, pad1;
+
+  int64_t st[NSTAT];
+};
+
+// ------------------------------------------------------------ device helpers
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// Make LDS writes of this wave visible to its other lanes before they read.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+__device__ __forceinline__ int rank_below(uint64_t m) {
+  return __popcll(m & ((1ull << lane_id()) - 1ull));
+}
+
+// Wave-aggregated append: every active lane calls it; lanes with p get
+// consecutive positions from *ctr (one atomic per wave).  Returns -1 for !p.
+__device__ __forceinline__ int agg_append(int32_t* ctr, bool p) {
+  uint64_t m = ballot(p);
+  if (m == 0) return -1;
+  int leader = __ffsll((long long)m) - 1;
+  int base = 0;
+  if (lane_id() == leader) base = atomicAdd(ctr, __popcll(m));
+  base = __shfl(base, leader);
+  return p ? base + rank_below(m) : -1;
+}
+
+__device__ __forceinline__ int wave_min(int v) {
+  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+  return v;
+}
+
+__device__ __forceinline__ int64_t wave_sum64(int64_t v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// a <= b in every one of the d components (weak dominance, equality included).
+__device__ __forceinline__ bool weak_le(const int32_t* a, const int32_t* b, int d) {
+  bool ok = true;
+#pragma unroll
+  for (int k = 0; k < MAXD; ++k)
+    if (k < d) ok = ok && (a[k] <= b[k]);
+  return ok;
+}
+
+}  // namespace mos

@@ -1,0 +1,78 @@
+"""C ABI conventions that hold without a GPU: symbols, validation before any device call."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import gen
+
+
+@pytest.fixture(scope="module")
+def mos():
+    import paper_2411_16667_amd as m
+
+    return m
+
+
+def test_every_declared_symbol_is_exported(mos):
+    names = mos.exported_symbols_in_header()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(mos.raw, n), n
+
+
+def _create(mos, n, rp, col, cost, D):
+    h = ctypes.c_void_p()
+    rp = np.ascontiguousarray(rp, dtype=np.int64)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    cost = np.ascontiguousarray(cost, dtype=np.int32)
+    st = mos.raw.mos_graph_create(n, col.size, D, rp.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                  col.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                  cost.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                  ctypes.byref(h))
+    return st, h
+
+
+def test_validation_precedes_device(mos):
+    g, _, _ = gen.config1(0)
+    # negative cost
+    c = g.cost.copy(); c[10, 2] = -3
+    assert _create(mos, g.n, g.row_ptr, g.col, c, 3)[0] == mos.MOS_E_NEGATIVE_COST
+    # overflow risk: 2*sum + max > INT32_MAX
+    c = g.cost.copy(); c[0, 0] = 2**30
+    assert _create(mos, g.n, g.row_ptr, g.col, c, 3)[0] == mos.MOS_E_OVERFLOW_RISK
+    # target out of range
+    col = g.col.copy(); col[5] = g.n
+    assert _create(mos, g.n, g.row_ptr, col, g.cost, 3)[0] == mos.MOS_E_INVALID_ARG
+    # row_ptr not monotone / wrong ends
+    rp = g.row_ptr.copy(); rp[3], rp[4] = rp[4], rp[3]
+    assert _create(mos, g.n, rp, g.col, g.cost, 3)[0] == mos.MOS_E_INVALID_ARG
+    rp = g.row_ptr.copy(); rp[-1] -= 1
+    assert _create(mos, g.n, rp, g.col, g.cost, 3)[0] == mos.MOS_E_INVALID_ARG
+    # D out of range
+    assert _create(mos, g.n, g.row_ptr, g.col, np.zeros((g.n_arcs, 9)), 9)[0] == mos.MOS_E_INVALID_ARG
+    # NULL out-parameter
+    assert mos.raw.mos_graph_create(1, 0, 1, np.zeros(2, np.int64).ctypes.data_as(
+        ctypes.POINTER(ctypes.c_int64)), None, None, None) == mos.MOS_E_INVALID_ARG
+
+
+def test_status_strings_and_null_handles(mos):
+    for i in range(10):
+        assert mos.raw.mos_status_string(i)
+    assert mos.raw.mos_result_size(None) == 0
+    assert mos.raw.mos_result_dim(None) == 0
+    mos.raw.mos_result_destroy(None)
+    mos.raw.mos_graph_destroy(None)
+    mos.raw.mos_server_destroy(None)
+    assert mos.raw.mos_solve(None, 0, 0, None, None) == mos.MOS_E_INVALID_ARG
+
+
+def test_no_device_reported_cleanly(mos):
+    import torch
+
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is visible")
+    g, _, _ = gen.config1(0)
+    st, _ = _create(mos, g.n, g.row_ptr, g.col, g.cost, 3)
+    assert st == mos.MOS_E_NO_DEVICE
+    assert b"device" in mos.raw.mos_last_error()
