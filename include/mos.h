@@ -73,6 +73,8 @@ typedef struct {
   void* stream;         /* hipStream_t to run on, or NULL for the library's own */
   int32_t costs_only;   /* 0 (default) = also reconstruct witness paths; 1 = costs only */
   int32_t steps_per_poll; /* device steps between host status polls; 0 = default */
+  int32_t profile_kernels; /* sessions only: 1 = time every kernel of every step with
+                              HIP events (kernels are then launched one by one) */
 } mos_options;
 
 /* Counters of one query (paper, Section 6: label extractions, candidate
@@ -81,7 +83,8 @@ typedef struct {
  * make: against the goal front P, against another candidate of the same step
  * and target node, or against a live label of the target node's frontier. */
 typedef struct {
-  int64_t pops;            /* labels taken from OPEN and processed */
+  int64_t pops;            /* labels taken from OPEN and processed (expanded or merged
+                              into the goal front) */
   int64_t goal_pops;       /* of which at the goal */
   int64_t candidates;      /* arcs expanded (candidate labels generated) */
   int64_t p_pairs;         /* candidate x goal-front pairs */
@@ -92,6 +95,10 @@ typedef struct {
   int64_t steps;           /* batched label steps run */
   int64_t front;           /* size of the returned front */
   int64_t frontier_bytes;  /* algorithmic bytes of frontier reads: 4*d per frontier pair-row */
+  int64_t killed;          /* labels dropped when popped: the goal front dominates their F
+                              (the paper's PruneOPEN, applied lazily) */
+  int64_t frontier_bytes_onepass; /* part of frontier_bytes from groups checked by one
+                                     wave in a single pass */
   double search_ms;        /* device time of the label steps */
   double heuristic_ms;     /* device time of the heuristic (reverse SSSP) */
 } mos_stats;
@@ -162,6 +169,29 @@ mos_status mos_server_cancel(mos_server* s, uint64_t ticket);
  * [4] ticks run, [5] re-admissions after overflow. */
 mos_status mos_server_counters(mos_server* s, int64_t* out6);
 void mos_server_destroy(mos_server* s);
+
+/* Single-query session: the query's label state stays resident on the device
+ * and the caller advances the search a number of batched label steps at a time
+ * (the same steps mos_solve runs).  mos_session_create computes the heuristic
+ * and seeds the start label; mos_session_step runs up to nsteps steps and sets
+ * *done to 1 once OPEN is empty (steps after that do nothing);
+ * mos_session_stats reports the counters so far (a partial search: the front
+ * size is that of the goal front so far); mos_session_result runs the search
+ * to completion and returns the exact front (MOS_E_LABEL_LIMIT if the
+ * reservation is outgrown).  Kernel times are kept when
+ * options.profile_kernels = 1: entry i of mos_session_kernel_times gives the
+ * kernel's name, its summed duration in ms and its launch count; i ranges
+ * over 0 .. mos_session_kernel_count()-1. */
+typedef struct mos_session mos_session;
+mos_status mos_session_create(const mos_graph* g, int32_t start, int32_t goal,
+                              const mos_options* opt, mos_session** out);
+mos_status mos_session_step(mos_session* s, int64_t nsteps, int32_t* done);
+mos_status mos_session_stats(const mos_session* s, mos_stats* out);
+mos_status mos_session_result(mos_session* s, mos_result** out);
+int32_t mos_session_kernel_count(void);
+mos_status mos_session_kernel_times(const mos_session* s, int32_t i, const char** name, double* ms,
+                                    int64_t* launches);
+void mos_session_destroy(mos_session* s);
 
 const char* mos_status_string(mos_status s);
 const char* mos_last_error(void);

@@ -258,6 +258,7 @@ struct Search {
         double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         if (time_limit > 0 && el > time_limit) {
           R.status = ORACLE_TIME_LIMIT;
+          R.search_seconds = el;  // counters so far describe the searched prefix
           return;
         }
       }

@@ -41,13 +41,14 @@ class mos_options(ctypes.Structure):
                 ("batch_width", ctypes.c_int32), ("max_slots", ctypes.c_int32),
                 ("label_limit", ctypes.c_int64), ("mem_budget", ctypes.c_int64),
                 ("stream", ctypes.c_void_p), ("costs_only", ctypes.c_int32),
-                ("steps_per_poll", ctypes.c_int32)]
+                ("steps_per_poll", ctypes.c_int32), ("profile_kernels", ctypes.c_int32)]
 
 
 class mos_stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in
                 ("pops", "goal_pops", "candidates", "p_pairs", "group_pairs", "frontier_pairs",
-                 "inserted", "pruned", "steps", "front", "frontier_bytes")] + \
+                 "inserted", "pruned", "steps", "front", "frontier_bytes", "killed",
+                 "frontier_bytes_onepass")] + \
                [("search_ms", ctypes.c_double), ("heuristic_ms", ctypes.c_double)]
 
 
@@ -83,6 +84,16 @@ _SIGS = {
     "mos_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "mos_last_error": (ctypes.c_char_p, []),
     "mos_heuristic": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32, _i32p]),
+    "mos_session_create": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32,
+                                          ctypes.POINTER(mos_options), ctypes.POINTER(_vp)]),
+    "mos_session_step": (ctypes.c_int, [_vp, ctypes.c_int64, _i32p]),
+    "mos_session_stats": (ctypes.c_int, [_vp, ctypes.POINTER(mos_stats)]),
+    "mos_session_result": (ctypes.c_int, [_vp, ctypes.POINTER(_vp)]),
+    "mos_session_kernel_count": (ctypes.c_int32, []),
+    "mos_session_kernel_times": (ctypes.c_int, [_vp, ctypes.c_int32,
+                                                ctypes.POINTER(ctypes.c_char_p),
+                                                ctypes.POINTER(ctypes.c_double), _i64p]),
+    "mos_session_destroy": (None, [_vp]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -203,7 +214,8 @@ def _stream_ptr(stream):
 
 
 def make_options(n_objectives=0, batch_width=0, max_slots=0, label_limit=0, mem_budget=0,
-                 stream=None, costs_only=False, steps_per_poll=0) -> mos_options:
+                 stream=None, costs_only=False, steps_per_poll=0,
+                 profile_kernels=False) -> mos_options:
     o = mos_options()
     o.struct_size = ctypes.sizeof(mos_options)
     o.n_objectives = int(n_objectives)
@@ -214,6 +226,7 @@ def make_options(n_objectives=0, batch_width=0, max_slots=0, label_limit=0, mem_
     o.stream = _stream_ptr(stream)
     o.costs_only = 1 if costs_only else 0
     o.steps_per_poll = int(steps_per_poll)
+    o.profile_kernels = 1 if profile_kernels else 0
     return o
 
 
@@ -252,6 +265,56 @@ def mos_heuristic(graph: Graph, goal: int, n_objectives: int = 0) -> np.ndarray:
     _check(_lib.mos_heuristic(graph.handle, int(goal), int(n_objectives), _p(h, ctypes.c_int32)),
            "mos_heuristic")
     return h
+
+
+# ------------------------------------------------------------------- session
+class Session:
+    """One query stepped on demand (``mos_session_*``)."""
+
+    def __init__(self, graph: Graph, start: int, goal: int, **opts):
+        self.graph = graph
+        o = make_options(**opts)
+        h = _vp()
+        _check(_lib.mos_session_create(graph.handle, int(start), int(goal), ctypes.byref(o),
+                                       ctypes.byref(h)), "mos_session_create")
+        self._h = h
+
+    def step(self, nsteps: int) -> bool:
+        done = ctypes.c_int32()
+        _check(_lib.mos_session_step(self._h, int(nsteps), ctypes.byref(done)), "mos_session_step")
+        return bool(done.value)
+
+    def stats(self) -> dict:
+        s = mos_stats()
+        _check(_lib.mos_session_stats(self._h, ctypes.byref(s)), "mos_session_stats")
+        return {f: getattr(s, f) for f, _ in mos_stats._fields_}
+
+    def result(self) -> Result:
+        h = _vp()
+        _check(_lib.mos_session_result(self._h, ctypes.byref(h)), "mos_session_result")
+        return _take_result(h)
+
+    def kernel_times(self) -> dict:
+        out = {}
+        name = ctypes.c_char_p()
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        for i in range(_lib.mos_session_kernel_count()):
+            _check(_lib.mos_session_kernel_times(self._h, i, ctypes.byref(name), ctypes.byref(ms),
+                                                 ctypes.byref(n)), "mos_session_kernel_times")
+            out[name.value.decode()] = (ms.value, n.value)
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.mos_session_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # -------------------------------------------------------------------- server

@@ -16,6 +16,8 @@
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -131,10 +133,31 @@ static int ensure_device() {
 }
 
 // ------------------------------------------------------------------ graph
+class Engine;
+
+// Engines are cached per graph and reused by later solves with the same
+// configuration (arena, slot table and captured step graph stay allocated).
+struct EngineKey {
+  int S;
+  int dm;
+  int64_t budget;
+  void* stream;
+  int B;
+  int64_t label_limit;
+  bool paths;
+  int steps;
+  bool operator==(const EngineKey& o) const {
+    return S == o.S && dm == o.dm && budget == o.budget && stream == o.stream && B == o.B &&
+           label_limit == o.label_limit && paths == o.paths && steps == o.steps;
+  }
+};
+
 struct mos_graph {
   int32_t n = 0, D = 0, maxdeg = 0, device = 0;
   int64_t m = 0;
   DevBuf row_ptr, col, cost, rrow, rsrc, rarc;
+  std::mutex pool_mu;
+  std::vector<std::pair<EngineKey, Engine*>> pool;  // idle engines, oldest first
   GraphDev view() const {
     GraphDev g;
     g.n = n;
@@ -218,9 +241,8 @@ static inline int64_t al(int64_t x) { return (x + 255) & ~int64_t(255); }
 static int64_t fixed_bytes(int64_t n, int d, int batch_cap, int cand_cap, int tie_cap) {
   int64_t b = 0;
   b += al(4 * d * n) + al(16 * n) + 2 * al(4 * n);                   // h, node, grp
-  b += 3 * al(4 * (int64_t)batch_cap) + al(4 * ((int64_t)batch_cap + 1));  // batch, reg, goal, reg_off
-  b += 2 * al(4 * (int64_t)tie_cap);                                 // tie
-  b += 10 * al(4 * (int64_t)cand_cap) + al(4 * (int64_t)d * cand_cap) + al(8 * (int64_t)cand_cap);
+  b += 4 * al(4 * (int64_t)batch_cap) + al(4 * ((int64_t)batch_cap + 1));  // batch, reg, goal, kill, reg_off
+  b += 13 * al(4 * ((int64_t)cand_cap + 1)) + al(4 * (int64_t)d * cand_cap) + al(8 * (int64_t)cand_cap);
   return b + 64 * 256;
 }
 
@@ -233,22 +255,24 @@ static bool plan_layout(const mos_graph* g, int d, int B, int64_t budget, int64_
   L->batch_cap = std::min(2 * B, BATCH_SORT);
   L->cand_cap = L->batch_cap * std::max(1, g->maxdeg);
   L->tie_cap = TIECAP;
-  const int64_t fixed = fixed_bytes(g->n, d, L->batch_cap, L->cand_cap, L->tie_cap);
+  const int64_t fixed = fixed_bytes(g->n, d, L->batch_cap, L->cand_cap, 0);
   if (budget <= fixed) return false;
   // bytes per pooled label: pool (node, parent, arc, g, state) + OPEN 2x(F1,
-  // lab) + frontier 3*(d+1) words + goal front share 2*(d+1) words / 8 + scratch
-  const double per = (12.0 + 4.0 * d + 1.0) + 16.0 + 12.0 * (d + 1) + (8.0 * (d + 1) + 8.0) / 8.0;
+  // lab) + tie set (F1, lab, state) + frontier 3*(d+1) words + goal front share
+  const double per = (12.0 + 4.0 * d + 1.0) + 16.0 + 12.0 + 12.0 * (d + 1) + (8.0 * (d + 1) + 8.0) / 8.0;
   int64_t pool = (int64_t)((double)(budget - fixed - 32 * 256) / per);
   pool = std::min<int64_t>(pool, (int64_t)1 << 30);
   if (label_limit > 0) pool = std::min<int64_t>(pool, label_limit);
   if (pool < 16) return false;
   L->pool_cap = (int32_t)pool;
   L->open_cap = (int32_t)pool;
+  L->tie_cap = (int32_t)pool;
   L->P_cap = (int32_t)std::max<int64_t>(std::min<int64_t>(pool, 1024), pool / 8);
   L->fw_cap = 3 * (int64_t)(d + 1) * pool + (int64_t)MINCAP * (d + 1);
   int64_t b = fixed;
   b += 3 * al(4 * pool) + al(4 * (int64_t)d * pool) + al(pool);  // pool
   b += 4 * al(4 * pool);                                          // OPEN
+  b += 3 * al(4 * pool);                                          // tie set
   b += 2 * (al(4 * (int64_t)d * L->P_cap) + al(4 * (int64_t)L->P_cap)) + al(8 * ((int64_t)L->P_cap + 1));
   b += al(4 * L->fw_cap);
   L->bytes = al(b);
@@ -271,8 +295,7 @@ static void carve(Slot& s, char* base, const Layout& L, int64_t n, int d) {
   s.reg = (int32_t*)take(4 * (int64_t)L.batch_cap);
   s.goal_lab = (int32_t*)take(4 * (int64_t)L.batch_cap);
   s.reg_off = (int32_t*)take(4 * ((int64_t)L.batch_cap + 1));
-  s.tie_f1 = (int32_t*)take(4 * (int64_t)L.tie_cap);
-  s.tie_lab = (int32_t*)take(4 * (int64_t)L.tie_cap);
+  s.reg_kill = (int32_t*)take(4 * (int64_t)L.batch_cap);
   const int64_t cc = L.cand_cap;
   s.c_node = (int32_t*)take(4 * cc);
   s.c_par = (int32_t*)take(4 * cc);
@@ -284,6 +307,9 @@ static void carve(Slot& s, char* base, const Layout& L, int64_t n, int d) {
   s.order = (int32_t*)take(4 * cc);
   s.grp_node = (int32_t*)take(4 * cc);
   s.grp_off = (int32_t*)take(4 * cc);
+  s.small_list = (int32_t*)take(4 * (cc + 1));
+  s.big_list = (int32_t*)take(4 * (cc + 1));
+  s.big_toff = (int32_t*)take(4 * (cc + 1));
   s.c_g = (int32_t*)take(4 * (int64_t)d * cc);
   s.c_fslot = (int64_t*)take(8 * cc);
   const int64_t pc = L.pool_cap;
@@ -296,6 +322,9 @@ static void carve(Slot& s, char* base, const Layout& L, int64_t n, int d) {
     s.open_f1[b] = (int32_t*)take(4 * (int64_t)L.open_cap);
     s.open_lab[b] = (int32_t*)take(4 * (int64_t)L.open_cap);
   }
+  s.tie_f1 = (int32_t*)take(4 * (int64_t)L.tie_cap);
+  s.tie_lab = (int32_t*)take(4 * (int64_t)L.tie_cap);
+  s.tie_st = (int32_t*)take(4 * (int64_t)L.tie_cap);
   for (int b = 0; b < 2; ++b) {
     s.Pg[b] = (int32_t*)take(4 * (int64_t)d * L.P_cap);
     s.Plab[b] = (int32_t*)take(4 * (int64_t)L.P_cap);
@@ -331,9 +360,9 @@ struct SlotHost {
 
 class Engine {
  public:
-  Engine(const mos_graph* g, int nslots, int64_t budget, hipStream_t user_stream, int B,
+  Engine(const mos_graph* g, int nslots, int dm, int64_t budget, hipStream_t user_stream, int B,
          int64_t label_limit, bool want_paths, int steps_per_poll)
-      : g_(g), S_(nslots), B_(B), label_limit_(label_limit), want_paths_(want_paths),
+      : g_(g), S_(nslots), DM_(dm), B_(B), label_limit_(label_limit), want_paths_(want_paths),
         K_(steps_per_poll) {
     HIPCHK(hipSetDevice(g->device));
     if (user_stream) {
@@ -356,9 +385,20 @@ class Engine {
     HIPCHK(hipEventCreate(&ev0_));
     HIPCHK(hipEventCreate(&ev1_));
     HIPCHK(hipStreamSynchronize(st_));
+    // MOS_HIPGRAPH=0 launches the step kernels one by one instead of replaying
+    // a captured graph (same kernels, same order).
+    const char* e = std::getenv("MOS_HIPGRAPH");
+    use_graph_ = !(e && e[0] == '0');
+    // MOS_PROGRESS=1 prints the state of resident queries every few seconds
+    // from the poll loop (long single solves otherwise run silently).
+    const char* pr = std::getenv("MOS_PROGRESS");
+    progress_ = pr && pr[0] == '1';
+    t_last_ = std::chrono::steady_clock::now();
   }
 
   ~Engine() {
+    hipStreamSynchronize(st_);
+    for (auto& e : pev_) hipEventDestroy(e);
     if (graph_exec_) hipGraphExecDestroy(graph_exec_);
     if (hslots_) hipHostFree(hslots_);
     hipEventDestroy(ev0_);
@@ -391,7 +431,17 @@ class Engine {
 
   // Admit, step, harvest.  Returns finished queries through `done`.
   void tick(std::deque<QueryReq>& pending, std::vector<Finished>& done) {
-    // ---- cancellations of resident queries
+    cancellations(done);
+    std::vector<int> fresh = admit(pending, done);
+    if (!fresh.empty()) run_heuristics(fresh);
+    if (busy_count() > 0) {
+      advance(K_);
+      collect(pending, done);
+    }
+  }
+
+  // Cancelled resident queries leave their slot at once.
+  void cancellations(std::vector<Finished>& done) {
     for (int s = 0; s < S_; ++s) {
       if (sh_[s].busy && sh_[s].cancel) {
         int32_t idle = S_IDLE;
@@ -402,7 +452,11 @@ class Engine {
         done.push_back({sh_[s].q.id, MOS_E_CANCELLED, nullptr, "cancelled"});
       }
     }
-    // ---- admission (first fit, in queue order)
+  }
+
+  // Admission, first fit in queue order: a query enters a free slot when its
+  // reservation fits into the arena; the head of the queue waits otherwise.
+  std::vector<int> admit(std::deque<QueryReq>& pending, std::vector<Finished>& done) {
     std::vector<int> fresh;
     while (!pending.empty()) {
       int free_slot = -1;
@@ -459,50 +513,122 @@ class Engine {
                             hipMemcpyHostToDevice, st_));
       fresh.push_back(free_slot);
     }
-    if (!fresh.empty()) run_heuristics(fresh);
-    // ---- steps
-    if (busy_count() > 0) {
-      HIPCHK(hipEventRecord(ev0_, st_));
-      run_steps();
-      HIPCHK(hipEventRecord(ev1_, st_));
-      HIPCHK(hipMemcpyAsync(hslots_, slots_.p, sizeof(Slot) * S_, hipMemcpyDeviceToHost, st_));
-      HIPCHK(hipStreamSynchronize(st_));
-      float ms = 0;
-      HIPCHK(hipEventElapsedTime(&ms, ev0_, ev1_));
-      for (int s = 0; s < S_; ++s)
-        if (sh_[s].busy) sh_[s].search_ms += ms;
-      for (int s = 0; s < S_; ++s) {
-        if (!sh_[s].busy) continue;
-        const Slot& d = hslots_[s];
-        if (d.status == S_RUN) continue;
-        if (d.status == S_DONE) {
-          Finished f{sh_[s].q.id, MOS_OK, nullptr, ""};
-          f.res = harvest(s);
-          release(s);
-          done.push_back(f);
+    return fresh;
+  }
+
+  // Run n label steps over every resident slot, then read the slot table back.
+  void advance(int64_t n) {
+    HIPCHK(hipEventRecord(ev0_, st_));
+    launch_steps(n);
+    HIPCHK(hipEventRecord(ev1_, st_));
+    HIPCHK(hipMemcpyAsync(hslots_, slots_.p, sizeof(Slot) * S_, hipMemcpyDeviceToHost, st_));
+    HIPCHK(hipStreamSynchronize(st_));
+    if (profile_) drain_profile();
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, ev0_, ev1_));
+    for (int s = 0; s < S_; ++s)
+      if (sh_[s].busy) sh_[s].search_ms += ms;
+    if (progress_) report_progress();
+  }
+
+  // Harvest finished slots; re-queue overflowed ones with a larger reservation.
+  void collect(std::deque<QueryReq>& pending, std::vector<Finished>& done) {
+    for (int s = 0; s < S_; ++s) {
+      if (!sh_[s].busy) continue;
+      const Slot& d = hslots_[s];
+      if (d.status == S_RUN) continue;
+      if (d.status == S_DONE) {
+        Finished f{sh_[s].q.id, MOS_OK, nullptr, ""};
+        f.res = harvest(s);
+        release(s);
+        done.push_back(f);
+      } else {
+        QueryReq q = sh_[s].q;
+        const Layout L = sh_[s].L;
+        release(s);
+        if ((label_limit_ > 0 && L.pool_cap >= label_limit_) || q.reserve >= arena_bytes()) {
+          done.push_back({q.id, MOS_E_LABEL_LIMIT, nullptr,
+                          "search state outgrew the label limit or memory budget"});
         } else {
-          QueryReq q = sh_[s].q;
-          const Layout L = sh_[s].L;
-          release(s);
-          if (d.status == S_TIE) {
-            done.push_back({q.id, MOS_E_DEVICE, nullptr,
-                            "a tie set exceeded the exact-selection capacity"});
-          } else if ((label_limit_ > 0 && L.pool_cap >= label_limit_) ||
-                     q.reserve >= arena_bytes()) {
-            done.push_back({q.id, MOS_E_LABEL_LIMIT, nullptr,
-                            "search state outgrew the label limit or memory budget"});
-          } else {
-            q.reserve = std::min<int64_t>(arena_bytes(), q.reserve * 4);
-            q.attempts++;
-            readmissions_++;
-            pending.push_front(q);
-          }
+          q.reserve = std::min<int64_t>(arena_bytes(), q.reserve * 4);
+          q.attempts++;
+          readmissions_++;
+          pending.push_front(q);
         }
       }
     }
   }
 
+  // ---- single-query sessions (stepped on demand)
+  mos_status session_admit(const QueryReq& q0, std::string* msg) {
+    std::deque<QueryReq> p{q0};
+    std::vector<Finished> d;
+    std::vector<int> fresh = admit(p, d);
+    if (!d.empty()) {
+      *msg = d[0].msg;
+      return d[0].st;
+    }
+    if (fresh.empty()) {
+      *msg = "query does not fit the arena";
+      return MOS_E_LABEL_LIMIT;
+    }
+    run_heuristics(fresh);
+    HIPCHK(hipMemcpyAsync(hslots_, slots_.p, sizeof(Slot) * S_, hipMemcpyDeviceToHost, st_));
+    HIPCHK(hipStreamSynchronize(st_));
+    return MOS_OK;
+  }
+  const Slot& slot0() const { return hslots_[0]; }
+  const SlotHost& host0() const { return sh_[0]; }
+  void set_profile(bool on) { profile_ = on; }
+  double kernel_ms(int i) const { return kms_[i]; }
+  int64_t kernel_launches(int i) const { return klaunch_[i]; }
+  mos_result* harvest_slot0() {
+    mos_result* r = harvest(0);
+    release(0);
+    return r;
+  }
+  mos_stats stats_of(int s) const {
+    const Slot& d = hslots_[s];
+    mos_stats o{};
+    o.pops = d.st[ST_POPS];
+    o.goal_pops = d.st[ST_GOAL_POPS];
+    o.candidates = d.st[ST_CANDS];
+    o.p_pairs = d.st[ST_PPAIRS];
+    o.group_pairs = d.st[ST_GPAIRS];
+    o.frontier_pairs = d.st[ST_FPAIRS];
+    o.inserted = d.st[ST_INSERTED];
+    o.pruned = d.st[ST_PRUNED];
+    o.steps = d.st[ST_STEPS];
+    o.front = d.P_n;
+    o.frontier_bytes = d.st[ST_FBYTES];
+    o.killed = d.st[ST_KILLED];
+    o.frontier_bytes_onepass = d.st[ST_FBYTES_WAVE];
+    o.search_ms = sh_[s].search_ms;
+    o.heuristic_ms = sh_[s].heur_ms;
+    return o;
+  }
+
   int64_t readmissions() const { return readmissions_; }
+
+  void report_progress() {
+    const auto now = std::chrono::steady_clock::now();
+    if (std::chrono::duration<double>(now - t_last_).count() < 5.0) return;
+    t_last_ = now;
+    int shown = 0;
+    for (int s = 0; s < S_ && shown < 4; ++s) {
+      if (!sh_[s].busy) continue;
+      const Slot& d = hslots_[s];
+      std::fprintf(stderr,
+                   "[mos] slot %d query %lld: steps %lld pops %lld labels %d open %d front %d "
+                   "frontier words %lld/%lld search %.0f ms\n",
+                   s, (long long)sh_[s].q.id, (long long)d.st[ST_STEPS], (long long)d.st[ST_POPS],
+                   d.n_labels, d.open_n, d.P_n, (long long)d.fw_top, (long long)d.fw_cap,
+                   sh_[s].search_ms);
+      ++shown;
+    }
+    std::fprintf(stderr, "[mos] resident %d\n", busy_count());
+    std::fflush(stderr);
+  }
 
   // Heuristic only: h planes of one goal (used by mos_heuristic).
   void heuristic_only(int32_t goal, int d, int32_t* out) {
@@ -574,20 +700,31 @@ class Engine {
     for (int s : fresh) sh_[s].heur_ms += ms;
   }
 
-  void run_steps() {
+  StepArgs step_args() const {
     StepArgs a;
     a.slots = slots_.as<Slot>();
     a.hist = hist_.as<int32_t>();
     a.G = g_->view();
     a.nslots = S_;
     a.gx = gx_;
-    if (!graph_exec_ && !graph_failed_) {
+    a.dm = DM_;
+    return a;
+  }
+
+  // K_ steps are captured once into a graph and replayed; the remainder (and
+  // everything in profile mode) is launched directly.
+  void launch_steps(int64_t n) {
+    const StepArgs a = step_args();
+    if (profile_) {
+      for (int64_t i = 0; i < n; ++i) profiled_step(a);
+      return;
+    }
+    if (use_graph_ && !graph_exec_ && !graph_failed_ && n >= K_) {
       hipGraph_t gr = nullptr;
       if (hipStreamBeginCapture(st_, hipStreamCaptureModeThreadLocal) == hipSuccess) {
         for (int k = 0; k < K_; ++k) launch_step(a, st_);
-        if (hipStreamEndCapture(st_, &gr) == hipSuccess && gr &&
-            hipGraphInstantiate(&graph_exec_, gr, nullptr, nullptr, 0) == hipSuccess) {
-        } else {
+        if (hipStreamEndCapture(st_, &gr) != hipSuccess || !gr ||
+            hipGraphInstantiate(&graph_exec_, gr, nullptr, nullptr, 0) != hipSuccess) {
           graph_exec_ = nullptr;
           graph_failed_ = true;
         }
@@ -598,11 +735,42 @@ class Engine {
       hipGetLastError();
     }
     if (graph_exec_) {
-      HIPCHK(hipGraphLaunch(graph_exec_, st_));
-    } else {
-      for (int k = 0; k < K_; ++k) launch_step(a, st_);
-      HIPCHK(hipGetLastError());
+      for (; n >= K_; n -= K_) HIPCHK(hipGraphLaunch(graph_exec_, st_));
     }
+    for (; n > 0; --n) launch_step(a, st_);
+    HIPCHK(hipGetLastError());
+  }
+
+  // Profile mode: every kernel of every step is bracketed by events; a ring of
+  // event sets is drained as it wraps and at every poll.
+  static constexpr int RING = 32;
+  void profiled_step(const StepArgs& a) {
+    constexpr int NE = kStepKernels + 1;
+    if (pev_.empty()) {
+      pev_.resize((size_t)RING * NE);
+      for (auto& e : pev_) HIPCHK(hipEventCreate(&e));
+    }
+    if (ring_used_ == RING) drain_one();
+    hipEvent_t* set = &pev_[(size_t)((ring_head_ + ring_used_) % RING) * NE];
+    launch_step(a, st_, set);
+    HIPCHK(hipGetLastError());
+    ++ring_used_;
+  }
+  void drain_one() {
+    constexpr int NE = kStepKernels + 1;
+    hipEvent_t* set = &pev_[(size_t)ring_head_ * NE];
+    HIPCHK(hipEventSynchronize(set[kStepKernels]));
+    for (int i = 0; i < kStepKernels; ++i) {
+      float ms = 0;
+      HIPCHK(hipEventElapsedTime(&ms, set[i], set[i + 1]));
+      kms_[i] += ms;
+      klaunch_[i]++;
+    }
+    ring_head_ = (ring_head_ + 1) % RING;
+    --ring_used_;
+  }
+  void drain_profile() {
+    while (ring_used_ > 0) drain_one();
   }
 
   mos_result* harvest(int s) {
@@ -645,25 +813,13 @@ class Engine {
     } else if (want_paths_) {
       r->path_off.assign(1, 0);
     }
-    mos_stats& o = r->stats;
-    o.pops = d.st[ST_POPS];
-    o.goal_pops = d.st[ST_GOAL_POPS];
-    o.candidates = d.st[ST_CANDS];
-    o.p_pairs = d.st[ST_PPAIRS];
-    o.group_pairs = d.st[ST_GPAIRS];
-    o.frontier_pairs = d.st[ST_FPAIRS];
-    o.inserted = d.st[ST_INSERTED];
-    o.pruned = d.st[ST_PRUNED];
-    o.steps = d.st[ST_STEPS];
-    o.front = np;
-    o.frontier_bytes = d.st[ST_FBYTES];
-    o.search_ms = sh_[s].search_ms;
-    o.heuristic_ms = sh_[s].heur_ms;
+    r->stats = stats_of(s);
+    r->stats.front = np;
     return r.release();
   }
 
   const mos_graph* g_;
-  int S_, B_;
+  int S_, DM_, B_;
   int64_t label_limit_;
   bool want_paths_;
   int K_;
@@ -677,12 +833,50 @@ class Engine {
   hipEvent_t ev0_ = nullptr, ev1_ = nullptr;
   hipGraphExec_t graph_exec_ = nullptr;
   bool graph_failed_ = false;
+  bool use_graph_ = true;
+  bool progress_ = false;
+  bool profile_ = false;
+  std::vector<hipEvent_t> pev_;
+  int ring_head_ = 0, ring_used_ = 0;
+  double kms_[kStepKernels] = {};
+  int64_t klaunch_[kStepKernels] = {};
+  std::chrono::steady_clock::time_point t_last_;
   int64_t readmissions_ = 0;
 };
 
+// ------------------------------------------------------------- engine cache
+static Engine* acquire_engine(const mos_graph* gc, const EngineKey& k, int64_t budget,
+                              hipStream_t stream) {
+  mos_graph* g = const_cast<mos_graph*>(gc);
+  {
+    std::lock_guard<std::mutex> lk(g->pool_mu);
+    for (size_t i = 0; i < g->pool.size(); ++i)
+      if (g->pool[i].first == k) {
+        Engine* e = g->pool[i].second;
+        g->pool.erase(g->pool.begin() + i);
+        return e;
+      }
+  }
+  return new Engine(g, k.S, k.dm, budget, stream, k.B, k.label_limit, k.paths, k.steps);
+}
+
+static void release_engine(const mos_graph* gc, const EngineKey& k, Engine* e) {
+  mos_graph* g = const_cast<mos_graph*>(gc);
+  Engine* evict = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g->pool_mu);
+    g->pool.emplace_back(k, e);
+    if (g->pool.size() > 2) {
+      evict = g->pool.front().second;
+      g->pool.erase(g->pool.begin());
+    }
+  }
+  delete evict;
+}
+
 // ------------------------------------------------------------ option helpers
 struct Opts {
-  int n_objectives = 0, B = 256, max_slots = 0, want_paths = 1, steps = 8;
+  int n_objectives = 0, B = 256, max_slots = 0, want_paths = 1, steps = 8, profile = 0;
   int64_t label_limit = 0, mem_budget = 0;
   hipStream_t stream = nullptr;
 };
@@ -699,7 +893,9 @@ static mos_status read_opts(const mos_options* o, Opts* out) {
     r.mem_budget = o->mem_budget;
     r.stream = (hipStream_t)o->stream;
     if (o->struct_size >= offsetof(mos_options, steps_per_poll)) r.want_paths = o->costs_only ? 0 : 1;
-    if (o->struct_size >= sizeof(mos_options) && o->steps_per_poll > 0) r.steps = o->steps_per_poll;
+    if (o->struct_size >= offsetof(mos_options, profile_kernels) && o->steps_per_poll > 0)
+      r.steps = o->steps_per_poll;
+    if (o->struct_size >= sizeof(mos_options)) r.profile = o->profile_kernels != 0;
   }
   if (r.B < 1 || r.B > BATCH_SORT / 2)
     return set_err(MOS_E_INVALID_ARG, "batch_width must lie in [1, 4096]");
@@ -822,7 +1018,12 @@ mos_status mos_graph_create(int32_t n, int64_t m, int32_t D, const int64_t* row_
   });
 }
 
-void mos_graph_destroy(mos_graph* g) { delete g; }
+void mos_graph_destroy(mos_graph* g) {
+  if (!g) return;
+  for (auto& kv : g->pool) delete kv.second;
+  g->pool.clear();
+  delete g;
+}
 
 static mos_status check_query(const mos_graph* g, int32_t s, int32_t t, int32_t nobj, int* d) {
   if (s < 0 || s >= g->n || t < 0 || t >= g->n)
@@ -850,8 +1051,12 @@ mos_status mos_solve_batch(const mos_graph* g, int32_t nq, const int32_t* starts
   return guarded([&]() -> mos_status {
     HIPCHK(hipSetDevice(g->device));
     const int S = o.max_slots > 0 ? std::min(o.max_slots, nq) : std::min(nq, 256);
-    Engine eng(g, S, default_budget(o.mem_budget), o.stream, o.B, o.label_limit, o.want_paths != 0,
-               o.steps);
+    const int dmax = *std::max_element(dq.begin(), dq.end());
+    const EngineKey key{S, dm_for(dmax), o.mem_budget, (void*)o.stream, o.B, o.label_limit,
+                        o.want_paths != 0, o.steps};
+    Engine* ep = acquire_engine(g, key, default_budget(o.mem_budget), o.stream);
+    std::unique_ptr<Engine> guard(ep);
+    Engine& eng = *ep;
     std::deque<QueryReq> pending;
     for (int32_t i = 0; i < nq; ++i) {
       QueryReq q;
@@ -883,6 +1088,7 @@ mos_status mos_solve_batch(const mos_graph* g, int32_t nq, const int32_t* starts
       if (pending.empty() && eng.busy_count() == 0 && left > 0)
         throw MosError(MOS_E_DEVICE, "engine stalled");
     }
+    release_engine(g, key, guard.release());
     if (first_bad != MOS_OK) return set_err(first_bad, msg);
     return MOS_OK;
   });
@@ -954,11 +1160,99 @@ mos_status mos_heuristic(const mos_graph* g, int32_t goal, int32_t n_objectives,
       }
       if (b > ((int64_t)1 << 40)) throw MosError(MOS_E_OUT_OF_MEMORY, "graph too large");
     }
-    Engine eng(g, 1, need, nullptr, 1, 16, false, 1);
+    Engine eng(g, 1, dm_for(d), need, nullptr, 1, 16, false, 1);
     eng.heuristic_only(goal, d, h);
     return MOS_OK;
   });
 }
+
+}  // extern "C"
+
+// ----------------------------------------------------------------- session
+struct mos_session {
+  const mos_graph* g = nullptr;
+  std::unique_ptr<Engine> eng;
+  bool finished = false;
+};
+
+extern "C" {
+
+mos_status mos_session_create(const mos_graph* g, int32_t start, int32_t goal,
+                              const mos_options* opt, mos_session** out) {
+  if (!g || !out) return set_err(MOS_E_INVALID_ARG, "NULL argument");
+  Opts o;
+  mos_status rs = read_opts(opt, &o);
+  if (rs != MOS_OK) return rs;
+  int d;
+  rs = check_query(g, start, goal, o.n_objectives, &d);
+  if (rs != MOS_OK) return rs;
+  return guarded([&]() -> mos_status {
+    HIPCHK(hipSetDevice(g->device));
+    std::unique_ptr<mos_session> s(new mos_session());
+    s->g = g;
+    s->eng.reset(new Engine(g, 1, dm_for(d), default_budget(o.mem_budget), o.stream, o.B,
+                            o.label_limit, o.want_paths != 0, o.steps));
+    s->eng->set_profile(o.profile != 0);
+    QueryReq q;
+    q.id = 0;
+    q.start = start;
+    q.goal = goal;
+    q.d = d;
+    q.reserve = s->eng->arena_bytes();
+    std::string msg;
+    mos_status st = s->eng->session_admit(q, &msg);
+    if (st != MOS_OK) return set_err(st, msg);
+    *out = s.release();
+    return MOS_OK;
+  });
+}
+
+mos_status mos_session_step(mos_session* s, int64_t nsteps, int32_t* done) {
+  if (!s || !done || nsteps < 0) return set_err(MOS_E_INVALID_ARG, "bad session step");
+  return guarded([&]() -> mos_status {
+    HIPCHK(hipSetDevice(s->g->device));
+    const int32_t st = s->eng->slot0().status;
+    if (st == S_RUN && nsteps > 0) s->eng->advance(nsteps);
+    const int32_t st2 = s->eng->slot0().status;
+    if (st2 == S_OVERFLOW) return set_err(MOS_E_LABEL_LIMIT, "search state outgrew the reservation");
+    *done = st2 == S_RUN ? 0 : 1;
+    return MOS_OK;
+  });
+}
+
+mos_status mos_session_stats(const mos_session* s, mos_stats* out) {
+  if (!s || !out) return set_err(MOS_E_INVALID_ARG, "NULL argument");
+  *out = s->eng->stats_of(0);
+  return MOS_OK;
+}
+
+mos_status mos_session_result(mos_session* s, mos_result** out) {
+  if (!s || !out) return set_err(MOS_E_INVALID_ARG, "NULL argument");
+  if (s->finished) return set_err(MOS_E_INVALID_ARG, "result already taken");
+  return guarded([&]() -> mos_status {
+    HIPCHK(hipSetDevice(s->g->device));
+    while (s->eng->slot0().status == S_RUN) s->eng->advance(64);
+    if (s->eng->slot0().status != S_DONE)
+      return set_err(MOS_E_LABEL_LIMIT, "search state outgrew the reservation");
+    *out = s->eng->harvest_slot0();
+    s->finished = true;
+    return MOS_OK;
+  });
+}
+
+int32_t mos_session_kernel_count(void) { return kStepKernels; }
+
+mos_status mos_session_kernel_times(const mos_session* s, int32_t i, const char** name, double* ms,
+                                    int64_t* launches) {
+  if (!s || i < 0 || i >= kStepKernels || !name || !ms || !launches)
+    return set_err(MOS_E_INVALID_ARG, "bad kernel index or NULL argument");
+  *name = kStepKernelNames[i];
+  *ms = s->eng->kernel_ms(i);
+  *launches = s->eng->kernel_launches(i);
+  return MOS_OK;
+}
+
+void mos_session_destroy(mos_session* s) { delete s; }
 
 }  // extern "C"
 
@@ -1052,7 +1346,7 @@ mos_status mos_server_create(const mos_graph* g, int64_t mem_budget, int32_t max
     std::unique_ptr<mos_server> s(new mos_server());
     s->g = g;
     const int S = max_slots > 0 ? max_slots : 64;
-    s->eng.reset(new Engine(g, S, default_budget(mem_budget), nullptr, 256, 0, true, 4));
+    s->eng.reset(new Engine(g, S, dm_for(g->D), default_budget(mem_budget), nullptr, 256, 0, true, 4));
     s->th = std::thread([p = s.get()] { p->loop(); });
     *out = s.release();
     return MOS_OK;

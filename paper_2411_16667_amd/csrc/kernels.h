@@ -13,10 +13,18 @@ struct StepArgs {
   GraphDev G;
   int nslots;
   int gx;  // workgroups per slot of the tiled kernels
+  int dm;  // compile-time bound on the objectives of every slot (2,3,4,5,6,8)
 };
 
-// One batched label step over every resident slot (13 kernel launches).
-void launch_step(const StepArgs& a, hipStream_t st);
+// Smallest supported compile-time objective bound >= d.
+int dm_for(int d);
+
+// One batched label step over every resident slot: a fixed sequence of
+// kStepKernels kernels.  With ev != nullptr, ev[i] is recorded before kernel i
+// and ev[kStepKernels] after the last one (kStepKernels + 1 events).
+constexpr int kStepKernels = 17;
+extern const char* const kStepKernelNames[kStepKernels];
+void launch_step(const StepArgs& a, hipStream_t st, hipEvent_t* ev = nullptr);
 
 void launch_heur_init(Slot* slots, const int32_t* slot_of, int njobs, const GraphDev& G,
                       int32_t* hs, int32_t* cnt, hipStream_t st);

@@ -15,18 +15,20 @@ namespace mos {
 
 constexpr int MAXD = 8;           // objectives supported by the kernels
 constexpr int NB = 4096;          // OPEN histogram bins: exact F1 values lo..lo+NB-2, then overflow
-constexpr int TIECAP = 1024;      // largest threshold-bin (tie) set ordered in LDS
+constexpr int TIECAP = 1024;      // tie sets up to this size are ordered in LDS; larger ones
+                                  // are first narrowed by exact radix refinement
 constexpr int MINCAP = 8;         // smallest frontier block, in entries
 constexpr int BATCH_SORT = 8192;  // largest popped batch (LDS sort by label id)
 constexpr int32_t UNREACH = INT32_MAX;  // heuristic of a node that cannot reach the goal
 constexpr int WAVE = 64;
+constexpr int64_t BIG_WORK = 64 * 1024;  // pair checks above which a group is split across waves
+constexpr int32_t PRUNED_BIT = (int32_t)0x80000000;  // marks a pruned entry in a label-id slot
 
 enum SlotStatus : int32_t {
   S_IDLE = 0,
   S_RUN = 1,
   S_DONE = 2,
   S_OVERFLOW = 3,  // a capacity of the reservation was exceeded
-  S_TIE = 4,       // a tie set too large to order exactly (not expected)
 };
 
 enum LabelState : uint8_t { L_OPEN = 0, L_CLOSED = 1, L_DEAD = 2 };
@@ -44,6 +46,8 @@ enum Stat {
   ST_STEPS,
   ST_FBYTES,
   ST_GROUPS,
+  ST_KILLED,
+  ST_FBYTES_WAVE,  // frontier bytes of the groups checked in one pass by one wave
   NSTAT = 16
 };
 
@@ -92,9 +96,11 @@ struct Slot {
   int32_t* batch;      // batch_cap: popped labels
   int32_t* reg;        // batch_cap: popped regular labels (ascending label id)
   int32_t* reg_off;    // batch_cap+1: exclusive prefix of their out-degrees
+  int32_t* reg_kill;   // batch_cap: popped regular label found dominated by the goal front
   int32_t* goal_lab;   // batch_cap: popped goal labels
-  int32_t* tie_f1;     // tie_cap
+  int32_t* tie_f1;     // tie_cap (= open_cap): entries of the threshold F1 bin
   int32_t* tie_lab;    // tie_cap
+  int32_t* tie_st;     // tie_cap: refinement state of each tie entry
   int32_t* c_node;     // cand_cap: candidate target node
   int32_t* c_par;      //   parent label
   int32_t* c_arc;      //   arc
@@ -107,16 +113,19 @@ struct Slot {
   int32_t* order;      // cand_cap: candidates grouped by node
   int32_t* grp_node;   // cand_cap: node of each group
   int32_t* grp_off;    // cand_cap: first position of each group in `order`
+  int32_t* small_list; // cand_cap: groups handled by one wave in one pass
+  int32_t* big_list;   // cand_cap: groups split into pair tiles across waves
+  int32_t* big_toff;   // cand_cap+1: exclusive prefix of the pair tiles of big groups
   int32_t* fw;         // frontier words
 
   // ---------------- dynamic (device-updated)
   int32_t n_labels, open_n, open_sel, P_n;
   int32_t P_sel, lo, lo_next, cur_min;
   int64_t fw_top;
-  int32_t t_star, r_tie, tie_mode, rebase;
+  int32_t t_star, r_tie, tie_mode, pad0;
   int32_t batch_n, goal_n, reg_n, cand_n;
   int32_t ngroups, tie_n, keep_n, accept_n;
-  int32_t err_line, pad1;
+  int32_t nsmall, nbig, big_tiles, err_line;
 
   int64_t st[NSTAT];
 };
@@ -132,6 +141,14 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+// Element i (0 or 1) of a two-entry member array, as a select: a runtime
+// index into a member array would force a local copy of the descriptor into
+// scratch memory.
+template <class T>
+__device__ __forceinline__ T pick(const T (&a)[2], int i) {
+  return i ? a[1] : a[0];
+}
 
 __device__ __forceinline__ int rank_below(uint64_t m) {
   return __popcll(m & ((1ull << lane_id()) - 1ull));

@@ -2,21 +2,25 @@
 //
 // A step follows the paper's Algorithm 1 body (NAMOA*), applied to a batch of
 // labels popped in lexicographic order as Algorithm 2 (OPMOS) does:
-//   pop     k_open_hist, k_open_threshold, k_open_scatter, k_batch_finalize
-//           (the B lexicographically smallest live OPEN labels; labels pruned
-//           since they were queued are skipped lazily, Section 5.1)
-//   goal    k_goal_merge   (Algorithm 1 lines 11-13: P <- minimal(P + goal labels))
-//   expand  k_expand       (lines 15-17: g' = g + c, F' = g' + h; lines 19/29:
-//                           drop F' that the goal front weakly dominates)
-//   group   k_group_count, k_group_offsets, k_group_scatter (candidates by target node)
-//   check   k_group_process (candidates of one node against each other and
-//           against the node's frontier: lines 22-28, fused in one read of the
-//           frontier, which is compacted and extended in the same pass)
-//   insert  k_accept_scan, k_insert, k_step_end (lines 20-21 / 30-31)
+//   pop      k_open_hist, k_open_threshold, k_open_scatter, k_batch_finalize:
+//            the B lexicographically smallest live OPEN labels (labels pruned
+//            since they were queued are skipped lazily, Section 5.1)
+//   goal     k_goal_merge: lines 11-13, P <- minimal(P + popped goal labels)
+//   prune    k_popcheck: lines 9-10 (PruneOPEN) applied to the popped labels
+//   expand   k_expand: lines 15-17, g' = g + c, F' = g' + h
+//   filter   k_pfilter: lines 19 / 29, drop F' that the goal front dominates
+//   group    k_group_count, k_group_offsets, k_group_scatter: candidates by node
+//   check    k_group_process (one wave per group, one streamed pass over the
+//            node's frontier) or k_group_pairs + k_group_finish (large groups
+//            split into pair tiles): lines 22-28 plus dominance among the
+//            candidates of the same step
+//   insert   k_accept_scan, k_insert, k_step_end: lines 20-21 / 30-31
 //
 // All arithmetic is exact int32.  Tiled kernels run on a (gx, slots) grid and
 // grid-stride over the slot's items; per-slot kernels run one 1024-thread
-// workgroup per slot.
+// workgroup per slot.  Each kernel copies its slot descriptor once (scalar
+// registers); writes to descriptor fields go through the pointer.  Objective
+// loops are unrolled to the engine's compile-time bound DM (d <= DM).
 #include "kernels.h"
 
 namespace mos {
@@ -24,6 +28,9 @@ namespace mos {
 constexpr int NT_SLOT = 1024;  // threads of the one-workgroup-per-slot kernels
 constexpr int NT_TILE = 256;   // threads of the tiled kernels
 constexpr int GP_WAVES = NT_TILE / WAVE;
+constexpr int PCH = 256;       // goal-front entries per LDS chunk
+
+#define FOR_K(k) _Pragma("unroll") for (int k = 0; k < DM; ++k) if (k < d)
 
 // Exclusive scan of one value per thread across a workgroup of NT threads.
 template <int NT>
@@ -54,46 +61,25 @@ __device__ int block_exscan(int v, int* total, int* tmp /* >= NT/64 ints */) {
   return before + x - v;
 }
 
-// Exclusive scan of flags[0..n) into out[0..n) by one workgroup; returns the total.
-template <int NT>
-__device__ int block_scan_array(const int32_t* in, int32_t* out, int n, int* tmp) {
-  int carry = 0;
-  for (int base = 0; base < n; base += NT) {
-    int i = base + threadIdx.x;
-    int v = i < n ? in[i] : 0;
-    int tot;
-    int ex = block_exscan<NT>(v, &tot, tmp);
-    if (i < n) out[i] = carry + ex;
-    carry += tot;
-  }
-  return carry;
-}
-
 // ---------------------------------------------------------------- pop
 // Histogram of live OPEN entries over F1 (bin = F1 - lo, width 1, last bin = overflow).
 __global__ __launch_bounds__(NT_TILE) void k_open_hist(Slot* slots, int32_t* hist) {
-  Slot* S = &slots[blockIdx.y];
-  if (S->status != S_RUN) return;
-  const int n = S->open_n;
+  const Slot S = slots[blockIdx.y];
+  if (S.status != S_RUN) return;
+  const int n = S.open_n;
   if ((int)(blockIdx.x * NT_TILE) >= n) return;
   __shared__ int32_t h[NB];
   for (int i = threadIdx.x; i < NB; i += NT_TILE) h[i] = 0;
   __syncthreads();
-  const int sel = S->open_sel, lo = S->lo;
-  const int32_t* F1 = S->open_f1[sel];
-  const int32_t* LB = S->open_lab[sel];
-  const uint8_t* st = S->Lstate;
-  int mn = INT32_MAX;
+  const int32_t* F1 = pick(S.open_f1, S.open_sel);
+  const int32_t* LB = pick(S.open_lab, S.open_sel);
+  const int lo = S.lo;
   for (int i = blockIdx.x * NT_TILE + threadIdx.x; i < n; i += gridDim.x * NT_TILE) {
-    if (st[LB[i]] == L_OPEN) {
-      int f = F1[i];
-      int b = min(max(f - lo, 0), NB - 1);
+    if (S.Lstate[LB[i]] == L_OPEN) {
+      const int b = min(max(F1[i] - lo, 0), NB - 1);
       atomicAdd(&h[b], 1);
-      mn = min(mn, f);
     }
   }
-  mn = wave_min(mn);
-  if (lane_id() == 0 && mn != INT32_MAX) atomicMin(&S->cur_min, mn);
   __syncthreads();
   int32_t* gh = hist + (size_t)blockIdx.y * NB;
   for (int i = threadIdx.x; i < NB; i += NT_TILE)
@@ -101,21 +87,24 @@ __global__ __launch_bounds__(NT_TILE) void k_open_hist(Slot* slots, int32_t* his
 }
 
 // Pick the threshold bin: bins below t_star are popped whole; r_tie entries of
-// bin t_star are taken in exact lexicographic order (tie_mode).
+// bin t_star are then selected exactly by k_batch_finalize (tie_mode).
 __global__ __launch_bounds__(NT_SLOT) void k_open_threshold(Slot* slots, int32_t* hist) {
-  Slot* S = &slots[blockIdx.x];
-  if (S->status != S_RUN) return;
+  Slot* Sp = &slots[blockIdx.x];
+  if (Sp->status != S_RUN) return;
+  const int B = Sp->B;
   __shared__ int32_t cum[NB];
   __shared__ int tmp[NT_SLOT / WAVE];
   int32_t* gh = hist + (size_t)blockIdx.x * NB;
   constexpr int PER = NB / NT_SLOT;
   int loc[PER], s = 0;
+#pragma unroll
   for (int j = 0; j < PER; ++j) {
     loc[j] = gh[threadIdx.x * PER + j];
     s += loc[j];
   }
   int total;
   int ex = block_exscan<NT_SLOT>(s, &total, tmp);
+#pragma unroll
   for (int j = 0; j < PER; ++j) {
     ex += loc[j];
     cum[threadIdx.x * PER + j] = ex;  // inclusive
@@ -123,57 +112,47 @@ __global__ __launch_bounds__(NT_SLOT) void k_open_threshold(Slot* slots, int32_t
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    const int B = S->B;
-    int t_star = NB, r = 0, mode = 0, rebase = 0;
+    int t_star = NB, r = 0, mode = 0;
     if (total > B) {
       int lo_i = 0, hi_i = NB - 1;  // first bin with cum >= B
       while (lo_i < hi_i) {
-        int mid = (lo_i + hi_i) >> 1;
+        const int mid = (lo_i + hi_i) >> 1;
         if (cum[mid] >= B) hi_i = mid; else lo_i = mid + 1;
       }
-      int t = lo_i;
-      int below = t > 0 ? cum[t - 1] : 0;
-      int inbin = cum[t] - below;
+      const int t = lo_i;
+      const int below = t > 0 ? cum[t - 1] : 0;
+      const int inbin = cum[t] - below;
       r = B - below;
       if (r == inbin) {
-        t_star = t + 1; r = 0;
-      } else if (inbin <= TIECAP && inbin <= S->tie_cap) {
-        t_star = t; mode = 1;
-      } else if (below > 0) {
-        t_star = t; r = 0;  // pop the bins below only: still an exact lexicographic prefix
-      } else if (t < NB - 1 && inbin <= S->batch_cap) {
-        t_star = t + 1; r = 0;  // the whole lowest F1 value: an exact prefix, larger than B
-      } else if (t == NB - 1) {
-        t_star = 0; r = 0; rebase = 1;  // every live entry lies far above lo: re-anchor, pop nothing
+        t_star = t + 1;  // the threshold bin is popped whole
+        r = 0;
       } else {
-        S->status = S_TIE;
-        S->err_line = __LINE__;
+        t_star = t;  // r of its entries are selected exactly in k_batch_finalize
+        mode = 1;
       }
     }
-    S->t_star = t_star;
-    S->r_tie = r;
-    S->tie_mode = mode;
-    S->rebase = rebase;
-    S->batch_n = 0;
-    S->tie_n = 0;
-    S->keep_n = 0;
-    S->lo_next = INT32_MAX;
+    Sp->t_star = t_star;
+    Sp->r_tie = r;
+    Sp->tie_mode = mode;
+    Sp->batch_n = 0;
+    Sp->tie_n = 0;
+    Sp->keep_n = 0;
+    Sp->lo_next = INT32_MAX;
   }
 }
 
 // Route every live OPEN entry: popped (bin < t_star), tie (bin == t_star in
 // tie mode) or kept (into the other OPEN buffer).  Dead entries vanish here.
 __global__ __launch_bounds__(NT_TILE) void k_open_scatter(Slot* slots) {
-  Slot* S = &slots[blockIdx.y];
-  if (S->status != S_RUN) return;
-  const int n = S->open_n;
-  const int sel = S->open_sel, lo = S->lo, t_star = S->t_star, mode = S->tie_mode;
-  const int32_t* F1 = S->open_f1[sel];
-  const int32_t* LB = S->open_lab[sel];
-  int32_t* KF = S->open_f1[sel ^ 1];
-  int32_t* KL = S->open_lab[sel ^ 1];
-  const uint8_t* st = S->Lstate;
-  const int bcap = S->batch_cap, tcap = S->tie_cap, ocap = S->open_cap;
+  Slot* Sp = &slots[blockIdx.y];
+  const Slot S = *Sp;
+  if (S.status != S_RUN) return;
+  const int n = S.open_n;
+  const int sel = S.open_sel, lo = S.lo, t_star = S.t_star, mode = S.tie_mode;
+  const int32_t* F1 = pick(S.open_f1, sel);
+  const int32_t* LB = pick(S.open_lab, sel);
+  int32_t* KF = pick(S.open_f1, sel ^ 1);
+  int32_t* KL = pick(S.open_lab, sel ^ 1);
   const int stride = gridDim.x * NT_TILE;
   int kmin = INT32_MAX;
   for (int base = blockIdx.x * NT_TILE; base < n; base += stride) {
@@ -184,138 +163,229 @@ __global__ __launch_bounds__(NT_TILE) void k_open_scatter(Slot* slots) {
     if (valid) {
       lab = LB[i];
       f = F1[i];
-      live = st[lab] == L_OPEN;
+      live = S.Lstate[lab] == L_OPEN;
     }
     const int b = min(max(f - lo, 0), NB - 1);
     const bool to_batch = live && b < t_star;
     const bool to_tie = live && mode && b == t_star;
     const bool to_keep = live && !to_batch && !to_tie;
-    int p = agg_append(&S->batch_n, to_batch);
-    if (to_batch && p < bcap) S->batch[p] = lab;
-    p = agg_append(&S->tie_n, to_tie);
-    if (to_tie && p < tcap) {
-      S->tie_f1[p] = f;
-      S->tie_lab[p] = lab;
+    int p = agg_append(&Sp->batch_n, to_batch);
+    if (to_batch && p < S.batch_cap) S.batch[p] = lab;
+    p = agg_append(&Sp->tie_n, to_tie);
+    if (to_tie && p < S.tie_cap) {
+      S.tie_f1[p] = f;
+      S.tie_lab[p] = lab;
     }
-    p = agg_append(&S->keep_n, to_keep);
-    if (to_keep && p < ocap) {
+    p = agg_append(&Sp->keep_n, to_keep);
+    if (to_keep && p < S.open_cap) {
       KF[p] = f;
       KL[p] = lab;
       kmin = min(kmin, f);
     }
   }
   kmin = wave_min(kmin);
-  if (lane_id() == 0 && kmin != INT32_MAX) atomicMin(&S->lo_next, kmin);
+  if (lane_id() == 0 && kmin != INT32_MAX) atomicMin(&Sp->lo_next, kmin);
 }
 
-// Lexicographic key of a label: F_1..F_d, then node.
-__device__ __forceinline__ void label_key(const Slot* S, const GraphDev& G, int lab, int32_t* key) {
-  const int d = S->d;
-  const int v = S->Lnode[lab];
-  const int pc = S->pool_cap;
-  for (int k = 0; k < d; ++k) key[k] = S->Lg[(size_t)k * pc + lab] + S->h[(size_t)k * G.n + v];
-  key[d] = v;
+// Word w of the lexicographic key of a label: F_{w+1} for w < d, the node for w = d.
+__device__ __forceinline__ int key_word(const Slot& S, const GraphDev& G, int lab, int w) {
+  const int v = S.Lnode[lab];
+  if (w >= S.d) return v;
+  return S.Lg[(size_t)w * S.pool_cap + lab] + S.h[(size_t)w * G.n + v];
 }
 
 // Finish the pop: exact selection inside the tie bin, canonical batch order
 // (ascending label id), goal/regular split, out-degree prefix of the regular labels.
+template <int DM>
 __global__ __launch_bounds__(NT_SLOT) void k_batch_finalize(Slot* slots, GraphDev G) {
-  Slot* S = &slots[blockIdx.x];
-  if (S->status != S_RUN) return;
+  Slot* Sp = &slots[blockIdx.x];
+  const Slot S = *Sp;
+  if (S.status != S_RUN) return;
   __shared__ int32_t lds[10240];
   __shared__ int tmp[NT_SLOT / WAVE];
-  __shared__ int sh_base;
-  const int d = S->d;
-  if (S->tie_mode) {
-    // ---- tie bin: order by (F_1..F_d, node), take the first r_tie
-    const int n = min(S->tie_n, TIECAP);
-    int n2 = 1;
-    while (n2 < n) n2 <<= 1;
-    int32_t* K = lds;               // (d+1) planes of TIECAP
-    int32_t* idx = lds + 9 * TIECAP;
-    for (int i = threadIdx.x; i < n2; i += NT_SLOT) {
-      int32_t key[MAXD + 1];
-      if (i < n) {
-        label_key(S, G, S->tie_lab[i], key);
-      } else {
-        for (int k = 0; k <= d; ++k) key[k] = INT32_MAX;
-      }
-      for (int k = 0; k <= d; ++k) K[k * TIECAP + i] = key[k];
-      idx[i] = i;
-    }
+  __shared__ int sh_a, sh_b;
+  const int d = S.d;
+  int nb = S.batch_n, keep_n = S.keep_n;
+  if (S.tie_mode) {
+    // ---- threshold bin: take exactly the r_tie lexicographically smallest of
+    // its entries by (F_1..F_d, node).  While more than TIECAP remain
+    // undecided, one radix level on the current key word decides every entry
+    // outside the bin that holds the r-th smallest; the last <= TIECAP entries
+    // are ordered in LDS.  (F, node) is unique among live labels, so this ends.
+    const int n = min(S.tie_n, S.tie_cap);
+    int need = S.r_tie;
+    int32_t* TS = S.tie_st;  // 0 undecided, 1 taken, 2 not taken
+    for (int i = threadIdx.x; i < n; i += NT_SLOT) TS[i] = 0;
     __syncthreads();
-    for (int kk = 2; kk <= n2; kk <<= 1) {
-      for (int j = kk >> 1; j > 0; j >>= 1) {
-        for (int i = threadIdx.x; i < n2; i += NT_SLOT) {
-          int ixj = i ^ j;
-          if (ixj > i) {
-            int a = idx[i], b = idx[ixj];
-            // lexicographic less(b, a)
-            int c = 0;
-            for (int k = 0; k <= d && c == 0; ++k) {
-              int ka = K[k * TIECAP + a], kb = K[k * TIECAP + b];
-              c = (kb < ka) ? 1 : (kb > ka ? -1 : 0);
-            }
-            bool b_less = c == 1;
-            bool asc = (i & kk) == 0;
-            if (asc ? b_less : (c == -1)) {
-              idx[i] = b;
-              idx[ixj] = a;
+    int und = n, word = 0;
+    int32_t* hist = lds;  // NB ints
+    while (und > TIECAP && need > 0 && need < und) {
+      if (threadIdx.x == 0) sh_a = INT32_MAX;
+      __syncthreads();
+      int mn = INT32_MAX;
+      for (int i = threadIdx.x; i < n; i += NT_SLOT)
+        if (TS[i] == 0) mn = min(mn, key_word(S, G, S.tie_lab[i], word));
+      mn = wave_min(mn);
+      if (lane_id() == 0) atomicMin(&sh_a, mn);
+      for (int i = threadIdx.x; i < NB; i += NT_SLOT) hist[i] = 0;
+      __syncthreads();
+      const int m = sh_a;
+      for (int i = threadIdx.x; i < n; i += NT_SLOT)
+        if (TS[i] == 0) {
+          const int64_t b = (int64_t)key_word(S, G, S.tie_lab[i], word) - m;
+          atomicAdd(&hist[b < NB - 1 ? (int)b : NB - 1], 1);
+        }
+      __syncthreads();
+      constexpr int PER = NB / NT_SLOT;
+      int loc[PER], sum = 0;
+#pragma unroll
+      for (int j = 0; j < PER; ++j) {
+        loc[j] = hist[threadIdx.x * PER + j];
+        sum += loc[j];
+      }
+      int tot;
+      int ex = block_exscan<NT_SLOT>(sum, &tot, tmp);
+#pragma unroll
+      for (int j = 0; j < PER; ++j) {
+        ex += loc[j];
+        hist[threadIdx.x * PER + j] = ex;
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        int lo_i = 0, hi_i = NB - 1;
+        while (lo_i < hi_i) {
+          const int mid = (lo_i + hi_i) >> 1;
+          if (hist[mid] >= need) hi_i = mid; else lo_i = mid + 1;
+        }
+        sh_b = lo_i;
+      }
+      __syncthreads();
+      const int bstar = sh_b;
+      const int below = bstar > 0 ? hist[bstar - 1] : 0;
+      const int inb = hist[bstar] - below;
+      for (int i = threadIdx.x; i < n; i += NT_SLOT)
+        if (TS[i] == 0) {
+          const int64_t b64 = (int64_t)key_word(S, G, S.tie_lab[i], word) - m;
+          const int b = b64 < NB - 1 ? (int)b64 : NB - 1;
+          if (b < bstar) TS[i] = 1;
+          else if (b > bstar) TS[i] = 2;
+        }
+      need -= below;
+      und = inb;
+      if (bstar < NB - 1) ++word;  // the undecided now share this word's value
+      __syncthreads();
+    }
+    if (need == 0 || need >= und) {
+      const int fill = need == 0 ? 2 : 1;
+      for (int i = threadIdx.x; i < n; i += NT_SLOT)
+        if (TS[i] == 0) TS[i] = fill;
+      __syncthreads();
+    } else {
+      // compact the undecided (<= TIECAP) and sort them by full key in LDS
+      int32_t* K = lds;                          // (d+1) planes of TIECAP
+      int32_t* idx = lds + (MAXD + 1) * TIECAP;  // positions into the tie arrays
+      int cnt = 0;
+      for (int base = 0; base < n; base += NT_SLOT) {
+        const int i = base + threadIdx.x;
+        const int u = (i < n && TS[i] == 0) ? 1 : 0;
+        int tt;
+        const int p = block_exscan<NT_SLOT>(u, &tt, tmp);
+        if (u) idx[cnt + p] = i;
+        cnt += tt;
+      }
+      __syncthreads();
+      int n2 = 1;
+      while (n2 < cnt) n2 <<= 1;
+      for (int i = threadIdx.x; i < n2; i += NT_SLOT) {
+        if (i < cnt) {
+          const int lab = S.tie_lab[idx[i]];
+          const int v = S.Lnode[lab];
+          FOR_K(k) K[k * TIECAP + i] = S.Lg[(size_t)k * S.pool_cap + lab] + S.h[(size_t)k * G.n + v];
+          K[d * TIECAP + i] = v;
+        } else {
+          for (int k = 0; k <= d; ++k) K[k * TIECAP + i] = INT32_MAX;
+          idx[i] = -1;
+        }
+      }
+      __syncthreads();
+      for (int kk = 2; kk <= n2; kk <<= 1) {
+        for (int j = kk >> 1; j > 0; j >>= 1) {
+          for (int i = threadIdx.x; i < n2; i += NT_SLOT) {
+            const int ixj = i ^ j;
+            if (ixj > i) {
+              int c = 0;
+              for (int k = 0; k <= d && c == 0; ++k) {
+                const int ka = K[k * TIECAP + i], kb = K[k * TIECAP + ixj];
+                c = (kb < ka) ? 1 : (kb > ka ? -1 : 0);
+              }
+              const bool asc = (i & kk) == 0;
+              if (asc ? (c == 1) : (c == -1)) {
+                for (int k = 0; k <= d; ++k) {
+                  const int tk = K[k * TIECAP + i];
+                  K[k * TIECAP + i] = K[k * TIECAP + ixj];
+                  K[k * TIECAP + ixj] = tk;
+                }
+                const int ti = idx[i];
+                idx[i] = idx[ixj];
+                idx[ixj] = ti;
+              }
             }
           }
+          __syncthreads();
         }
-        __syncthreads();
       }
+      for (int i = threadIdx.x; i < cnt; i += NT_SLOT) TS[idx[i]] = (i < need) ? 1 : 2;
+      __syncthreads();
     }
-    const int r = S->r_tie;
-    const int nb0 = S->batch_n;
-    int32_t* KF = S->open_f1[S->open_sel ^ 1];
-    int32_t* KL = S->open_lab[S->open_sel ^ 1];
-    int kmin = INT32_MAX;
-    for (int i = threadIdx.x; i < n; i += NT_SLOT) {
-      int e = idx[i];
-      if (i < r) {
-        int p = nb0 + i;
-        if (p < S->batch_cap) S->batch[p] = S->tie_lab[e];
-      } else {
-        int p = S->keep_n + (i - r);
-        if (p < S->open_cap) {
-          KF[p] = S->tie_f1[e];
-          KL[p] = S->tie_lab[e];
-        }
-        kmin = min(kmin, S->tie_f1[e]);
+    // taken -> batch, not taken -> OPEN (other buffer)
+    int32_t* KF = pick(S.open_f1, S.open_sel ^ 1);
+    int32_t* KL = pick(S.open_lab, S.open_sel ^ 1);
+    int taken = 0, kept = 0, kmin = INT32_MAX;
+    for (int base = 0; base < n; base += NT_SLOT) {
+      const int i = base + threadIdx.x;
+      const int st = i < n ? TS[i] : 0;
+      int t1, t2;
+      const int p1 = block_exscan<NT_SLOT>(st == 1 ? 1 : 0, &t1, tmp);
+      const int p2 = block_exscan<NT_SLOT>(st == 2 ? 1 : 0, &t2, tmp);
+      if (st == 1 && nb + taken + p1 < S.batch_cap) S.batch[nb + taken + p1] = S.tie_lab[i];
+      if (st == 2 && keep_n + kept + p2 < S.open_cap) {
+        KF[keep_n + kept + p2] = S.tie_f1[i];
+        KL[keep_n + kept + p2] = S.tie_lab[i];
+        kmin = min(kmin, S.tie_f1[i]);
       }
+      taken += t1;
+      kept += t2;
     }
     kmin = wave_min(kmin);
-    if (lane_id() == 0 && kmin != INT32_MAX) atomicMin(&S->lo_next, kmin);
-    __syncthreads();
+    if (lane_id() == 0 && kmin != INT32_MAX) atomicMin(&Sp->lo_next, kmin);
+    nb += taken;
+    keep_n += kept;
     if (threadIdx.x == 0) {
-      S->batch_n = nb0 + min(r, n);
-      S->keep_n += max(n - r, 0);
+      Sp->batch_n = nb;
+      Sp->keep_n = keep_n;
     }
     __syncthreads();
   }
   // ---- canonical batch order: ascending label id
-  int nb = S->batch_n;
-  if (nb > S->batch_cap || nb > BATCH_SORT || S->keep_n > S->open_cap) {
+  if (nb > S.batch_cap || nb > BATCH_SORT || keep_n > S.open_cap) {
     if (threadIdx.x == 0) {
-      S->status = S_OVERFLOW;
-      S->err_line = __LINE__;
+      Sp->status = S_OVERFLOW;
+      Sp->err_line = __LINE__;
     }
     return;
   }
   int n2 = 1;
   while (n2 < nb) n2 <<= 1;
   int32_t* V = lds;
-  for (int i = threadIdx.x; i < n2; i += NT_SLOT) V[i] = i < nb ? S->batch[i] : INT32_MAX;
+  for (int i = threadIdx.x; i < n2; i += NT_SLOT) V[i] = i < nb ? S.batch[i] : INT32_MAX;
   __syncthreads();
   for (int kk = 2; kk <= n2; kk <<= 1) {
     for (int j = kk >> 1; j > 0; j >>= 1) {
       for (int i = threadIdx.x; i < n2; i += NT_SLOT) {
-        int ixj = i ^ j;
+        const int ixj = i ^ j;
         if (ixj > i) {
-          int a = V[i], b = V[ixj];
-          bool asc = (i & kk) == 0;
+          const int a = V[i], b = V[ixj];
+          const bool asc = (i & kk) == 0;
           if (asc ? (b < a) : (a < b)) {
             V[i] = b;
             V[ixj] = a;
@@ -326,44 +396,45 @@ __global__ __launch_bounds__(NT_SLOT) void k_batch_finalize(Slot* slots, GraphDe
     }
   }
   // ---- split into goal and regular labels (stable), mark them closed
-  const int goal = S->goal;
+  const int goal = S.goal;
   int goal_total = 0, reg_total = 0, deg_carry = 0;
   for (int base = 0; base < nb; base += NT_SLOT) {
-    int i = base + threadIdx.x;
-    bool valid = i < nb;
-    int lab = valid ? V[i] : 0;
-    int v = valid ? S->Lnode[lab] : 0;
-    bool isg = valid && v == goal;
-    bool isr = valid && !isg;
-    int deg = isr ? (G.row_ptr[v + 1] - G.row_ptr[v]) : 0;
-    if (valid) S->Lstate[lab] = L_CLOSED;
+    const int i = base + threadIdx.x;
+    const bool valid = i < nb;
+    const int lab = valid ? V[i] : 0;
+    const int v = valid ? S.Lnode[lab] : 0;
+    const bool isg = valid && v == goal;
+    const bool isr = valid && !isg;
+    const int deg = isr ? (G.row_ptr[v + 1] - G.row_ptr[v]) : 0;
+    if (valid) S.Lstate[lab] = L_CLOSED;
     int tg, tr, td;
-    int pg = block_exscan<NT_SLOT>(isg ? 1 : 0, &tg, tmp);
-    int pr = block_exscan<NT_SLOT>(isr ? 1 : 0, &tr, tmp);
-    int pd = block_exscan<NT_SLOT>(deg, &td, tmp);
-    if (isg) S->goal_lab[goal_total + pg] = lab;
+    const int pg = block_exscan<NT_SLOT>(isg ? 1 : 0, &tg, tmp);
+    const int pr = block_exscan<NT_SLOT>(isr ? 1 : 0, &tr, tmp);
+    const int pd = block_exscan<NT_SLOT>(deg, &td, tmp);
+    if (isg) S.goal_lab[goal_total + pg] = lab;
     if (isr) {
-      S->reg[reg_total + pr] = lab;
-      S->reg_off[reg_total + pr] = deg_carry + pd;
+      S.reg[reg_total + pr] = lab;
+      S.reg_off[reg_total + pr] = deg_carry + pd;
+      S.reg_kill[reg_total + pr] = 0;
     }
     goal_total += tg;
     reg_total += tr;
     deg_carry += td;
   }
   if (threadIdx.x == 0) {
-    S->reg_off[reg_total] = deg_carry;
-    S->goal_n = goal_total;
-    S->reg_n = reg_total;
-    S->cand_n = deg_carry;
-    S->ngroups = 0;
-    S->accept_n = 0;
-    S->st[ST_POPS] += nb;
-    S->st[ST_GOAL_POPS] += goal_total;
-    if (deg_carry > S->cand_cap) {
-      S->status = S_OVERFLOW;
-      S->err_line = __LINE__;
-    } else if (nb == 0 && !S->rebase) {
-      S->status = S_DONE;  // no live label left in OPEN
+    S.reg_off[reg_total] = deg_carry;
+    Sp->goal_n = goal_total;
+    Sp->reg_n = reg_total;
+    Sp->cand_n = deg_carry;
+    Sp->ngroups = 0;
+    Sp->accept_n = 0;
+    Sp->st[ST_POPS] += nb;
+    Sp->st[ST_GOAL_POPS] += goal_total;
+    if (deg_carry > S.cand_cap) {
+      Sp->status = S_OVERFLOW;
+      Sp->err_line = __LINE__;
+    } else if (nb == 0) {
+      Sp->status = S_DONE;  // no live label left in OPEN
     }
   }
 }
@@ -374,30 +445,44 @@ __global__ __launch_bounds__(NT_SLOT) void k_batch_finalize(Slot* slots, GraphDe
 // or another goal label dominates it (equal vectors: the smaller label id
 // stays); an old entry is dropped if some goal label strictly dominates it.
 // The new front is written lexicographically sorted into the other buffer.
+template <int DM>
+__device__ __forceinline__ bool lex_less(const int32_t* a, const int32_t* b, int d) {
+  bool decided = false, less = false;
+#pragma unroll
+  for (int k = 0; k < DM; ++k)
+    if (k < d && !decided && a[k] != b[k]) {
+      decided = true;
+      less = a[k] < b[k];
+    }
+  return less;
+}
+
+template <int DM>
 __global__ __launch_bounds__(NT_SLOT) void k_goal_merge(Slot* slots) {
-  Slot* S = &slots[blockIdx.x];
-  if (S->status != S_RUN || S->goal_n == 0) return;
+  Slot* Sp = &slots[blockIdx.x];
+  const Slot S = *Sp;
+  if (S.status != S_RUN || S.goal_n == 0) return;
   constexpr int GT = 256;  // goal labels per pass
-  __shared__ int32_t gv[MAXD][GT];
+  __shared__ int32_t gv[DM][GT];
   __shared__ int32_t glab[GT];
   __shared__ int32_t gacc[GT];
   __shared__ int tmp[NT_SLOT / WAVE];
-  const int d = S->d, pc = S->pool_cap, Pc = S->P_cap;
-  const int ng = S->goal_n;
-  const int np = S->P_n;
-  const int32_t* Pg = S->Pg[S->P_sel];
-  const int32_t* Pl = S->Plab[S->P_sel];
-  int32_t* Qg = S->Pg[S->P_sel ^ 1];
-  int32_t* Ql = S->Plab[S->P_sel ^ 1];
-  // Scratch: prune flags of old P entries and their survivor prefix; the
-  // accepted goal labels are collected in `batch` (free after the pop).
-  int32_t* pflag = S->pscr;
-  int32_t* sprefix = S->pscr + (Pc + 1);
-  int32_t* acc_lab = S->batch;
+  const int d = S.d, pc = S.pool_cap, Pc = S.P_cap;
+  const int ng = S.goal_n;
+  const int np = S.P_n;
+  const int32_t* Pg = pick(S.Pg, S.P_sel);
+  const int32_t* Pl = pick(S.Plab, S.P_sel);
+  int32_t* Qg = pick(S.Pg, S.P_sel ^ 1);
+  int32_t* Ql = pick(S.Plab, S.P_sel ^ 1);
+  // scratch: prune flags of old entries and their survivor prefix; accepted
+  // goal labels are collected in `batch` (free after the pop)
+  int32_t* pflag = S.pscr;
+  int32_t* sprefix = S.pscr + (Pc + 1);
+  int32_t* acc_lab = S.batch;
   if (np + ng > Pc) {
     if (threadIdx.x == 0) {
-      S->status = S_OVERFLOW;
-      S->err_line = __LINE__;
+      Sp->status = S_OVERFLOW;
+      Sp->err_line = __LINE__;
     }
     return;
   }
@@ -407,46 +492,45 @@ __global__ __launch_bounds__(NT_SLOT) void k_goal_merge(Slot* slots) {
   for (int t0 = 0; t0 < ng; t0 += GT) {
     const int nt = min(GT, ng - t0);
     __syncthreads();
-    if (threadIdx.x < nt) {
-      int lab = S->goal_lab[t0 + threadIdx.x];
+    if ((int)threadIdx.x < nt) {
+      const int lab = S.goal_lab[t0 + threadIdx.x];
       glab[threadIdx.x] = lab;
-      for (int k = 0; k < d; ++k) gv[k][threadIdx.x] = S->Lg[(size_t)k * pc + lab];
+      FOR_K(k) gv[k][threadIdx.x] = S.Lg[(size_t)k * pc + lab];
       gacc[threadIdx.x] = 1;
     }
     __syncthreads();
-    // old P entries: pruned if a goal label of this tile strictly dominates them;
-    // goal labels rejected if an old entry weakly dominates them.
+    // old entries against this tile of goal labels
     for (int i = threadIdx.x; i < np; i += NT_SLOT) {
-      int32_t p[MAXD];
-      for (int k = 0; k < d; ++k) p[k] = Pg[(size_t)k * Pc + i];
+      int32_t p[DM];
+      FOR_K(k) p[k] = Pg[(size_t)k * Pc + i];
       bool pruned = false;
       for (int j = 0; j < nt; ++j) {
-        bool le = true, gl = true, anylt = false;
-        for (int k = 0; k < d; ++k) {
-          int gk = gv[k][j];
+        bool le = true, ge = true, anylt = false;
+        FOR_K(k) {
+          const int gk = gv[k][j];
           le = le && (p[k] <= gk);
-          gl = gl && (gk <= p[k]);
+          ge = ge && (gk <= p[k]);
           anylt = anylt || (gk < p[k]);
         }
         if (le) gacc[j] = 0;  // benign race: every writer stores 0
-        if (gl && anylt) pruned = true;
+        if (ge && anylt) pruned = true;
       }
       if (pruned) pflag[i] = 1;
     }
     __syncthreads();
-    // goal labels against every goal label (all tiles)
-    if (threadIdx.x < nt && gacc[threadIdx.x]) {
+    // goal labels of this tile against every goal label
+    if ((int)threadIdx.x < nt && gacc[threadIdx.x]) {
       const int me = threadIdx.x;
-      int32_t a[MAXD];
-      for (int k = 0; k < d; ++k) a[k] = gv[k][me];
+      int32_t a[DM];
+      FOR_K(k) a[k] = gv[k][me];
       const int mylab = glab[me];
       bool rej = false;
       for (int j = 0; j < ng && !rej; ++j) {
-        const int lb = S->goal_lab[j];
+        const int lb = S.goal_lab[j];
         if (lb == mylab) continue;
         bool le = true, eq = true;
-        for (int k = 0; k < d; ++k) {
-          int bk = S->Lg[(size_t)k * pc + lb];
+        FOR_K(k) {
+          const int bk = S.Lg[(size_t)k * pc + lb];
           le = le && (bk <= a[k]);
           eq = eq && (bk == a[k]);
         }
@@ -455,392 +539,646 @@ __global__ __launch_bounds__(NT_SLOT) void k_goal_merge(Slot* slots) {
       if (rej) gacc[me] = 0;
     }
     __syncthreads();
-    // append the accepted goal labels of this tile to acc_lab (ascending label id)
-    int v = (threadIdx.x < nt) ? gacc[threadIdx.x] : 0;
+    const int v = ((int)threadIdx.x < nt) ? gacc[threadIdx.x] : 0;
     int tot;
-    int pos = block_exscan<NT_SLOT>(v, &tot, tmp);
+    const int pos = block_exscan<NT_SLOT>(v, &tot, tmp);
     if (v) acc_lab[na + pos] = glab[threadIdx.x];
     na += tot;
     pairs += (int64_t)nt * np + (int64_t)nt * ng;
   }
   __syncthreads();
-  // survivors of old P: exclusive prefix (stored in the batch scratch `reg_off`? no: reuse c_rank)
   int carry = 0;
   for (int base = 0; base < np; base += NT_SLOT) {
-    int i = base + threadIdx.x;
-    int alive = (i < np && !pflag[i]) ? 1 : 0;
+    const int i = base + threadIdx.x;
+    const int alive = (i < np && !pflag[i]) ? 1 : 0;
     int tot;
-    int ex = block_exscan<NT_SLOT>(alive, &tot, tmp);
+    const int ex = block_exscan<NT_SLOT>(alive, &tot, tmp);
     if (i < np) sprefix[i] = carry + ex;
     carry += tot;
   }
   const int nsurv = carry;
-  __syncthreads();
   if (threadIdx.x == 0) sprefix[np] = nsurv;
   __syncthreads();
-  // output positions: old survivor i -> sprefix[i] + #(accepted goal vectors < it)
-  //                   accepted goal j -> #(old survivors < it) + #(accepted goal vectors < it)
-  // (vectors are pairwise distinct across the two lists after the filtering above)
-  auto lexless = [&](const int32_t* a, const int32_t* b) {
-    for (int k = 0; k < d; ++k)
-      if (a[k] != b[k]) return a[k] < b[k];
-    return false;
-  };
-  // Write old survivors into the other buffer.
-  for (int base = 0; base < np; base += NT_SLOT) {
-    int i = base + threadIdx.x;
-    bool alive = i < np && !pflag[i];
-    int32_t p[MAXD];
-    int lab = 0, outpos = 0;
-    if (alive) {
-      for (int k = 0; k < d; ++k) p[k] = Pg[(size_t)k * Pc + i];
-      lab = Pl[i];
-      int c = 0;
-      for (int j = 0; j < na; ++j) {
-        int32_t q[MAXD];
-        const int lb = acc_lab[j];
-        for (int k = 0; k < d; ++k) q[k] = S->Lg[(size_t)k * pc + lb];
-        if (lexless(q, p)) ++c;
-      }
-      outpos = sprefix[i] + c;
+  // output position of an old survivor i: sprefix[i] + #(accepted goal vectors
+  // below it); of an accepted goal vector q: #(old survivors below q) +
+  // #(accepted goal vectors below q).  All these vectors are distinct.
+  for (int i = threadIdx.x; i < np; i += NT_SLOT) {
+    if (pflag[i]) continue;
+    int32_t p[DM];
+    FOR_K(k) p[k] = Pg[(size_t)k * Pc + i];
+    int c = 0;
+    for (int j = 0; j < na; ++j) {
+      int32_t q[DM];
+      const int lb = acc_lab[j];
+      FOR_K(k) q[k] = S.Lg[(size_t)k * pc + lb];
+      if (lex_less<DM>(q, p, d)) ++c;
     }
-    if (alive) {
-      for (int k = 0; k < d; ++k) Qg[(size_t)k * Pc + outpos] = p[k];
-      Ql[outpos] = lab;
-    }
+    const int outpos = sprefix[i] + c;
+    FOR_K(k) Qg[(size_t)k * Pc + outpos] = p[k];
+    Ql[outpos] = Pl[i];
   }
-  // accepted goal labels
   for (int j = threadIdx.x; j < na; j += NT_SLOT) {
     const int lb = acc_lab[j];
-    int32_t q[MAXD];
-    for (int k = 0; k < d; ++k) q[k] = S->Lg[(size_t)k * pc + lb];
-    // #old survivors lexicographically below q: binary search in old P, then sprefix
-    int lo_i = 0, hi_i = np;
+    int32_t q[DM];
+    FOR_K(k) q[k] = S.Lg[(size_t)k * pc + lb];
+    int lo_i = 0, hi_i = np;  // old entries lexicographically below q
     while (lo_i < hi_i) {
-      int mid = (lo_i + hi_i) >> 1;
-      int32_t p[MAXD];
-      for (int k = 0; k < d; ++k) p[k] = Pg[(size_t)k * Pc + mid];
-      if (lexless(p, q)) lo_i = mid + 1; else hi_i = mid;
+      const int mid = (lo_i + hi_i) >> 1;
+      int32_t p[DM];
+      FOR_K(k) p[k] = Pg[(size_t)k * Pc + mid];
+      if (lex_less<DM>(p, q, d)) lo_i = mid + 1; else hi_i = mid;
     }
     int c = 0;
     for (int i = 0; i < na; ++i) {
       if (i == j) continue;
       const int lb2 = acc_lab[i];
-      int32_t r[MAXD];
-      for (int k = 0; k < d; ++k) r[k] = S->Lg[(size_t)k * pc + lb2];
-      if (lexless(r, q)) ++c;
+      int32_t r[DM];
+      FOR_K(k) r[k] = S.Lg[(size_t)k * pc + lb2];
+      if (lex_less<DM>(r, q, d)) ++c;
     }
-    int outpos = sprefix[lo_i] + c;
-    for (int k = 0; k < d; ++k) Qg[(size_t)k * Pc + outpos] = q[k];
+    const int outpos = sprefix[lo_i] + c;
+    FOR_K(k) Qg[(size_t)k * Pc + outpos] = q[k];
     Ql[outpos] = lb;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    S->P_n = nsurv + na;
-    S->P_sel ^= 1;
-    S->st[ST_PPAIRS] += pairs;
+    Sp->P_n = nsurv + na;
+    Sp->P_sel = S.P_sel ^ 1;
+    Sp->st[ST_PPAIRS] += pairs;
+    // goal labels the front already covers were not processed (lazy PruneOPEN)
+    Sp->st[ST_POPS] -= ng - na;
+    Sp->st[ST_KILLED] += ng - na;
   }
 }
 
-// ---------------------------------------------------------------- expand + P filter
+// ---------------------------------------------------------------- pop-time front check
+// The paper's PruneOPEN drops every open label whose F the goal front
+// dominates (Algorithm 1 lines 9-10); here it is applied lazily to the
+// popped regular labels (weak dominance), after this step's goal labels were
+// merged into the front.  A dropped label is not expanded.  Work items are
+// (label tile, front chunk) pairs.
+template <int DM>
+__global__ __launch_bounds__(NT_TILE) void k_popcheck(Slot* slots, GraphDev G) {
+  Slot* Sp = &slots[blockIdx.y];
+  const Slot S = *Sp;
+  if (S.status != S_RUN) return;
+  const int R = S.reg_n, np = S.P_n;
+  if (R == 0 || np == 0) return;
+  const int nlt = (R + NT_TILE - 1) / NT_TILE, npc = (np + PCH - 1) / PCH;
+  const int ntiles = nlt * npc;
+  if ((int)blockIdx.x >= ntiles) return;
+  __shared__ int32_t ps[DM][PCH];
+  const int d = S.d, pc = S.pool_cap, Pc = S.P_cap, n = G.n;
+  const int32_t* Pg = pick(S.Pg, S.P_sel);
+  int killed = 0;
+  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int lt = t / npc, pcn = t - lt * npc;
+    const int p0 = pcn * PCH, npt = min(PCH, np - p0);
+    __syncthreads();
+    if ((int)threadIdx.x < npt) FOR_K(k) ps[k][threadIdx.x] = Pg[(size_t)k * Pc + p0 + threadIdx.x];
+    __syncthreads();
+    const int i = lt * NT_TILE + threadIdx.x;
+    if (i < R) {
+      const int lab = S.reg[i];
+      const int v = S.Lnode[lab];
+      int32_t F[DM];
+      FOR_K(k) F[k] = S.Lg[(size_t)k * pc + lab] + S.h[(size_t)k * n + v];
+      bool dom = false;
+      for (int q = 0; q < npt && !dom; ++q) {
+        bool le = true;
+        FOR_K(k) le = le && (ps[k][q] <= F[k]);
+        dom = le;
+      }
+      if (dom && atomicExch(&S.reg_kill[i], 1) == 0) {
+        S.Lstate[lab] = L_DEAD;
+        ++killed;
+      }
+    }
+  }
+  const int64_t k64 = wave_sum64(killed);
+  if (lane_id() == 0 && k64) {
+    atomicAdd((unsigned long long*)&Sp->st[ST_KILLED], (unsigned long long)k64);
+    atomicAdd((unsigned long long*)&Sp->st[ST_POPS], (unsigned long long)(-k64));
+  }
+}
+
+// ---------------------------------------------------------------- expand
+// One thread per candidate (flat index over the regular labels' out-arcs):
+// g' = g + c(e), F' = g' + h(v') (Algorithm 1 lines 16-17).  A target that
+// cannot reach the goal is dropped at once.
+template <int DM>
 __global__ __launch_bounds__(NT_TILE) void k_expand(Slot* slots, GraphDev G) {
-  Slot* S = &slots[blockIdx.y];
-  if (S->status != S_RUN) return;
-  const int M = S->cand_n;
-  if ((int)(blockIdx.x * NT_TILE) >= M) return;
-  constexpr int PT = NT_TILE;
-  __shared__ int32_t ps[MAXD][PT];
-  const int d = S->d, pc = S->pool_cap, cc = S->cand_cap, n = G.n;
-  const int reg_n = S->reg_n;
-  const int np = S->P_n;
-  const int32_t* Pg = S->Pg[S->P_sel];
-  const int Pc = S->P_cap;
+  Slot* Sp = &slots[blockIdx.y];
+  const Slot S = *Sp;
+  if (S.status != S_RUN) return;
+  const int M = S.cand_n;
+  const int d = S.d, pc = S.pool_cap, cc = S.cand_cap, n = G.n;
+  const int reg_n = S.reg_n;
+  const int np = S.P_n;
   int64_t ncand = 0, npairs = 0;
-  for (int base = blockIdx.x * NT_TILE; base < M; base += gridDim.x * NT_TILE) {
-    const int f = base + threadIdx.x;
-    const bool valid = f < M;
-    bool alive = false;
-    int32_t g[MAXD], F[MAXD];
-    int v = 0, lab = 0, e = 0;
-    if (valid) {
-      // regular label owning flat index f: last j with reg_off[j] <= f
-      int lo_i = 0, hi_i = reg_n - 1;
-      while (lo_i < hi_i) {
-        int mid = (lo_i + hi_i + 1) >> 1;
-        if (S->reg_off[mid] <= f) lo_i = mid; else hi_i = mid - 1;
-      }
-      lab = S->reg[lo_i];
-      const int u = S->Lnode[lab];
-      e = G.row_ptr[u] + (f - S->reg_off[lo_i]);
-      v = G.col[e];
-      alive = true;
-      for (int k = 0; k < d; ++k) {
-        int hk = S->h[(size_t)k * n + v];
-        if (hk == UNREACH) alive = false;
-        g[k] = S->Lg[(size_t)k * pc + lab] + G.cost[(size_t)k * G.m + e];
-        F[k] = g[k] + (hk == UNREACH ? 0 : hk);
-      }
-      ncand++;
-      if (alive) npairs += np;
+  for (int f = blockIdx.x * NT_TILE + threadIdx.x; f < M; f += gridDim.x * NT_TILE) {
+    int lo_i = 0, hi_i = reg_n - 1;  // regular label owning flat index f
+    while (lo_i < hi_i) {
+      const int mid = (lo_i + hi_i + 1) >> 1;
+      if (S.reg_off[mid] <= f) lo_i = mid; else hi_i = mid - 1;
     }
-    // goal-front filter: drop F' weakly dominated by some P entry
-    for (int p0 = 0; p0 < np; p0 += PT) {
-      const int npt = min(PT, np - p0);
-      __syncthreads();
-      if ((int)threadIdx.x < npt)
-        for (int k = 0; k < d; ++k) ps[k][threadIdx.x] = Pg[(size_t)k * Pc + p0 + threadIdx.x];
-      __syncthreads();
-      if (alive) {
-        for (int q = 0; q < npt; ++q) {
-          bool le = true;
-          for (int k = 0; k < d; ++k) le = le && (ps[k][q] <= F[k]);
-          if (le) {
-            alive = false;
-            break;
-          }
-        }
-      }
+    S.c_rej[f] = 0;
+    S.c_acc[f] = 0;
+    if (S.reg_kill[lo_i]) {  // dropped at pop: nothing to expand
+      S.c_keep[f] = 0;
+      continue;
     }
-    if (valid) {
-      S->c_node[f] = v;
-      S->c_par[f] = lab;
-      S->c_arc[f] = e;
-      for (int k = 0; k < d; ++k) S->c_g[(size_t)k * cc + f] = g[k];
-      S->c_keep[f] = alive ? 1 : 0;
-      S->c_rej[f] = 0;
-      S->c_acc[f] = 0;
+    const int lab = S.reg[lo_i];
+    const int u = S.Lnode[lab];
+    const int e = G.row_ptr[u] + (f - S.reg_off[lo_i]);
+    const int v = G.col[e];
+    bool alive = true;
+    FOR_K(k) {
+      if (S.h[(size_t)k * n + v] == UNREACH) alive = false;
+      S.c_g[(size_t)k * cc + f] = S.Lg[(size_t)k * pc + lab] + G.cost[(size_t)k * G.m + e];
     }
+    S.c_node[f] = v;
+    S.c_par[f] = lab;
+    S.c_arc[f] = e;
+    S.c_keep[f] = alive ? 1 : 0;
+    ncand++;
+    if (alive) npairs += np;
   }
   ncand = wave_sum64(ncand);
   npairs = wave_sum64(npairs);
   if (lane_id() == 0) {
-    if (ncand) atomicAdd((unsigned long long*)&S->st[ST_CANDS], (unsigned long long)ncand);
-    if (npairs) atomicAdd((unsigned long long*)&S->st[ST_PPAIRS], (unsigned long long)npairs);
+    if (ncand) atomicAdd((unsigned long long*)&Sp->st[ST_CANDS], (unsigned long long)ncand);
+    if (npairs) atomicAdd((unsigned long long*)&Sp->st[ST_PPAIRS], (unsigned long long)npairs);
+  }
+}
+
+// ---------------------------------------------------------------- goal-front filter
+// Drop a candidate whose F' is weakly dominated by a goal-front entry
+// (Algorithm 1 lines 19 and 29; weak dominance: a completion of F' = p
+// cannot improve on p).  Work items are (candidate tile, front chunk) pairs so
+// that a large front spreads over the whole chip; every writer stores 0.
+template <int DM>
+__global__ __launch_bounds__(NT_TILE) void k_pfilter(Slot* slots, GraphDev G) {
+  const Slot S = slots[blockIdx.y];
+  if (S.status != S_RUN) return;
+  const int M = S.cand_n, np = S.P_n;
+  if (M == 0 || np == 0) return;
+  const int nct = (M + NT_TILE - 1) / NT_TILE, npc = (np + PCH - 1) / PCH;
+  const int ntiles = nct * npc;
+  if ((int)blockIdx.x >= ntiles) return;
+  __shared__ int32_t ps[DM][PCH];
+  const int d = S.d, cc = S.cand_cap, Pc = S.P_cap, n = G.n;
+  const int32_t* Pg = pick(S.Pg, S.P_sel);
+  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int ct = t / npc, pcn = t - ct * npc;
+    const int p0 = pcn * PCH, npt = min(PCH, np - p0);
+    __syncthreads();
+    if ((int)threadIdx.x < npt) FOR_K(k) ps[k][threadIdx.x] = Pg[(size_t)k * Pc + p0 + threadIdx.x];
+    __syncthreads();
+    const int f = ct * NT_TILE + threadIdx.x;
+    if (f < M && S.c_keep[f]) {
+      int32_t F[DM];
+      const int v = S.c_node[f];
+      FOR_K(k) F[k] = S.c_g[(size_t)k * cc + f] + S.h[(size_t)k * n + v];
+      bool dom = false;
+      for (int q = 0; q < npt && !dom; ++q) {
+        bool le = true;
+        FOR_K(k) le = le && (ps[k][q] <= F[k]);
+        dom = le;
+      }
+      if (dom) S.c_keep[f] = 0;
+    }
   }
 }
 
 // ---------------------------------------------------------------- group by target node
 __global__ __launch_bounds__(NT_TILE) void k_group_count(Slot* slots) {
-  Slot* S = &slots[blockIdx.y];
-  if (S->status != S_RUN) return;
-  const int M = S->cand_n;
+  Slot* Sp = &slots[blockIdx.y];
+  const Slot S = *Sp;
+  if (S.status != S_RUN) return;
+  const int M = S.cand_n;
   for (int f = blockIdx.x * NT_TILE + threadIdx.x; f < M; f += gridDim.x * NT_TILE) {
-    if (!S->c_keep[f]) continue;
-    const int v = S->c_node[f];
-    const int r = atomicAdd(&S->grp_cnt[v], 1);
-    S->c_rank[f] = r;
+    if (!S.c_keep[f]) continue;
+    const int v = S.c_node[f];
+    const int r = atomicAdd(&S.grp_cnt[v], 1);
+    S.c_rank[f] = r;
     if (r == 0) {
-      const int gid = atomicAdd(&S->ngroups, 1);
-      S->grp_node[gid] = v;
-      S->grp_id[v] = gid;
+      const int gid = atomicAdd(&Sp->ngroups, 1);
+      S.grp_node[gid] = v;
+      S.grp_id[v] = gid;
     }
   }
 }
 
+// Group offsets, and the split of groups into small (one wave, one pass) and
+// big (pair tiles across waves): a group is big when it has more than one
+// candidate tile or its candidate x (frontier + candidates) work is large.
 __global__ __launch_bounds__(NT_SLOT) void k_group_offsets(Slot* slots) {
-  Slot* S = &slots[blockIdx.x];
-  if (S->status != S_RUN) return;
+  Slot* Sp = &slots[blockIdx.x];
+  const Slot S = *Sp;
+  if (S.status != S_RUN) return;
   __shared__ int tmp[NT_SLOT / WAVE];
-  const int ng = S->ngroups;
-  int carry = 0;
+  const int ng = S.ngroups;
+  int carry = 0, ns = 0, nb = 0, nt = 0;
   for (int base = 0; base < ng; base += NT_SLOT) {
-    int i = base + threadIdx.x;
-    int sz = i < ng ? S->grp_cnt[S->grp_node[i]] : 0;
-    int tot;
-    int ex = block_exscan<NT_SLOT>(sz, &tot, tmp);
-    if (i < ng) S->grp_off[i] = carry + ex;
+    const int i = base + threadIdx.x;
+    int sz = 0, cnt = 0;
+    if (i < ng) {
+      const int v = S.grp_node[i];
+      sz = S.grp_cnt[v];
+      cnt = S.node[v].count;
+    }
+    const bool big = i < ng && (sz > WAVE || (int64_t)sz * (cnt + sz) > BIG_WORK);
+    const bool small = i < ng && !big;
+    const int nct = (sz + WAVE - 1) / WAVE, nft = (cnt + WAVE - 1) / WAVE;
+    const int tiles = big ? nct * nct + nft * nct : 0;
+    int tot, ts, tb, tt;
+    const int ex = block_exscan<NT_SLOT>(sz, &tot, tmp);
+    const int ps = block_exscan<NT_SLOT>(small ? 1 : 0, &ts, tmp);
+    const int pb = block_exscan<NT_SLOT>(big ? 1 : 0, &tb, tmp);
+    const int pt = block_exscan<NT_SLOT>(tiles, &tt, tmp);
+    if (i < ng) S.grp_off[i] = carry + ex;
+    if (small) S.small_list[ns + ps] = i;
+    if (big) {
+      S.big_list[nb + pb] = i;
+      S.big_toff[nb + pb] = nt + pt;
+    }
     carry += tot;
+    ns += ts;
+    nb += tb;
+    nt += tt;
   }
-  if (threadIdx.x == 0) S->st[ST_GROUPS] += ng;
+  if (threadIdx.x == 0) {
+    S.big_toff[nb] = nt;
+    Sp->nsmall = ns;
+    Sp->nbig = nb;
+    Sp->big_tiles = nt;
+    Sp->st[ST_GROUPS] += ng;
+  }
 }
 
 __global__ __launch_bounds__(NT_TILE) void k_group_scatter(Slot* slots) {
-  Slot* S = &slots[blockIdx.y];
-  if (S->status != S_RUN) return;
-  const int M = S->cand_n;
+  const Slot S = slots[blockIdx.y];
+  if (S.status != S_RUN) return;
+  const int M = S.cand_n;
   for (int f = blockIdx.x * NT_TILE + threadIdx.x; f < M; f += gridDim.x * NT_TILE) {
-    if (!S->c_keep[f]) continue;
-    const int gid = S->grp_id[S->c_node[f]];
-    S->order[S->grp_off[gid] + S->c_rank[f]] = f;
+    if (!S.c_keep[f]) continue;
+    const int gid = S.grp_id[S.c_node[f]];
+    S.order[S.grp_off[gid] + S.c_rank[f]] = f;
   }
 }
 
-// ---------------------------------------------------------------- frontier check
-// One wave per group (all candidates of this step with the same target node v):
+// Take a new frontier block when `need` entries do not fit the node's block.
+// Returns false (and marks the slot) when the slot's frontier region is exhausted.
+__device__ __forceinline__ bool frontier_dest(Slot* Sp, const Slot& S, const NodeRec& nr, int need,
+                                              int d, int64_t* doff, int* dcap) {
+  *doff = nr.off;
+  *dcap = nr.cap;
+  if (need <= nr.cap) return true;
+  int nc = MINCAP;
+  while (nc < need) nc <<= 1;
+  const int64_t words = (int64_t)nc * (d + 1);
+  int64_t pos = 0;
+  if (lane_id() == 0)
+    pos = (int64_t)atomicAdd((unsigned long long*)&Sp->fw_top, (unsigned long long)words);
+  pos = __shfl(pos, 0);
+  if (pos + words > S.fw_cap) {
+    if (lane_id() == 0) {
+      Sp->status = S_OVERFLOW;
+      Sp->err_line = __LINE__;
+    }
+    return false;
+  }
+  *doff = pos;
+  *dcap = nc;
+  return true;
+}
+
+// ---------------------------------------------------------------- frontier check (small groups)
+// One wave per group (all candidates of this step with the same target node v,
+// at most one candidate per lane):
 //  A. candidates against each other: c_i is dropped if some c_j <= c_i in every
 //     objective and (c_j != c_i or j precedes i in flat order);
-//  B. survivors against the live frontier of v, 64 frontier entries per lane
-//     tile, every entry loaded once: a candidate is rejected if an entry
-//     weakly dominates it (dominated or duplicate, Algorithm 1 lines 22-25);
-//     an entry is pruned if a survivor strictly dominates it (lines 26-28; a
-//     rejected candidate can dominate no live entry because the frontier is an
-//     antichain); pruned entries are marked dead in the pool and the block is
-//     compacted as it is streamed;
+//  B. survivors against the live frontier of v, one frontier entry per lane,
+//     every entry loaded once (the next tile is loaded before the current one
+//     is compared): a candidate is rejected if an entry weakly dominates it
+//     (dominated or duplicate, Algorithm 1 lines 22-25); an entry is pruned if
+//     a survivor strictly dominates it (lines 26-28; a rejected candidate can
+//     dominate no live entry because the frontier is an antichain); pruned
+//     entries are marked dead in the pool and the block is compacted as it is
+//     streamed;
 //  C. accepted candidates are appended (a larger block is taken when needed).
+template <int DM>
 __global__ __launch_bounds__(NT_TILE) void k_group_process(Slot* slots) {
-  Slot* S = &slots[blockIdx.y];
-  if (S->status != S_RUN) return;
-  const int ngroups = S->ngroups;
+  Slot* Sp = &slots[blockIdx.y];
+  const Slot S = *Sp;
+  if (S.status != S_RUN) return;
+  const int nsmall = S.nsmall;
   const int wave = threadIdx.x / WAVE, lane = lane_id();
-  __shared__ int32_t cg_all[GP_WAVES][MAXD][WAVE];
+  __shared__ int32_t cg_all[GP_WAVES][DM][WAVE];
   __shared__ int32_t cf_all[GP_WAVES][WAVE];
   __shared__ int32_t cr_all[GP_WAVES][WAVE];
   int32_t(*cg)[WAVE] = cg_all[wave];
   int32_t* cf = cf_all[wave];
   int32_t* cr = cr_all[wave];
-  const int d = S->d, cc = S->cand_cap;
-  int32_t* fw = S->fw;
+  const int d = S.d, cc = S.cand_cap;
+  int32_t* fw = S.fw;
   int64_t gpairs = 0, fpairs = 0, fbytes = 0, pruned = 0;
-  for (int gid = blockIdx.x * GP_WAVES + wave; gid < ngroups; gid += gridDim.x * GP_WAVES) {
-    const int v = S->grp_node[gid];
-    const int off = S->grp_off[gid];
-    const int k = S->grp_cnt[v];
-    int32_t* ord = S->order + off;
-    // ---- A. intra-group resolution
-    int ks = k;
+  for (int si = blockIdx.x * GP_WAVES + wave; si < nsmall; si += gridDim.x * GP_WAVES) {
+    const int gid = S.small_list[si];
+    const int v = S.grp_node[gid];
+    const int k = S.grp_cnt[v];  // <= WAVE for small groups
+    int32_t* ord = S.order + S.grp_off[gid];
+    // ---- A. intra-group resolution (one candidate tile)
+    const bool have = lane < k;
+    const int fi = have ? ord[lane] : 0;
+    int32_t ci[DM];
+    FOR_K(kk) ci[kk] = have ? S.c_g[(size_t)kk * cc + fi] : 0;
+    wave_sync();
+    cf[lane] = fi;
+    FOR_K(kk) cg[kk][lane] = ci[kk];
+    wave_sync();
+    bool rej = false;
     if (k > 1) {
       gpairs += (int64_t)k * (k - 1);
-      for (int it = 0; it < k; it += WAVE) {
-        const int i = it + lane;
-        const bool have = i < k;
-        const int fi = have ? ord[i] : 0;
-        int32_t ci[MAXD];
-        for (int kk = 0; kk < d; ++kk) ci[kk] = have ? S->c_g[(size_t)kk * cc + fi] : 0;
-        bool rej = false;
-        for (int jt = 0; jt < k; jt += WAVE) {
-          const int j = jt + lane;
-          wave_sync();
-          if (j < k) {
-            const int fj = ord[j];
-            cf[lane] = fj;
-            for (int kk = 0; kk < d; ++kk) cg[kk][lane] = S->c_g[(size_t)kk * cc + fj];
+      if (have)
+        for (int jj = 0; jj < k && !rej; ++jj) {
+          if (jj == lane) continue;
+          bool le = true, eq = true;
+          FOR_K(kk) {
+            const int b = cg[kk][jj];
+            le = le && (b <= ci[kk]);
+            eq = eq && (b == ci[kk]);
           }
-          wave_sync();
-          const int nj = min(WAVE, k - jt);
-          if (have && !rej) {
-            for (int jj = 0; jj < nj; ++jj) {
-              if (jt + jj == i) continue;
-              bool le = true, eq = true;
-              for (int kk = 0; kk < d; ++kk) {
-                const int b = cg[kk][jj];
-                le = le && (b <= ci[kk]);
-                eq = eq && (b == ci[kk]);
-              }
-              if (le && (!eq || cf[jj] < fi)) {
-                rej = true;
-                break;
-              }
-            }
-          }
+          rej = le && (!eq || cf[jj] < fi);
         }
-        if (have && rej) S->c_rej[fi] = 1;
-      }
-      __threadfence_block();
-      // compact survivors to the front of the group's order list (in place)
-      int cur = 0;
-      for (int it = 0; it < k; it += WAVE) {
-        const int i = it + lane;
-        const bool have = i < k;
-        const int fi = have ? ord[i] : 0;
-        const bool surv = have && !S->c_rej[fi];
-        const uint64_t m = ballot(surv);
-        wave_sync();
-        if (surv) ord[cur + rank_below(m)] = fi;
-        cur += __popcll(m);
-      }
-      ks = cur;
-      __threadfence_block();
     }
+    // survivors to the front of the tile (LDS), in order
+    const uint64_t sm = ballot(have && !rej);
+    const int ks = __popcll(sm);
+    wave_sync();
+    if (have && !rej) {
+      const int p = rank_below(sm);
+      cf[p] = fi;
+      FOR_K(kk) cg[kk][p] = ci[kk];
+    }
+    if (lane < ks) cr[lane] = 0;
+    if (have && rej) S.c_rej[fi] = 1;
+    wave_sync();
     // ---- B. frontier check + prune + compaction
-    const NodeRec nr = S->node[v];
+    const NodeRec nr = S.node[v];
     const int cnt = nr.count;
-    int64_t doff = nr.off;
-    int dcap = nr.cap;
-    if (cnt + ks > nr.cap) {
-      int nc = MINCAP;
-      while (nc < cnt + ks) nc <<= 1;
-      const int64_t words = (int64_t)nc * (d + 1);
-      int64_t pos = 0;
-      if (lane == 0) pos = (int64_t)atomicAdd((unsigned long long*)&S->fw_top, (unsigned long long)words);
-      pos = __shfl(pos, 0);
-      if (pos + words > S->fw_cap) {
-        if (lane == 0) {
-          S->status = S_OVERFLOW;
-          S->err_line = __LINE__;
-        }
-        break;
-      }
-      doff = pos;
-      dcap = nc;
-    }
+    int64_t doff;
+    int dcap;
+    if (!frontier_dest(Sp, S, nr, cnt + ks, d, &doff, &dcap)) break;
     const bool moved = doff != nr.off;
     fpairs += (int64_t)ks * cnt;
     fbytes += (int64_t)cnt * 4 * d;
     int cursor = 0;
+    int32_t nv[DM];
+    int nlab = 0;
+    {
+      const bool h0 = lane < cnt;
+      FOR_K(kk) nv[kk] = h0 ? fw[nr.off + (int64_t)kk * nr.cap + lane] : 0;
+      nlab = h0 ? fw[nr.off + (int64_t)d * nr.cap + lane] : 0;
+    }
     for (int t = 0; t < cnt; t += WAVE) {
       const int e = t + lane;
       const bool has = e < cnt;
-      int32_t sv[MAXD];
-      for (int kk = 0; kk < d; ++kk) sv[kk] = has ? fw[nr.off + (int64_t)kk * nr.cap + e] : 0;
-      const int slab = has ? fw[nr.off + (int64_t)d * nr.cap + e] : 0;
-      bool prune = false;
-      for (int ct = 0; ct < ks; ct += WAVE) {
-        const int j = ct + lane;
-        wave_sync();
-        if (j < ks) {
-          const int fj = ord[j];
-          cf[lane] = fj;
-          cr[lane] = S->c_rej[fj];
-          for (int kk = 0; kk < d; ++kk) cg[kk][lane] = S->c_g[(size_t)kk * cc + fj];
-        }
-        wave_sync();
-        const int nj = min(WAVE, ks - ct);
-        for (int jj = 0; jj < nj; ++jj) {
-          if (cr[jj]) continue;  // uniform across the wave
-          bool le = has, ge = has, lt = false;
-          for (int kk = 0; kk < d; ++kk) {
-            const int c = cg[kk][jj];
-            le = le && (sv[kk] <= c);
-            ge = ge && (c <= sv[kk]);
-            lt = lt || (c < sv[kk]);
-          }
-          if (ballot(le)) {
-            if (lane == 0) cr[jj] = 1;
-            wave_sync();
-          } else if (ge && lt) {
-            prune = true;
-          }
-        }
-        wave_sync();
-        if (j < ks && cr[lane]) S->c_rej[cf[lane]] = 1;
+      int32_t sv[DM];
+      FOR_K(kk) sv[kk] = nv[kk];
+      const int slab = nlab;
+      {  // prefetch the next tile
+        const int e2 = e + WAVE;
+        const bool h2 = e2 < cnt;
+        FOR_K(kk) nv[kk] = h2 ? fw[nr.off + (int64_t)kk * nr.cap + e2] : 0;
+        nlab = h2 ? fw[nr.off + (int64_t)d * nr.cap + e2] : 0;
       }
-      if (prune) S->Lstate[slab] = L_DEAD;
+      bool prune = false;
+      for (int jj = 0; jj < ks; ++jj) {
+        if (cr[jj]) continue;  // uniform across the wave
+        bool le = has, ge = has, lt = false;
+        FOR_K(kk) {
+          const int c = cg[kk][jj];
+          le = le && (sv[kk] <= c);
+          ge = ge && (c <= sv[kk]);
+          lt = lt || (c < sv[kk]);
+        }
+        if (ballot(le)) {
+          if (lane == 0) cr[jj] = 1;
+          wave_sync();
+        } else if (ge && lt) {
+          prune = true;
+        }
+      }
+      if (prune) S.Lstate[slab] = L_DEAD;
       const uint64_t hm = ballot(has);
       const uint64_t am = ballot(has && !prune);
       pruned += __popcll(hm & ~am);
       if (moved || cursor != t || am != hm) {
         if (has && !prune) {
           const int64_t w = doff + cursor + rank_below(am);
-          for (int kk = 0; kk < d; ++kk) fw[w + (int64_t)kk * dcap] = sv[kk];
+          FOR_K(kk) fw[w + (int64_t)kk * dcap] = sv[kk];
           fw[w + (int64_t)d * dcap] = slab;
         }
       }
       cursor += __popcll(am);
     }
-    __threadfence_block();
     // ---- C. append the accepted candidates
-    for (int ct = 0; ct < ks; ct += WAVE) {
+    wave_sync();
+    const bool acc = lane < ks && !cr[lane];
+    const uint64_t m = ballot(acc);
+    if (lane < ks && !acc) S.c_rej[cf[lane]] = 1;
+    if (acc) {
+      const int fj = cf[lane];
+      const int64_t w = doff + cursor + rank_below(m);
+      FOR_K(kk) fw[w + (int64_t)kk * dcap] = cg[kk][lane];
+      fw[w + (int64_t)d * dcap] = -1;
+      S.c_fslot[fj] = w + (int64_t)d * dcap;
+      S.c_acc[fj] = 1;
+    }
+    cursor += __popcll(m);
+    if (lane == 0) {
+      NodeRec out;
+      out.off = doff;
+      out.cap = dcap;
+      out.count = cursor;
+      S.node[v] = out;
+      S.grp_cnt[v] = 0;
+      S.grp_id[v] = -1;
+    }
+  }
+  // the per-group totals are wave-uniform: lane 0 publishes them
+  if (lane == 0) {
+    if (gpairs) atomicAdd((unsigned long long*)&Sp->st[ST_GPAIRS], (unsigned long long)gpairs);
+    if (fpairs) atomicAdd((unsigned long long*)&Sp->st[ST_FPAIRS], (unsigned long long)fpairs);
+    if (fbytes) {
+      atomicAdd((unsigned long long*)&Sp->st[ST_FBYTES], (unsigned long long)fbytes);
+      atomicAdd((unsigned long long*)&Sp->st[ST_FBYTES_WAVE], (unsigned long long)fbytes);
+    }
+    if (pruned) atomicAdd((unsigned long long*)&Sp->st[ST_PRUNED], (unsigned long long)pruned);
+  }
+}
+
+// ---------------------------------------------------------------- big groups
+// Pair tiles of the big groups, one wave per tile:
+//   A-tiles (candidate tile I x candidate tile J): a candidate of I is rejected
+//     if a candidate of J weakly dominates it (ties: smaller flat index stays);
+//   B-tiles (frontier tile T x candidate tile J): a candidate is rejected if an
+//     entry of T weakly dominates it; an entry is pruned if a candidate strictly
+//     dominates it.  Any candidate may prune: the minimal candidates below a
+//     pruning one are accepted (the live frontier is an antichain), so the
+//     outcome equals pruning by accepted candidates only.
+// Rejections are idempotent stores; a prune sets PRUNED_BIT in the entry's
+// label-id slot with an atomic OR, and the first setter marks the label dead.
+template <int DM>
+__global__ __launch_bounds__(NT_TILE) void k_group_pairs(Slot* slots) {
+  Slot* Sp = &slots[blockIdx.y];
+  const Slot S = *Sp;
+  if (S.status != S_RUN) return;
+  const int total = S.big_tiles, nbig = S.nbig;
+  const int wave = threadIdx.x / WAVE, lane = lane_id();
+  __shared__ int32_t cg_all[GP_WAVES][DM][WAVE];
+  __shared__ int32_t cf_all[GP_WAVES][WAVE];
+  int32_t(*cg)[WAVE] = cg_all[wave];
+  int32_t* cf = cf_all[wave];
+  const int d = S.d, cc = S.cand_cap;
+  int32_t* fw = S.fw;
+  int64_t pruned = 0;
+  for (int tt = blockIdx.x * GP_WAVES + wave; tt < total; tt += gridDim.x * GP_WAVES) {
+    int lo_i = 0, hi_i = nbig - 1;  // big group owning tile tt
+    while (lo_i < hi_i) {
+      const int mid = (lo_i + hi_i + 1) >> 1;
+      if (S.big_toff[mid] <= tt) lo_i = mid; else hi_i = mid - 1;
+    }
+    const int gid = S.big_list[lo_i];
+    const int local = tt - S.big_toff[lo_i];
+    const int v = S.grp_node[gid];
+    const int k = S.grp_cnt[v];
+    const int32_t* ord = S.order + S.grp_off[gid];
+    const int nct = (k + WAVE - 1) / WAVE;
+    const bool is_a = local < nct * nct;
+    const int rest = is_a ? local : local - nct * nct;
+    const int I = rest / nct, J = rest % nct;
+    const int j = J * WAVE + lane;
+    wave_sync();
+    if (j < k) {
+      const int fj = ord[j];
+      cf[lane] = fj;
+      FOR_K(kk) cg[kk][lane] = S.c_g[(size_t)kk * cc + fj];
+    }
+    wave_sync();
+    const int nj = min(WAVE, k - J * WAVE);
+    if (is_a) {
+      const int i = I * WAVE + lane;
+      if (i < k) {
+        const int fi = ord[i];
+        int32_t ci[DM];
+        FOR_K(kk) ci[kk] = S.c_g[(size_t)kk * cc + fi];
+        bool rej = false;
+        for (int jj = 0; jj < nj && !rej; ++jj) {
+          if (cf[jj] == fi) continue;
+          bool le = true, eq = true;
+          FOR_K(kk) {
+            const int b = cg[kk][jj];
+            le = le && (b <= ci[kk]);
+            eq = eq && (b == ci[kk]);
+          }
+          rej = le && (!eq || cf[jj] < fi);
+        }
+        if (rej) S.c_rej[fi] = 1;
+      }
+    } else {
+      const NodeRec nr = S.node[v];
+      const int e = I * WAVE + lane;
+      const bool has = e < nr.count;
+      int32_t sv[DM];
+      FOR_K(kk) sv[kk] = has ? fw[nr.off + (int64_t)kk * nr.cap + e] : 0;
+      bool prune = false;
+      for (int jj = 0; jj < nj; ++jj) {
+        bool le = has, ge = has, lt = false;
+        FOR_K(kk) {
+          const int c = cg[kk][jj];
+          le = le && (sv[kk] <= c);
+          ge = ge && (c <= sv[kk]);
+          lt = lt || (c < sv[kk]);
+        }
+        if (ballot(le)) {
+          if (lane == 0) S.c_rej[cf[jj]] = 1;
+        } else if (ge && lt) {
+          prune = true;
+        }
+      }
+      if (prune) {
+        const int old = atomicOr(&fw[nr.off + (int64_t)d * nr.cap + e], PRUNED_BIT);
+        if (old >= 0) {
+          S.Lstate[old] = L_DEAD;
+          pruned++;
+        }
+      }
+    }
+  }
+  pruned = wave_sum64(pruned);
+  if (lane == 0 && pruned)
+    atomicAdd((unsigned long long*)&Sp->st[ST_PRUNED], (unsigned long long)pruned);
+}
+
+// Finish a big group (one wave): compact the frontier without its pruned
+// entries, append the accepted candidates, reset the node's group scratch.
+template <int DM>
+__global__ __launch_bounds__(NT_TILE) void k_group_finish(Slot* slots) {
+  Slot* Sp = &slots[blockIdx.y];
+  const Slot S = *Sp;
+  if (S.status != S_RUN) return;
+  const int nbig = S.nbig;
+  const int wave = threadIdx.x / WAVE, lane = lane_id();
+  const int d = S.d, cc = S.cand_cap;
+  int32_t* fw = S.fw;
+  int64_t gpairs = 0, fpairs = 0, fbytes = 0;
+  for (int bi = blockIdx.x * GP_WAVES + wave; bi < nbig; bi += gridDim.x * GP_WAVES) {
+    const int gid = S.big_list[bi];
+    const int v = S.grp_node[gid];
+    const int k = S.grp_cnt[v];
+    const int32_t* ord = S.order + S.grp_off[gid];
+    const NodeRec nr = S.node[v];
+    const int cnt = nr.count;
+    gpairs += (int64_t)k * (k - 1);
+    fpairs += (int64_t)k * cnt;
+    fbytes += (int64_t)cnt * 4 * d;
+    int64_t doff;
+    int dcap;
+    if (!frontier_dest(Sp, S, nr, cnt + k, d, &doff, &dcap)) break;
+    const bool moved = doff != nr.off;
+    int cursor = 0;
+    for (int t = 0; t < cnt; t += WAVE) {
+      const int e = t + lane;
+      const bool has = e < cnt;
+      const int slab = has ? fw[nr.off + (int64_t)d * nr.cap + e] : 0;
+      const bool keep = has && slab >= 0;
+      int32_t sv[DM];
+      FOR_K(kk) sv[kk] = keep ? fw[nr.off + (int64_t)kk * nr.cap + e] : 0;
+      const uint64_t hm = ballot(has), am = ballot(keep);
+      if (moved || cursor != t || am != hm) {
+        if (keep) {
+          const int64_t w = doff + cursor + rank_below(am);
+          FOR_K(kk) fw[w + (int64_t)kk * dcap] = sv[kk];
+          fw[w + (int64_t)d * dcap] = slab;
+        }
+      }
+      cursor += __popcll(am);
+    }
+    for (int ct = 0; ct < k; ct += WAVE) {
       const int j = ct + lane;
-      const bool have = j < ks;
+      const bool have = j < k;
       const int fj = have ? ord[j] : 0;
-      const bool acc = have && !S->c_rej[fj];
+      const bool acc = have && !S.c_rej[fj];
       const uint64_t m = ballot(acc);
       if (acc) {
         const int64_t w = doff + cursor + rank_below(m);
-        for (int kk = 0; kk < d; ++kk) fw[w + (int64_t)kk * dcap] = S->c_g[(size_t)kk * cc + fj];
+        FOR_K(kk) fw[w + (int64_t)kk * dcap] = S.c_g[(size_t)kk * cc + fj];
         fw[w + (int64_t)d * dcap] = -1;
-        S->c_fslot[fj] = w + (int64_t)d * dcap;
-        S->c_acc[fj] = 1;
+        S.c_fslot[fj] = w + (int64_t)d * dcap;
+        S.c_acc[fj] = 1;
       }
       cursor += __popcll(m);
     }
@@ -849,63 +1187,72 @@ __global__ __launch_bounds__(NT_TILE) void k_group_process(Slot* slots) {
       out.off = doff;
       out.cap = dcap;
       out.count = cursor;
-      S->node[v] = out;
-      S->grp_cnt[v] = 0;
-      S->grp_id[v] = -1;
+      S.node[v] = out;
+      S.grp_cnt[v] = 0;
+      S.grp_id[v] = -1;
     }
   }
-  // the per-group totals are wave-uniform: lane 0 publishes them
   if (lane == 0) {
-    if (gpairs) atomicAdd((unsigned long long*)&S->st[ST_GPAIRS], (unsigned long long)gpairs);
-    if (fpairs) atomicAdd((unsigned long long*)&S->st[ST_FPAIRS], (unsigned long long)fpairs);
-    if (fbytes) atomicAdd((unsigned long long*)&S->st[ST_FBYTES], (unsigned long long)fbytes);
-    if (pruned) atomicAdd((unsigned long long*)&S->st[ST_PRUNED], (unsigned long long)pruned);
+    if (gpairs) atomicAdd((unsigned long long*)&Sp->st[ST_GPAIRS], (unsigned long long)gpairs);
+    if (fpairs) atomicAdd((unsigned long long*)&Sp->st[ST_FPAIRS], (unsigned long long)fpairs);
+    if (fbytes) atomicAdd((unsigned long long*)&Sp->st[ST_FBYTES], (unsigned long long)fbytes);
   }
 }
 
 // ---------------------------------------------------------------- insert
 __global__ __launch_bounds__(NT_SLOT) void k_accept_scan(Slot* slots) {
-  Slot* S = &slots[blockIdx.x];
-  if (S->status != S_RUN) return;
+  Slot* Sp = &slots[blockIdx.x];
+  const Slot S = *Sp;
+  if (S.status != S_RUN) return;
   __shared__ int tmp[NT_SLOT / WAVE];
-  const int M = S->cand_n;
-  const int total = block_scan_array<NT_SLOT>(S->c_acc, S->c_rank, M, tmp);
+  const int M = S.cand_n;
+  int carry = 0;
+  for (int base = 0; base < M; base += NT_SLOT) {
+    const int i = base + threadIdx.x;
+    const int v = i < M ? S.c_acc[i] : 0;
+    int tot;
+    const int ex = block_exscan<NT_SLOT>(v, &tot, tmp);
+    if (i < M) S.c_rank[i] = carry + ex;
+    carry += tot;
+  }
   if (threadIdx.x == 0) {
-    S->accept_n = total;
-    if (S->n_labels + total > S->pool_cap || S->keep_n + total > S->open_cap) {
-      S->status = S_OVERFLOW;
-      S->err_line = __LINE__;
+    Sp->accept_n = carry;
+    if (S.n_labels + carry > S.pool_cap || S.keep_n + carry > S.open_cap) {
+      Sp->status = S_OVERFLOW;
+      Sp->err_line = __LINE__;
     }
   }
 }
 
+template <int DM>
 __global__ __launch_bounds__(NT_TILE) void k_insert(Slot* slots, GraphDev G) {
-  Slot* S = &slots[blockIdx.y];
-  if (S->status != S_RUN) return;
-  const int M = S->cand_n;
-  const int d = S->d, pc = S->pool_cap, cc = S->cand_cap;
-  const int base_id = S->n_labels, keep = S->keep_n;
-  int32_t* KF = S->open_f1[S->open_sel ^ 1];
-  int32_t* KL = S->open_lab[S->open_sel ^ 1];
+  Slot* Sp = &slots[blockIdx.y];
+  const Slot S = *Sp;
+  if (S.status != S_RUN) return;
+  const int M = S.cand_n;
+  const int d = S.d, pc = S.pool_cap, cc = S.cand_cap;
+  const int base_id = S.n_labels, keep = S.keep_n;
+  int32_t* KF = pick(S.open_f1, S.open_sel ^ 1);
+  int32_t* KL = pick(S.open_lab, S.open_sel ^ 1);
   int mn = INT32_MAX;
   for (int f = blockIdx.x * NT_TILE + threadIdx.x; f < M; f += gridDim.x * NT_TILE) {
-    if (!S->c_acc[f]) continue;
-    const int r = S->c_rank[f];
+    if (!S.c_acc[f]) continue;
+    const int r = S.c_rank[f];
     const int id = base_id + r;
-    const int v = S->c_node[f];
-    S->Lnode[id] = v;
-    S->Lpar[id] = S->c_par[f];
-    S->Larc[id] = S->c_arc[f];
-    S->Lstate[id] = L_OPEN;
-    for (int k = 0; k < d; ++k) S->Lg[(size_t)k * pc + id] = S->c_g[(size_t)k * cc + f];
-    S->fw[S->c_fslot[f]] = id;
-    const int f1 = S->c_g[f] + S->h[v];
+    const int v = S.c_node[f];
+    S.Lnode[id] = v;
+    S.Lpar[id] = S.c_par[f];
+    S.Larc[id] = S.c_arc[f];
+    S.Lstate[id] = L_OPEN;
+    FOR_K(k) S.Lg[(size_t)k * pc + id] = S.c_g[(size_t)k * cc + f];
+    S.fw[S.c_fslot[f]] = id;
+    const int f1 = S.c_g[f] + S.h[v];
     KF[keep + r] = f1;
     KL[keep + r] = id;
     mn = min(mn, f1);
   }
   mn = wave_min(mn);
-  if (lane_id() == 0 && mn != INT32_MAX) atomicMin(&S->lo_next, mn);
+  if (lane_id() == 0 && mn != INT32_MAX) atomicMin(&Sp->lo_next, mn);
 }
 
 __global__ void k_step_end(Slot* slots, int nslots) {
@@ -917,29 +1264,64 @@ __global__ void k_step_end(Slot* slots, int nslots) {
   S->st[ST_INSERTED] += S->accept_n;
   S->open_n = S->keep_n + S->accept_n;
   S->open_sel ^= 1;
-  if (S->rebase) S->lo = S->cur_min;
-  else if (S->open_n > 0) S->lo = S->lo_next;
-  S->cur_min = INT32_MAX;
+  if (S->open_n > 0) S->lo = S->lo_next;
   S->st[ST_STEPS] += 1;
   if (S->open_n == 0) S->status = S_DONE;
 }
 
 // ---------------------------------------------------------------- launchers
-void launch_step(const StepArgs& a, hipStream_t st) {
+const char* const kStepKernelNames[kStepKernels] = {
+    "k_open_hist",   "k_open_threshold", "k_open_scatter",  "k_batch_finalize", "k_goal_merge",
+    "k_popcheck",    "k_expand",         "k_pfilter",       "k_group_count",    "k_group_offsets",
+    "k_group_scatter", "k_group_process", "k_group_pairs",  "k_group_finish",   "k_accept_scan",
+    "k_insert",      "k_step_end"};
+
+template <int DM>
+static void launch_step_dm(const StepArgs& a, hipStream_t st, hipEvent_t* ev) {
   const dim3 tiled(a.gx, a.nslots), per(a.nslots);
-  hipLaunchKernelGGL(k_open_hist, tiled, dim3(NT_TILE), 0, st, a.slots, a.hist);
-  hipLaunchKernelGGL(k_open_threshold, per, dim3(NT_SLOT), 0, st, a.slots, a.hist);
-  hipLaunchKernelGGL(k_open_scatter, tiled, dim3(NT_TILE), 0, st, a.slots);
-  hipLaunchKernelGGL(k_batch_finalize, per, dim3(NT_SLOT), 0, st, a.slots, a.G);
-  hipLaunchKernelGGL(k_goal_merge, per, dim3(NT_SLOT), 0, st, a.slots);
-  hipLaunchKernelGGL(k_expand, tiled, dim3(NT_TILE), 0, st, a.slots, a.G);
-  hipLaunchKernelGGL(k_group_count, tiled, dim3(NT_TILE), 0, st, a.slots);
-  hipLaunchKernelGGL(k_group_offsets, per, dim3(NT_SLOT), 0, st, a.slots);
-  hipLaunchKernelGGL(k_group_scatter, tiled, dim3(NT_TILE), 0, st, a.slots);
-  hipLaunchKernelGGL(k_group_process, tiled, dim3(NT_TILE), 0, st, a.slots);
-  hipLaunchKernelGGL(k_accept_scan, per, dim3(NT_SLOT), 0, st, a.slots);
-  hipLaunchKernelGGL(k_insert, tiled, dim3(NT_TILE), 0, st, a.slots, a.G);
-  hipLaunchKernelGGL(k_step_end, dim3((a.nslots + 63) / 64), dim3(64), 0, st, a.slots, a.nslots);
+  int i = 0;
+  auto mark = [&]() {
+    if (ev) hipEventRecord(ev[i], st);
+    ++i;
+  };
+  mark(); hipLaunchKernelGGL(k_open_hist, tiled, dim3(NT_TILE), 0, st, a.slots, a.hist);
+  mark(); hipLaunchKernelGGL(k_open_threshold, per, dim3(NT_SLOT), 0, st, a.slots, a.hist);
+  mark(); hipLaunchKernelGGL(k_open_scatter, tiled, dim3(NT_TILE), 0, st, a.slots);
+  mark(); hipLaunchKernelGGL(k_batch_finalize<DM>, per, dim3(NT_SLOT), 0, st, a.slots, a.G);
+  mark(); hipLaunchKernelGGL(k_goal_merge<DM>, per, dim3(NT_SLOT), 0, st, a.slots);
+  mark(); hipLaunchKernelGGL(k_popcheck<DM>, tiled, dim3(NT_TILE), 0, st, a.slots, a.G);
+  mark(); hipLaunchKernelGGL(k_expand<DM>, tiled, dim3(NT_TILE), 0, st, a.slots, a.G);
+  mark(); hipLaunchKernelGGL(k_pfilter<DM>, tiled, dim3(NT_TILE), 0, st, a.slots, a.G);
+  mark(); hipLaunchKernelGGL(k_group_count, tiled, dim3(NT_TILE), 0, st, a.slots);
+  mark(); hipLaunchKernelGGL(k_group_offsets, per, dim3(NT_SLOT), 0, st, a.slots);
+  mark(); hipLaunchKernelGGL(k_group_scatter, tiled, dim3(NT_TILE), 0, st, a.slots);
+  mark(); hipLaunchKernelGGL(k_group_process<DM>, tiled, dim3(NT_TILE), 0, st, a.slots);
+  mark(); hipLaunchKernelGGL(k_group_pairs<DM>, tiled, dim3(NT_TILE), 0, st, a.slots);
+  mark(); hipLaunchKernelGGL(k_group_finish<DM>, tiled, dim3(NT_TILE), 0, st, a.slots);
+  mark(); hipLaunchKernelGGL(k_accept_scan, per, dim3(NT_SLOT), 0, st, a.slots);
+  mark(); hipLaunchKernelGGL(k_insert<DM>, tiled, dim3(NT_TILE), 0, st, a.slots, a.G);
+  mark(); hipLaunchKernelGGL(k_step_end, dim3((a.nslots + 63) / 64), dim3(64), 0, st, a.slots, a.nslots);
+  mark();
+}
+
+int dm_for(int d) {
+  if (d <= 2) return 2;
+  if (d <= 3) return 3;
+  if (d <= 4) return 4;
+  if (d <= 5) return 5;
+  if (d <= 6) return 6;
+  return 8;
+}
+
+void launch_step(const StepArgs& a, hipStream_t st, hipEvent_t* ev) {
+  switch (a.dm) {
+    case 2: launch_step_dm<2>(a, st, ev); break;
+    case 3: launch_step_dm<3>(a, st, ev); break;
+    case 4: launch_step_dm<4>(a, st, ev); break;
+    case 5: launch_step_dm<5>(a, st, ev); break;
+    case 6: launch_step_dm<6>(a, st, ev); break;
+    default: launch_step_dm<8>(a, st, ev); break;
+  }
 }
 
 }  // namespace mos

@@ -72,3 +72,67 @@ def test_config1_front(mos, seed):
     assert np.array_equal(r.costs.astype(np.int64), ref.costs)
     assert is_antichain(r.costs)
     check_paths(g, s, t, r.costs, r.paths, 3)
+
+
+@pytest.mark.parametrize("seed", [0, 3, 5, 8])
+def test_batch_of_one_pops_like_the_oracle(mos, seed):
+    """With B = 1 each step pops the single lexicographically smallest live
+    label, so the GPU processes exactly the labels sequential NAMOA* processes
+    (weak goal-front tests, PruneOPEN applied when a label is popped)."""
+    g = gen.grid_uniform(10, 10, 3, 1, 10, seed=seed)
+    r = _front(mos, g, 0, g.n - 1, batch_width=1)
+    ref = oracle.solve(g, 0, g.n - 1, flags=oracle.WEAK_P | oracle.LAZY_PRUNEOPEN)
+    assert np.array_equal(r.costs.astype(np.int64), ref.costs)
+    assert r.stats["pops"] == ref.stats["pops"]
+    assert r.stats["steps"] >= r.stats["pops"]
+
+
+def test_repeatable_paths(mos):
+    g, s, t = gen.config1(4)
+    a = _front(mos, g, s, t, batch_width=512)
+    b = _front(mos, g, s, t, batch_width=512)
+    assert np.array_equal(a.costs, b.costs)
+    assert all(np.array_equal(x, y) for x, y in zip(a.paths, b.paths))
+
+
+@pytest.mark.parametrize("size", [48, 96])
+def test_ship_grid_front(mos, size):
+    g, s, t = gen.config2(0, size=size)
+    r = _front(mos, g, s, t, batch_width=1024)
+    ref = oracle.solve(g, s, t, flags=oracle.WEAK_P | oracle.LAZY_PRUNEOPEN)
+    assert np.array_equal(r.costs.astype(np.int64), ref.costs)
+    check_paths(g, s, t, r.costs, r.paths, 3)
+
+
+def test_diamond_chain_large_front(mos):
+    g, s, t = gen.diamond_chain(12)
+    r = _front(mos, g, s, t, batch_width=256)
+    W = 2 ** 12 - 1
+    expect = np.array([[x, W - x] for x in range(2 ** 12)], dtype=np.int64)
+    assert np.array_equal(r.costs.astype(np.int64), expect)
+    check_paths(g, s, t, r.costs, r.paths, 2)
+
+
+def test_unreachable_and_trivial(mos):
+    g2 = gen.from_arcs(4, [0, 1, 2], [1, 0, 3], np.ones((3, 2), dtype=np.int64))
+    G = mos.Graph.from_gen(g2)
+    assert mos.mos_solve(G, 0, 3).costs.shape == (0, 2)
+    r = mos.mos_solve(G, 2, 2)
+    assert r.costs.tolist() == [[0, 0]] and len(r.paths[0]) == 0
+
+
+def test_session_matches_solve(mos):
+    g, s, t = gen.config1(1)
+    G = mos.Graph.from_gen(g)
+    ref = mos.mos_solve(G, s, t, batch_width=512)
+    sess = mos.Session(G, s, t, batch_width=512, profile_kernels=True)
+    done = sess.step(5)
+    st5 = sess.stats()
+    assert not done and st5["steps"] == 5
+    r = sess.result()
+    assert np.array_equal(r.costs, ref.costs)
+    assert all(np.array_equal(x, y) for x, y in zip(r.paths, ref.paths))
+    kt = sess.kernel_times()
+    assert kt["k_group_process"][1] >= r.stats["steps"]  # steps after the end are no-ops
+    assert sum(v[0] for v in kt.values()) > 0
+    sess.close()
