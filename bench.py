@@ -91,20 +91,30 @@ def main():
     avg_s = ms_dom / 1e3 / max(launches, 1)
     fb = s1["frontier_bytes"] - s0["frontier_bytes"]
     fb1 = s1["frontier_bytes_onepass"] - s0["frontier_bytes_onepass"]
-    if dom in ("k_group_process", "k_group_finish"):
-        # algorithmic bytes: 4d per (candidate group, live frontier entry) of
-        # the groups this kernel streams
-        per_launch = (fb1 if dom == "k_group_process" else fb - fb1) / max(launches, 1)
-        achieved = per_launch / avg_s / 1e9
-        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None}
+    if dom == "k_group_process":
+        # algorithmic bytes: 4d per (candidate group, live frontier entry);
+        # algorithmic ops: 2d int32 comparisons per candidate pair (<= both ways)
+        nbytes = fb1
+        nops = 2 * d * (s1["pairs_onepass"] - s0["pairs_onepass"])
+    elif dom == "k_group_finish":
+        nbytes, nops = fb - fb1, 0
     else:
-        # pair checks are d int32 comparisons each: ALU bound
-        pp = s1["p_pairs"] - s0["p_pairs"]
-        per_launch = pp * d / max(launches, 1)
-        achieved = per_launch / avg_s / 1e12
-        roof = {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": "TOP/s",
-                "frac": achieved / ALU_PEAK_TOPS, "traffic": None}
+        # goal-front pairs: d int32 comparisons each, operands staged in LDS
+        nbytes, nops = 0, d * (s1["p_pairs"] - s0["p_pairs"])
+    bw = nbytes / max(launches, 1) / avg_s / 1e9          # GB/s
+    ops = nops / max(launches, 1) / avg_s / 1e12          # TOP/s
+    # the binding roof follows the kernel's arithmetic intensity (ops per byte)
+    balance = ALU_PEAK_TOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
+    intensity = nops / nbytes if nbytes else float("inf")
+    if intensity > balance:
+        roof = {"bound": "alu", "achieved": ops, "peak": ALU_PEAK_TOPS, "unit": "TOP/s",
+                "frac": ops / ALU_PEAK_TOPS, "traffic": None}
+    else:
+        roof = {"bound": "hbm", "achieved": bw, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": bw / HBM_PEAK_GBS, "traffic": None}
+    roof["intensity_ops_per_byte"] = intensity
+    roof["hbm_gbs"] = bw
+    roof["alu_tops"] = ops
     roof["kernel"] = dom
     roof["avg_launch_us"] = avg_s * 1e6
     roof["launches"] = launches

@@ -99,6 +99,7 @@ typedef struct {
                               (the paper's PruneOPEN, applied lazily) */
   int64_t frontier_bytes_onepass; /* part of frontier_bytes from groups checked by one
                                      wave in a single pass */
+  int64_t pairs_onepass;   /* frontier + same-group pairs of those groups */
   double search_ms;        /* device time of the label steps */
   double heuristic_ms;     /* device time of the heuristic (reverse SSSP) */
 } mos_stats;

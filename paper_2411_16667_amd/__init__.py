@@ -48,7 +48,7 @@ class mos_stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in
                 ("pops", "goal_pops", "candidates", "p_pairs", "group_pairs", "frontier_pairs",
                  "inserted", "pruned", "steps", "front", "frontier_bytes", "killed",
-                 "frontier_bytes_onepass")] + \
+                 "frontier_bytes_onepass", "pairs_onepass")] + \
                [("search_ms", ctypes.c_double), ("heuristic_ms", ctypes.c_double)]
 
 
@@ -335,11 +335,14 @@ class Server:
         return t.value
 
     def poll(self, ticket):
-        """None while not ready, else (status, Result or None)."""
+        """None while not ready, else (status, Result or None); raises for an
+        unknown or already collected ticket."""
         h = _vp()
         st = _lib.mos_server_poll(self._h, ctypes.c_uint64(ticket), ctypes.byref(h))
         if st == MOS_E_NOT_READY:
             return None
+        if st == MOS_E_INVALID_ARG:
+            raise MosError(st, "mos_server_poll")
         return st, (_take_result(h) if st == MOS_OK else None)
 
     def wait(self, ticket, timeout_ms=-1):
@@ -347,6 +350,8 @@ class Server:
         st = _lib.mos_server_wait(self._h, ctypes.c_uint64(ticket), int(timeout_ms), ctypes.byref(h))
         if st == MOS_E_NOT_READY:
             return None
+        if st == MOS_E_INVALID_ARG:
+            raise MosError(st, "mos_server_wait")
         return st, (_take_result(h) if st == MOS_OK else None)
 
     def cancel(self, ticket):

@@ -603,6 +603,7 @@ class Engine {
     o.frontier_bytes = d.st[ST_FBYTES];
     o.killed = d.st[ST_KILLED];
     o.frontier_bytes_onepass = d.st[ST_FBYTES_WAVE];
+    o.pairs_onepass = d.st[ST_PAIRS_WAVE];
     o.search_ms = sh_[s].search_ms;
     o.heuristic_ms = sh_[s].heur_ms;
     return o;

@@ -48,6 +48,7 @@ enum Stat {
   ST_GROUPS,
   ST_KILLED,
   ST_FBYTES_WAVE,  // frontier bytes of the groups checked in one pass by one wave
+  ST_PAIRS_WAVE,   // candidate pairs (frontier + same group) of those groups
   NSTAT = 16
 };
 

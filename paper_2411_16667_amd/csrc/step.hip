@@ -856,18 +856,37 @@ __device__ __forceinline__ bool frontier_dest(Slot* Sp, const Slot& S, const Nod
 
 // ---------------------------------------------------------------- frontier check (small groups)
 // One wave per group (all candidates of this step with the same target node v,
-// at most one candidate per lane):
+// candidate i held by lane i, k <= 64):
 //  A. candidates against each other: c_i is dropped if some c_j <= c_i in every
 //     objective and (c_j != c_i or j precedes i in flat order);
-//  B. survivors against the live frontier of v, one frontier entry per lane,
-//     every entry loaded once (the next tile is loaded before the current one
-//     is compared): a candidate is rejected if an entry weakly dominates it
-//     (dominated or duplicate, Algorithm 1 lines 22-25); an entry is pruned if
-//     a survivor strictly dominates it (lines 26-28; a rejected candidate can
-//     dominate no live entry because the frontier is an antichain); pruned
-//     entries are marked dead in the pool and the block is compacted as it is
-//     streamed;
+//  B. survivors against the live frontier of v, U entries per lane per pass
+//     (the next pass is loaded before the current one is compared); each
+//     surviving candidate is broadcast from its lane: it is rejected if an entry
+//     weakly dominates it (dominated or duplicate, Algorithm 1 lines 22-25); an
+//     entry is pruned if a candidate strictly dominates it (lines 26-28; a
+//     rejected candidate can dominate no live entry because the frontier is an
+//     antichain, so no test on rejection is needed); pruned entries are marked
+//     dead in the pool and the block is compacted as it is streamed;
 //  C. accepted candidates are appended (a larger block is taken when needed).
+// Rejections live in a wave-uniform 64-bit mask; all compares are branch-free.
+constexpr int U = 4;  // frontier entries per lane per pass
+
+__device__ __forceinline__ int bcast(int v, int lane) { return __builtin_amdgcn_readlane(v, lane); }
+
+template <int DM>
+__device__ __forceinline__ void load_entries(const int32_t* fw, const NodeRec& nr, int d, int base,
+                                             int32_t (&sv)[U][DM], int32_t (&lab)[U]) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int e = base + u * WAVE + lane;
+    const bool has = e < nr.count;
+#pragma unroll
+    for (int k = 0; k < DM; ++k) sv[u][k] = (has && k < d) ? fw[nr.off + (int64_t)k * nr.cap + e] : 0;
+    lab[u] = has ? fw[nr.off + (int64_t)d * nr.cap + e] : 0;
+  }
+}
+
 template <int DM>
 __global__ __launch_bounds__(NT_TILE) void k_group_process(Slot* slots) {
   Slot* Sp = &slots[blockIdx.y];
@@ -875,12 +894,6 @@ __global__ __launch_bounds__(NT_TILE) void k_group_process(Slot* slots) {
   if (S.status != S_RUN) return;
   const int nsmall = S.nsmall;
   const int wave = threadIdx.x / WAVE, lane = lane_id();
-  __shared__ int32_t cg_all[GP_WAVES][DM][WAVE];
-  __shared__ int32_t cf_all[GP_WAVES][WAVE];
-  __shared__ int32_t cr_all[GP_WAVES][WAVE];
-  int32_t(*cg)[WAVE] = cg_all[wave];
-  int32_t* cf = cf_all[wave];
-  int32_t* cr = cr_all[wave];
   const int d = S.d, cc = S.cand_cap;
   int32_t* fw = S.fw;
   int64_t gpairs = 0, fpairs = 0, fbytes = 0, pruned = 0;
@@ -888,116 +901,111 @@ __global__ __launch_bounds__(NT_TILE) void k_group_process(Slot* slots) {
     const int gid = S.small_list[si];
     const int v = S.grp_node[gid];
     const int k = S.grp_cnt[v];  // <= WAVE for small groups
-    int32_t* ord = S.order + S.grp_off[gid];
-    // ---- A. intra-group resolution (one candidate tile)
+    const int32_t* ord = S.order + S.grp_off[gid];
     const bool have = lane < k;
     const int fi = have ? ord[lane] : 0;
     int32_t ci[DM];
-    FOR_K(kk) ci[kk] = have ? S.c_g[(size_t)kk * cc + fi] : 0;
-    wave_sync();
-    cf[lane] = fi;
-    FOR_K(kk) cg[kk][lane] = ci[kk];
-    wave_sync();
+#pragma unroll
+    for (int kk = 0; kk < DM; ++kk) ci[kk] = (have && kk < d) ? S.c_g[(size_t)kk * cc + fi] : 0;
+    const NodeRec nr = S.node[v];
+    const int cnt = nr.count;
+    // first frontier pass in flight while the candidates are resolved
+    int32_t sv[U][DM], slab[U];
+    load_entries<DM>(fw, nr, d, 0, sv, slab);
+    // ---- A. intra-group resolution
     bool rej = false;
     if (k > 1) {
       gpairs += (int64_t)k * (k - 1);
-      if (have)
-        for (int jj = 0; jj < k && !rej; ++jj) {
-          if (jj == lane) continue;
-          bool le = true, eq = true;
-          FOR_K(kk) {
-            const int b = cg[kk][jj];
-            le = le && (b <= ci[kk]);
-            eq = eq && (b == ci[kk]);
-          }
-          rej = le && (!eq || cf[jj] < fi);
+      for (int jj = 0; jj < k; ++jj) {
+        bool le = true, eq = true;
+#pragma unroll
+        for (int kk = 0; kk < DM; ++kk) {
+          const int b = bcast(ci[kk], jj);
+          le = le & (b <= ci[kk]);
+          eq = eq & (b == ci[kk]);
         }
+        const int fj = bcast(fi, jj);
+        rej = rej | (jj != lane && le && (!eq || fj < fi));
+      }
     }
-    // survivors to the front of the tile (LDS), in order
-    const uint64_t sm = ballot(have && !rej);
-    const int ks = __popcll(sm);
-    wave_sync();
-    if (have && !rej) {
-      const int p = rank_below(sm);
-      cf[p] = fi;
-      FOR_K(kk) cg[kk][p] = ci[kk];
-    }
-    if (lane < ks) cr[lane] = 0;
-    if (have && rej) S.c_rej[fi] = 1;
-    wave_sync();
+    const uint64_t surv = ballot(have && !rej);
+    const int ks = __popcll(surv);
     // ---- B. frontier check + prune + compaction
-    const NodeRec nr = S.node[v];
-    const int cnt = nr.count;
     int64_t doff;
     int dcap;
     if (!frontier_dest(Sp, S, nr, cnt + ks, d, &doff, &dcap)) break;
     const bool moved = doff != nr.off;
     fpairs += (int64_t)ks * cnt;
     fbytes += (int64_t)cnt * 4 * d;
+    uint64_t rejm = 0;  // surviving candidates rejected by the frontier
     int cursor = 0;
-    int32_t nv[DM];
-    int nlab = 0;
-    {
-      const bool h0 = lane < cnt;
-      FOR_K(kk) nv[kk] = h0 ? fw[nr.off + (int64_t)kk * nr.cap + lane] : 0;
-      nlab = h0 ? fw[nr.off + (int64_t)d * nr.cap + lane] : 0;
-    }
-    for (int t = 0; t < cnt; t += WAVE) {
-      const int e = t + lane;
-      const bool has = e < cnt;
-      int32_t sv[DM];
-      FOR_K(kk) sv[kk] = nv[kk];
-      const int slab = nlab;
-      {  // prefetch the next tile
-        const int e2 = e + WAVE;
-        const bool h2 = e2 < cnt;
-        FOR_K(kk) nv[kk] = h2 ? fw[nr.off + (int64_t)kk * nr.cap + e2] : 0;
-        nlab = h2 ? fw[nr.off + (int64_t)d * nr.cap + e2] : 0;
+    for (int t = 0; t < cnt; t += U * WAVE) {
+      int32_t cv[U][DM], clab[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+#pragma unroll
+        for (int kk = 0; kk < DM; ++kk) cv[u][kk] = sv[u][kk];
+        clab[u] = slab[u];
       }
-      bool prune = false;
-      for (int jj = 0; jj < ks; ++jj) {
-        if (cr[jj]) continue;  // uniform across the wave
-        bool le = has, ge = has, lt = false;
-        FOR_K(kk) {
-          const int c = cg[kk][jj];
-          le = le && (sv[kk] <= c);
-          ge = ge && (c <= sv[kk]);
-          lt = lt || (c < sv[kk]);
+      if (t + U * WAVE < cnt) load_entries<DM>(fw, nr, d, t + U * WAVE, sv, slab);
+      bool prune[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) prune[u] = false;
+      for (uint64_t m = surv & ~rejm; m; m &= m - 1) {
+        const int jj = __ffsll((long long)m) - 1;
+        int32_t c[DM];
+#pragma unroll
+        for (int kk = 0; kk < DM; ++kk) c[kk] = bcast(ci[kk], jj);
+        bool anyle = false;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          bool le = true, ge = true, lt = false;
+#pragma unroll
+          for (int kk = 0; kk < DM; ++kk) {
+            le = le & (cv[u][kk] <= c[kk]);
+            ge = ge & (c[kk] <= cv[u][kk]);
+            lt = lt | (c[kk] < cv[u][kk]);
+          }
+          const bool has = t + u * WAVE + lane < cnt;
+          anyle = anyle | (has & le);
+          prune[u] = prune[u] | (has & ge & lt);
         }
-        if (ballot(le)) {
-          if (lane == 0) cr[jj] = 1;
-          wave_sync();
-        } else if (ge && lt) {
-          prune = true;
-        }
+        if (ballot(anyle)) rejm |= 1ull << jj;
       }
-      if (prune) S.Lstate[slab] = L_DEAD;
-      const uint64_t hm = ballot(has);
-      const uint64_t am = ballot(has && !prune);
-      pruned += __popcll(hm & ~am);
-      if (moved || cursor != t || am != hm) {
-        if (has && !prune) {
-          const int64_t w = doff + cursor + rank_below(am);
-          FOR_K(kk) fw[w + (int64_t)kk * dcap] = sv[kk];
-          fw[w + (int64_t)d * dcap] = slab;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int tb = t + u * WAVE;
+        if (tb >= cnt) break;
+        const bool has = tb + lane < cnt;
+        if (prune[u]) S.Lstate[clab[u]] = L_DEAD;
+        const uint64_t hm = ballot(has);
+        const uint64_t am = ballot(has && !prune[u]);
+        pruned += __popcll(hm & ~am);
+        if (moved || cursor != tb || am != hm) {
+          if (has && !prune[u]) {
+            const int64_t w = doff + cursor + rank_below(am);
+#pragma unroll
+            for (int kk = 0; kk < DM; ++kk)
+              if (kk < d) fw[w + (int64_t)kk * dcap] = cv[u][kk];
+            fw[w + (int64_t)d * dcap] = clab[u];
+          }
         }
+        cursor += __popcll(am);
       }
-      cursor += __popcll(am);
     }
     // ---- C. append the accepted candidates
-    wave_sync();
-    const bool acc = lane < ks && !cr[lane];
-    const uint64_t m = ballot(acc);
-    if (lane < ks && !acc) S.c_rej[cf[lane]] = 1;
+    const uint64_t accm = surv & ~rejm;
+    const bool acc = (accm >> lane) & 1ull;
     if (acc) {
-      const int fj = cf[lane];
-      const int64_t w = doff + cursor + rank_below(m);
-      FOR_K(kk) fw[w + (int64_t)kk * dcap] = cg[kk][lane];
+      const int64_t w = doff + cursor + rank_below(accm);
+#pragma unroll
+      for (int kk = 0; kk < DM; ++kk)
+        if (kk < d) fw[w + (int64_t)kk * dcap] = ci[kk];
       fw[w + (int64_t)d * dcap] = -1;
-      S.c_fslot[fj] = w + (int64_t)d * dcap;
-      S.c_acc[fj] = 1;
+      S.c_fslot[fi] = w + (int64_t)d * dcap;
+      S.c_acc[fi] = 1;
     }
-    cursor += __popcll(m);
+    cursor += __popcll(accm);
     if (lane == 0) {
       NodeRec out;
       out.off = doff;
@@ -1012,6 +1020,8 @@ __global__ __launch_bounds__(NT_TILE) void k_group_process(Slot* slots) {
   if (lane == 0) {
     if (gpairs) atomicAdd((unsigned long long*)&Sp->st[ST_GPAIRS], (unsigned long long)gpairs);
     if (fpairs) atomicAdd((unsigned long long*)&Sp->st[ST_FPAIRS], (unsigned long long)fpairs);
+    if (gpairs + fpairs)
+      atomicAdd((unsigned long long*)&Sp->st[ST_PAIRS_WAVE], (unsigned long long)(gpairs + fpairs));
     if (fbytes) {
       atomicAdd((unsigned long long*)&Sp->st[ST_FBYTES], (unsigned long long)fbytes);
       atomicAdd((unsigned long long*)&Sp->st[ST_FBYTES_WAVE], (unsigned long long)fbytes);
@@ -1021,7 +1031,7 @@ __global__ __launch_bounds__(NT_TILE) void k_group_process(Slot* slots) {
 }
 
 // ---------------------------------------------------------------- big groups
-// Pair tiles of the big groups, one wave per tile:
+// Pair tiles of the big groups, one wave per tile, both operands in lanes:
 //   A-tiles (candidate tile I x candidate tile J): a candidate of I is rejected
 //     if a candidate of J weakly dominates it (ties: smaller flat index stays);
 //   B-tiles (frontier tile T x candidate tile J): a candidate is rejected if an
@@ -1038,10 +1048,6 @@ __global__ __launch_bounds__(NT_TILE) void k_group_pairs(Slot* slots) {
   if (S.status != S_RUN) return;
   const int total = S.big_tiles, nbig = S.nbig;
   const int wave = threadIdx.x / WAVE, lane = lane_id();
-  __shared__ int32_t cg_all[GP_WAVES][DM][WAVE];
-  __shared__ int32_t cf_all[GP_WAVES][WAVE];
-  int32_t(*cg)[WAVE] = cg_all[wave];
-  int32_t* cf = cf_all[wave];
   const int d = S.d, cc = S.cand_cap;
   int32_t* fw = S.fw;
   int64_t pruned = 0;
@@ -1060,55 +1066,56 @@ __global__ __launch_bounds__(NT_TILE) void k_group_pairs(Slot* slots) {
     const bool is_a = local < nct * nct;
     const int rest = is_a ? local : local - nct * nct;
     const int I = rest / nct, J = rest % nct;
+    // candidate tile J, one candidate per lane
     const int j = J * WAVE + lane;
-    wave_sync();
-    if (j < k) {
-      const int fj = ord[j];
-      cf[lane] = fj;
-      FOR_K(kk) cg[kk][lane] = S.c_g[(size_t)kk * cc + fj];
-    }
-    wave_sync();
+    const bool hj = j < k;
+    const int fj = hj ? ord[j] : 0;
+    int32_t cj[DM];
+#pragma unroll
+    for (int kk = 0; kk < DM; ++kk) cj[kk] = (hj && kk < d) ? S.c_g[(size_t)kk * cc + fj] : 0;
     const int nj = min(WAVE, k - J * WAVE);
     if (is_a) {
       const int i = I * WAVE + lane;
-      if (i < k) {
-        const int fi = ord[i];
-        int32_t ci[DM];
-        FOR_K(kk) ci[kk] = S.c_g[(size_t)kk * cc + fi];
-        bool rej = false;
-        for (int jj = 0; jj < nj && !rej; ++jj) {
-          if (cf[jj] == fi) continue;
-          bool le = true, eq = true;
-          FOR_K(kk) {
-            const int b = cg[kk][jj];
-            le = le && (b <= ci[kk]);
-            eq = eq && (b == ci[kk]);
-          }
-          rej = le && (!eq || cf[jj] < fi);
+      const bool hi = i < k;
+      const int fi = hi ? ord[i] : 0;
+      int32_t ci[DM];
+#pragma unroll
+      for (int kk = 0; kk < DM; ++kk) ci[kk] = (hi && kk < d) ? S.c_g[(size_t)kk * cc + fi] : 0;
+      bool rej = false;
+      for (int jj = 0; jj < nj; ++jj) {
+        bool le = true, eq = true;
+#pragma unroll
+        for (int kk = 0; kk < DM; ++kk) {
+          const int b = bcast(cj[kk], jj);
+          le = le & (b <= ci[kk]);
+          eq = eq & (b == ci[kk]);
         }
-        if (rej) S.c_rej[fi] = 1;
+        const int fb = bcast(fj, jj);
+        rej = rej | (fb != fi && le && (!eq || fb < fi));
       }
+      if (hi && rej) S.c_rej[fi] = 1;
     } else {
       const NodeRec nr = S.node[v];
       const int e = I * WAVE + lane;
       const bool has = e < nr.count;
       int32_t sv[DM];
-      FOR_K(kk) sv[kk] = has ? fw[nr.off + (int64_t)kk * nr.cap + e] : 0;
+#pragma unroll
+      for (int kk = 0; kk < DM; ++kk) sv[kk] = (has && kk < d) ? fw[nr.off + (int64_t)kk * nr.cap + e] : 0;
       bool prune = false;
+      uint64_t rejm = 0;
       for (int jj = 0; jj < nj; ++jj) {
         bool le = has, ge = has, lt = false;
-        FOR_K(kk) {
-          const int c = cg[kk][jj];
-          le = le && (sv[kk] <= c);
-          ge = ge && (c <= sv[kk]);
-          lt = lt || (c < sv[kk]);
+#pragma unroll
+        for (int kk = 0; kk < DM; ++kk) {
+          const int c = bcast(cj[kk], jj);
+          le = le & (sv[kk] <= c);
+          ge = ge & (c <= sv[kk]);
+          lt = lt | (c < sv[kk]);
         }
-        if (ballot(le)) {
-          if (lane == 0) S.c_rej[cf[jj]] = 1;
-        } else if (ge && lt) {
-          prune = true;
-        }
+        if (ballot(le)) rejm |= 1ull << jj;
+        prune = prune | (ge & lt);
       }
+      if ((rejm >> lane) & 1ull) S.c_rej[fj] = 1;
       if (prune) {
         const int old = atomicOr(&fw[nr.off + (int64_t)d * nr.cap + e], PRUNED_BIT);
         if (old >= 0) {
