@@ -259,7 +259,7 @@ static bool plan_layout(const mos_graph* g, int d, int B, int64_t budget, int64_
   if (budget <= fixed) return false;
   // bytes per pooled label: pool (node, parent, arc, g, state) + OPEN 2x(F1,
   // lab) + tie set (F1, lab, state) + frontier 3*(d+1) words + goal front share
-  const double per = (12.0 + 4.0 * d + 1.0) + 16.0 + 12.0 + 12.0 * (d + 1) + (8.0 * (d + 1) + 8.0) / 8.0;
+  const double per = (12.0 + 4.0 * d + 1.0) + 32.0 + 12.0 + 12.0 * (d + 1) + (8.0 * (d + 1) + 8.0) / 8.0;
   int64_t pool = (int64_t)((double)(budget - fixed - 32 * 256) / per);
   pool = std::min<int64_t>(pool, (int64_t)1 << 30);
   if (label_limit > 0) pool = std::min<int64_t>(pool, label_limit);
@@ -271,7 +271,7 @@ static bool plan_layout(const mos_graph* g, int d, int B, int64_t budget, int64_
   L->fw_cap = 3 * (int64_t)(d + 1) * pool + (int64_t)MINCAP * (d + 1);
   int64_t b = fixed;
   b += 3 * al(4 * pool) + al(4 * (int64_t)d * pool) + al(pool);  // pool
-  b += 4 * al(4 * pool);                                          // OPEN
+  b += 8 * al(4 * pool);                                          // OPEN near + far tiers
   b += 3 * al(4 * pool);                                          // tie set
   b += 2 * (al(4 * (int64_t)d * L->P_cap) + al(4 * (int64_t)L->P_cap)) + al(8 * ((int64_t)L->P_cap + 1));
   b += al(4 * L->fw_cap);
@@ -321,6 +321,8 @@ static void carve(Slot& s, char* base, const Layout& L, int64_t n, int d) {
   for (int b = 0; b < 2; ++b) {
     s.open_f1[b] = (int32_t*)take(4 * (int64_t)L.open_cap);
     s.open_lab[b] = (int32_t*)take(4 * (int64_t)L.open_cap);
+    s.far_f1[b] = (int32_t*)take(4 * (int64_t)L.open_cap);
+    s.far_lab[b] = (int32_t*)take(4 * (int64_t)L.open_cap);
   }
   s.tie_f1 = (int32_t*)take(4 * (int64_t)L.tie_cap);
   s.tie_lab = (int32_t*)take(4 * (int64_t)L.tie_cap);
@@ -392,7 +394,8 @@ class Engine {
     // MOS_PROGRESS=1 prints the state of resident queries every few seconds
     // from the poll loop (long single solves otherwise run silently).
     const char* pr = std::getenv("MOS_PROGRESS");
-    progress_ = pr && pr[0] == '1';
+    progress_ = pr && (pr[0] == '1' || pr[0] == '2');
+    progress_level_ = progress_ ? pr[0] - '0' : 0;
     t_last_ = std::chrono::steady_clock::now();
   }
 
@@ -620,12 +623,18 @@ class Engine {
       if (!sh_[s].busy) continue;
       const Slot& d = hslots_[s];
       std::fprintf(stderr,
-                   "[mos] slot %d query %lld: steps %lld pops %lld labels %d open %d front %d "
+                   "[mos] slot %d query %lld: steps %lld pops %lld labels %d open %d+%d front %d "
                    "frontier words %lld/%lld search %.0f ms\n",
                    s, (long long)sh_[s].q.id, (long long)d.st[ST_STEPS], (long long)d.st[ST_POPS],
-                   d.n_labels, d.open_n, d.P_n, (long long)d.fw_top, (long long)d.fw_cap,
+                   d.n_labels, d.open_n, d.far_n, d.P_n, (long long)d.fw_top, (long long)d.fw_cap,
                    sh_[s].search_ms);
       ++shown;
+    }
+    if (progress_level_ > 1) {
+      const Slot& d = hslots_[0];
+      std::fprintf(stderr, "[mos] phase ticks:");
+      for (int i = 0; i < 8; ++i) std::fprintf(stderr, " %lld", (long long)d.st[ST_T0 + i]);
+      std::fprintf(stderr, "\n");
     }
     std::fprintf(stderr, "[mos] resident %d\n", busy_count());
     std::fflush(stderr);
@@ -836,6 +845,7 @@ class Engine {
   bool graph_failed_ = false;
   bool use_graph_ = true;
   bool progress_ = false;
+  int progress_level_ = 0;
   bool profile_ = false;
   std::vector<hipEvent_t> pev_;
   int ring_head_ = 0, ring_used_ = 0;

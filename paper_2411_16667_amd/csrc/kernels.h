@@ -22,7 +22,7 @@ int dm_for(int d);
 // One batched label step over every resident slot: a fixed sequence of
 // kStepKernels kernels.  With ev != nullptr, ev[i] is recorded before kernel i
 // and ev[kStepKernels] after the last one (kStepKernels + 1 events).
-constexpr int kStepKernels = 17;
+constexpr int kStepKernels = 19;
 extern const char* const kStepKernelNames[kStepKernels];
 void launch_step(const StepArgs& a, hipStream_t st, hipEvent_t* ev = nullptr);
 

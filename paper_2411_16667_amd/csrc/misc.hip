@@ -122,6 +122,13 @@ __global__ void k_slot_seed(Slot* slots, int s, GraphDev G) {
   S->open_lab[0][0] = 0;
   S->open_n = 1;
   S->open_sel = 0;
+  S->far_n = 0;
+  S->far_sel = 0;
+  S->t_all = 1;  // OPEN starts as one near tier; spills create the far tier
+  S->T = INT32_MAX;
+  S->refill = 0;
+  S->blocks_a = 0;
+  S->blocks_b = 0;
   S->lo = S->h[st];
   S->st[ST_INSERTED] = 1;
   S->status = S_RUN;

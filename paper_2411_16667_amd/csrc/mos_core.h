@@ -15,10 +15,13 @@ namespace mos {
 
 constexpr int MAXD = 8;           // objectives supported by the kernels
 constexpr int NB = 4096;          // OPEN histogram bins: exact F1 values lo..lo+NB-2, then overflow
-constexpr int TIECAP = 1024;      // tie sets up to this size are ordered in LDS; larger ones
+constexpr int TIECAP = 256;       // tie sets up to this size are ranked in LDS; larger ones
                                   // are first narrowed by exact radix refinement
 constexpr int MINCAP = 8;         // smallest frontier block, in entries
 constexpr int BATCH_SORT = 8192;  // largest popped batch (LDS sort by label id)
+// near-tier sizing, in multiples of B: refill below LOW, refill up to TARGET,
+// spill to far above HIGH (keeping TARGET)
+constexpr int NEAR_LOW = 4, NEAR_TARGET = 16, NEAR_HIGH = 48;
 constexpr int32_t UNREACH = INT32_MAX;  // heuristic of a node that cannot reach the goal
 constexpr int WAVE = 64;
 constexpr int64_t BIG_WORK = 64 * 1024;  // pair checks above which a group is split across waves
@@ -49,7 +52,8 @@ enum Stat {
   ST_KILLED,
   ST_FBYTES_WAVE,  // frontier bytes of the groups checked in one pass by one wave
   ST_PAIRS_WAVE,   // candidate pairs (frontier + same group) of those groups
-  NSTAT = 16
+  ST_T0 = 16,      // ST_T0..ST_T0+7: phase timers (constant-rate device clock ticks)
+  NSTAT = 24
 };
 
 // Frontier record of one node: the node's live labels are entries [0, count)
@@ -89,8 +93,10 @@ struct Slot {
   int32_t* Larc;       //   arc that created the label (-1 for the start label)
   int32_t* Lg;         //   d planes of pool_cap: g vectors
   uint8_t* Lstate;     //   LabelState
-  int32_t* open_f1[2]; // open_cap each: F1 of the open entry
-  int32_t* open_lab[2];//   label id of the open entry
+  int32_t* open_f1[2]; // open_cap each: near tier of OPEN (F1 < T): F1 of the entry
+  int32_t* open_lab[2];//   label id of the entry
+  int32_t* far_f1[2];  // open_cap each: far tier of OPEN (F1 >= T)
+  int32_t* far_lab[2];
   int32_t* Pg[2];      // d planes of P_cap each: goal front, lexicographically ascending
   int32_t* Plab[2];    //   label id of each goal-front entry
   int32_t* pscr;       // 2*(P_cap+1): goal-merge scratch (prune flags, survivor prefix)
@@ -127,6 +133,11 @@ struct Slot {
   int32_t batch_n, goal_n, reg_n, cand_n;
   int32_t ngroups, tie_n, keep_n, accept_n;
   int32_t nsmall, nbig, big_tiles, err_line;
+  // two-tier OPEN: near holds F1 < T (all of OPEN while t_all), far holds F1 >= T
+  int32_t far_n, far_sel, T, t_all;
+  int32_t refill, r_T, r_all, r_moved;  // refill of near from far, decided per step
+  int32_t r_keep, lo_refill, blocks_a, blocks_b;
+  int32_t spill_T, spill_on, accept_near, accept_far;
 
   int64_t st[NSTAT];
 };

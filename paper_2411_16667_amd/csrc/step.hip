@@ -61,8 +61,196 @@ __device__ int block_exscan(int v, int* total, int* tmp /* >= NT/64 ints */) {
   return before + x - v;
 }
 
+// Bitonic sort of E*NT int keys held in registers (thread t holds elements
+// t*E .. t*E+E-1): partners inside a thread are compared in registers,
+// partners in the same wave through lane shuffles, and only partners in other
+// waves through LDS (lds: E*NT ints).
+template <int E, int NT>
+__device__ void bitonic_sort_blocked(int (&v)[E], int* lds) {
+  const int t = threadIdx.x;
+  constexpr int n = E * NT;
+  for (int k = 2; k <= n; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      if (j < E) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          const int p = e ^ j;
+          if (p > e) {
+            const bool asc = ((t * E + e) & k) == 0;
+            const int a = v[e], b = v[p];
+            const bool sw = asc ? (b < a) : (a < b);
+            v[e] = sw ? b : a;
+            v[p] = sw ? a : b;
+          }
+        }
+      } else if (j < E * WAVE) {
+        const int lm = j / E;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          const int i = t * E + e;
+          const int other = __shfl_xor(v[e], lm);
+          const bool keep_min = (((i & j) == 0) == ((i & k) == 0));
+          v[e] = keep_min ? min(v[e], other) : max(v[e], other);
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < E; ++e) lds[t * E + e] = v[e];
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          const int i = t * E + e;
+          const int other = lds[i ^ j];
+          const bool keep_min = (((i & j) == 0) == ((i & k) == 0));
+          v[e] = keep_min ? min(v[e], other) : max(v[e], other);
+        }
+        __syncthreads();
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- OPEN tiers
+// OPEN is split by a threshold T on F1: the near tier (F1 < T) is scanned by
+// every pop; the far tier (F1 >= T) is only touched when the near tier runs
+// low (refill, below) or grows too large (spill, in k_open_scatter).  Every far
+// entry has a larger F1 than every near entry, so a pop from the near tier is
+// still an exact lexicographic prefix of all of OPEN.
+//
+// The per-slot decision of a tiled kernel is taken by its last workgroup to
+// finish (an atomic count of finished workgroups; all of them take part).
+__device__ __forceinline__ bool last_block(int32_t* counter) {
+  __shared__ bool is_last;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) is_last = atomicAdd(counter, 1) == (int)gridDim.x - 1;
+  __syncthreads();
+  if (is_last) __threadfence();
+  return is_last;
+}
+
+// Refill, part 1: histogram of the live far entries over F1 - T; the last
+// workgroup picks the refill threshold r_T so that the near tier grows back
+// to about NEAR_TARGET * B entries (or takes the whole far tier).
+__global__ __launch_bounds__(NT_TILE) void k_far_hist(Slot* slots, int32_t* hist) {
+  Slot* Sp = &slots[blockIdx.y];
+  const Slot S = *Sp;
+  if (S.status != S_RUN || !S.refill) return;
+  __shared__ int32_t h[NB];
+  __shared__ int tmp[NT_TILE / WAVE];
+  for (int i = threadIdx.x; i < NB; i += NT_TILE) h[i] = 0;
+  __syncthreads();
+  const int n = S.far_n, T = S.T;
+  const int32_t* F1 = pick(S.far_f1, S.far_sel);
+  const int32_t* LB = pick(S.far_lab, S.far_sel);
+  for (int i = blockIdx.x * NT_TILE + threadIdx.x; i < n; i += gridDim.x * NT_TILE)
+    if (S.Lstate[LB[i]] == L_OPEN) atomicAdd(&h[min(F1[i] - T, NB - 1)], 1);
+  __syncthreads();
+  int32_t* gh = hist + (size_t)blockIdx.y * NB;
+  for (int i = threadIdx.x; i < NB; i += NT_TILE)
+    if (h[i]) atomicAdd(&gh[i], h[i]);
+  if (!last_block(&Sp->blocks_a)) return;
+  constexpr int PER = NB / NT_TILE;
+  int loc[PER], sum = 0;
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    loc[j] = gh[threadIdx.x * PER + j];
+    gh[threadIdx.x * PER + j] = 0;
+    sum += loc[j];
+  }
+  int total;
+  int ex = block_exscan<NT_TILE>(sum, &total, tmp);
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    ex += loc[j];
+    h[threadIdx.x * PER + j] = ex;  // inclusive
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int target = max(S.B, NEAR_TARGET * S.B - S.open_n);
+    int r_all = 0, r_T = T;
+    if (total <= target || h[NB - 2] == 0) {
+      r_all = 1;
+    } else {
+      int lo_i = 0, hi_i = NB - 1;
+      while (lo_i < hi_i) {
+        const int mid = (lo_i + hi_i) >> 1;
+        if (h[mid] >= target) hi_i = mid; else lo_i = mid + 1;
+      }
+      r_T = T + min(lo_i + 1, NB - 1);
+    }
+    Sp->r_all = r_all;
+    Sp->r_T = r_T;
+    Sp->r_moved = 0;
+    Sp->r_keep = 0;
+    Sp->lo_refill = INT32_MAX;
+    Sp->blocks_a = 0;
+  }
+}
+
+// Refill, part 2: live far entries below r_T join the near tier, the rest is
+// compacted into the other far buffer (dead entries vanish); the last
+// workgroup publishes the new tier sizes and threshold.
+__global__ __launch_bounds__(NT_TILE) void k_far_move(Slot* slots) {
+  Slot* Sp = &slots[blockIdx.y];
+  const Slot S = *Sp;
+  if (S.status != S_RUN || !S.refill) return;
+  const int n = S.far_n, base = S.open_n, r_T = S.r_T, r_all = S.r_all;
+  const int32_t* F1 = pick(S.far_f1, S.far_sel);
+  const int32_t* LB = pick(S.far_lab, S.far_sel);
+  int32_t* KF = pick(S.far_f1, S.far_sel ^ 1);
+  int32_t* KL = pick(S.far_lab, S.far_sel ^ 1);
+  int32_t* NF = pick(S.open_f1, S.open_sel);
+  int32_t* NLb = pick(S.open_lab, S.open_sel);
+  int mn = INT32_MAX;
+  for (int b0 = blockIdx.x * NT_TILE; b0 < n; b0 += gridDim.x * NT_TILE) {
+    const int i = b0 + threadIdx.x;
+    int f = 0, lab = 0;
+    bool live = false;
+    if (i < n) {
+      f = F1[i];
+      lab = LB[i];
+      live = S.Lstate[lab] == L_OPEN;
+    }
+    const bool move = live && (r_all || f < r_T);
+    const bool keep = live && !move;
+    int p = agg_append(&Sp->r_moved, move);
+    if (move && base + p < S.open_cap) {
+      NF[base + p] = f;
+      NLb[base + p] = lab;
+      mn = min(mn, f);
+    }
+    p = agg_append(&Sp->r_keep, keep);
+    if (keep && p < S.open_cap) {
+      KF[p] = f;
+      KL[p] = lab;
+    }
+  }
+  mn = wave_min(mn);
+  if (lane_id() == 0 && mn != INT32_MAX) atomicMin(&Sp->lo_refill, mn);
+  if (!last_block(&Sp->blocks_b)) return;
+  if (threadIdx.x == 0) {
+    const int moved = Sp->r_moved, kept = Sp->r_keep;
+    Sp->open_n = base + moved;
+    Sp->far_n = kept;
+    Sp->far_sel = S.far_sel ^ 1;
+    if (r_all) {
+      Sp->t_all = 1;
+      Sp->T = INT32_MAX;
+    } else {
+      Sp->T = r_T;
+    }
+    if (moved > 0) Sp->lo = base > 0 ? min(S.lo, Sp->lo_refill) : Sp->lo_refill;
+    if (base + moved > S.open_cap || kept > S.open_cap) {
+      Sp->status = S_OVERFLOW;
+      Sp->err_line = __LINE__;
+    }
+    Sp->refill = 0;
+    Sp->blocks_b = 0;
+  }
+}
+
 // ---------------------------------------------------------------- pop
-// Histogram of live OPEN entries over F1 (bin = F1 - lo, width 1, last bin = overflow).
+// Histogram of live near entries over F1 (bin = F1 - lo, width 1, last bin = overflow).
 __global__ __launch_bounds__(NT_TILE) void k_open_hist(Slot* slots, int32_t* hist) {
   const Slot S = slots[blockIdx.y];
   if (S.status != S_RUN) return;
@@ -131,6 +319,20 @@ __global__ __launch_bounds__(NT_SLOT) void k_open_threshold(Slot* slots, int32_t
         mode = 1;
       }
     }
+    // spill: a near tier above NEAR_HIGH * B live entries keeps its lowest
+    // NEAR_TARGET * B (whole F1 values); the rest moves to the far tier
+    if (total > NEAR_HIGH * B) {
+      const int keep = NEAR_TARGET * B;
+      int lo_i = 0, hi_i = NB - 1;
+      while (lo_i < hi_i) {
+        const int mid = (lo_i + hi_i) >> 1;
+        if (cum[mid] >= keep) hi_i = mid; else lo_i = mid + 1;
+      }
+      if (lo_i < NB - 2) {
+        Sp->T = Sp->lo + lo_i + 1;
+        Sp->t_all = 0;
+      }
+    }
     Sp->t_star = t_star;
     Sp->r_tie = r;
     Sp->tie_mode = mode;
@@ -153,6 +355,8 @@ __global__ __launch_bounds__(NT_TILE) void k_open_scatter(Slot* slots) {
   const int32_t* LB = pick(S.open_lab, sel);
   int32_t* KF = pick(S.open_f1, sel ^ 1);
   int32_t* KL = pick(S.open_lab, sel ^ 1);
+  int32_t* FF = pick(S.far_f1, S.far_sel);
+  int32_t* FL = pick(S.far_lab, S.far_sel);
   const int stride = gridDim.x * NT_TILE;
   int kmin = INT32_MAX;
   for (int base = blockIdx.x * NT_TILE; base < n; base += stride) {
@@ -176,11 +380,18 @@ __global__ __launch_bounds__(NT_TILE) void k_open_scatter(Slot* slots) {
       S.tie_f1[p] = f;
       S.tie_lab[p] = lab;
     }
-    p = agg_append(&Sp->keep_n, to_keep);
-    if (to_keep && p < S.open_cap) {
+    const bool to_far = to_keep && !S.t_all && f >= S.T;  // spilled this step
+    const bool to_near = to_keep && !to_far;
+    p = agg_append(&Sp->keep_n, to_near);
+    if (to_near && p < S.open_cap) {
       KF[p] = f;
       KL[p] = lab;
       kmin = min(kmin, f);
+    }
+    p = agg_append(&Sp->far_n, to_far);
+    if (to_far && p < S.open_cap) {
+      FF[p] = f;
+      FL[p] = lab;
     }
   }
   kmin = wave_min(kmin);
@@ -192,6 +403,21 @@ __device__ __forceinline__ int key_word(const Slot& S, const GraphDev& G, int la
   const int v = S.Lnode[lab];
   if (w >= S.d) return v;
   return S.Lg[(size_t)w * S.pool_cap + lab] + S.h[(size_t)w * G.n + v];
+}
+
+// Sort the popped label ids ascending into V[0 .. E*NT_SLOT) (padding at the end).
+template <int E>
+__device__ void sort_batch(const Slot& S, int nb, int32_t* V) {
+  int v[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int i = threadIdx.x * E + e;
+    v[e] = i < nb ? S.batch[i] : INT32_MAX;
+  }
+  bitonic_sort_blocked<E, NT_SLOT>(v, V);
+#pragma unroll
+  for (int e = 0; e < E; ++e) V[threadIdx.x * E + e] = v[e];
+  __syncthreads();
 }
 
 // Finish the pop: exact selection inside the tie bin, canonical batch order
@@ -206,6 +432,7 @@ __global__ __launch_bounds__(NT_SLOT) void k_batch_finalize(Slot* slots, GraphDe
   __shared__ int sh_a, sh_b;
   const int d = S.d;
   int nb = S.batch_n, keep_n = S.keep_n;
+  const uint64_t c0 = wall_clock64();
   if (S.tie_mode) {
     // ---- threshold bin: take exactly the r_tie lexicographically smallest of
     // its entries by (F_1..F_d, node).  While more than TIECAP remain
@@ -281,60 +508,59 @@ __global__ __launch_bounds__(NT_SLOT) void k_batch_finalize(Slot* slots, GraphDe
         if (TS[i] == 0) TS[i] = fill;
       __syncthreads();
     } else {
-      // compact the undecided (<= TIECAP) and sort them by full key in LDS
-      int32_t* K = lds;                          // (d+1) planes of TIECAP
-      int32_t* idx = lds + (MAXD + 1) * TIECAP;  // positions into the tie arrays
+      // the undecided (<= TIECAP): the rank of each one by full key decides it;
+      // keys are packed as int4 words (padding words are equal for everyone)
+      constexpr int KW = (DM + 1 + 3) / 4;
+      int4* K4 = reinterpret_cast<int4*>(lds);          // TIECAP x KW words
+      int32_t* idx = lds + 4 * KW * TIECAP;              // positions into the tie arrays
       int cnt = 0;
       for (int base = 0; base < n; base += NT_SLOT) {
         const int i = base + threadIdx.x;
         const int u = (i < n && TS[i] == 0) ? 1 : 0;
         int tt;
         const int p = block_exscan<NT_SLOT>(u, &tt, tmp);
-        if (u) idx[cnt + p] = i;
+        if (u && cnt + p < TIECAP) idx[cnt + p] = i;
         cnt += tt;
       }
       __syncthreads();
-      int n2 = 1;
-      while (n2 < cnt) n2 <<= 1;
-      for (int i = threadIdx.x; i < n2; i += NT_SLOT) {
-        if (i < cnt) {
-          const int lab = S.tie_lab[idx[i]];
-          const int v = S.Lnode[lab];
-          FOR_K(k) K[k * TIECAP + i] = S.Lg[(size_t)k * S.pool_cap + lab] + S.h[(size_t)k * G.n + v];
-          K[d * TIECAP + i] = v;
-        } else {
-          for (int k = 0; k <= d; ++k) K[k * TIECAP + i] = INT32_MAX;
-          idx[i] = -1;
-        }
+      if (threadIdx.x < cnt) {
+        const int i = threadIdx.x;
+        const int lab = S.tie_lab[idx[i]];
+        const int v = S.Lnode[lab];
+        int32_t key[KW * 4];
+#pragma unroll
+        for (int k = 0; k < KW * 4; ++k)
+          key[k] = k < d ? S.Lg[(size_t)k * S.pool_cap + lab] + S.h[(size_t)k * G.n + v]
+                         : (k == d ? v : 0);
+#pragma unroll
+        for (int w = 0; w < KW; ++w)
+          K4[i * KW + w] = make_int4(key[4 * w], key[4 * w + 1], key[4 * w + 2], key[4 * w + 3]);
       }
       __syncthreads();
-      for (int kk = 2; kk <= n2; kk <<= 1) {
-        for (int j = kk >> 1; j > 0; j >>= 1) {
-          for (int i = threadIdx.x; i < n2; i += NT_SLOT) {
-            const int ixj = i ^ j;
-            if (ixj > i) {
-              int c = 0;
-              for (int k = 0; k <= d && c == 0; ++k) {
-                const int ka = K[k * TIECAP + i], kb = K[k * TIECAP + ixj];
-                c = (kb < ka) ? 1 : (kb > ka ? -1 : 0);
-              }
-              const bool asc = (i & kk) == 0;
-              if (asc ? (c == 1) : (c == -1)) {
-                for (int k = 0; k <= d; ++k) {
-                  const int tk = K[k * TIECAP + i];
-                  K[k * TIECAP + i] = K[k * TIECAP + ixj];
-                  K[k * TIECAP + ixj] = tk;
-                }
-                const int ti = idx[i];
-                idx[i] = idx[ixj];
-                idx[ixj] = ti;
-              }
-            }
+      if (threadIdx.x < cnt) {
+        const int i = threadIdx.x;
+        int4 mine[KW];
+#pragma unroll
+        for (int w = 0; w < KW; ++w) mine[w] = K4[i * KW + w];
+        int rank = 0;  // keys are distinct: (F, node) is unique among live labels
+        for (int j = 0; j < cnt; ++j) {
+          int less = 0, decided = 0;
+#pragma unroll
+          for (int w = 0; w < KW; ++w) {
+            const int4 o = K4[j * KW + w];
+            less |= !decided & (o.x < mine[w].x);
+            decided |= o.x != mine[w].x;
+            less |= !decided & (o.y < mine[w].y);
+            decided |= o.y != mine[w].y;
+            less |= !decided & (o.z < mine[w].z);
+            decided |= o.z != mine[w].z;
+            less |= !decided & (o.w < mine[w].w);
+            decided |= o.w != mine[w].w;
           }
-          __syncthreads();
+          rank += less;
         }
+        TS[idx[i]] = rank < need ? 1 : 2;
       }
-      for (int i = threadIdx.x; i < cnt; i += NT_SLOT) TS[idx[i]] = (i < need) ? 1 : 2;
       __syncthreads();
     }
     // taken -> batch, not taken -> OPEN (other buffer)
@@ -366,6 +592,7 @@ __global__ __launch_bounds__(NT_SLOT) void k_batch_finalize(Slot* slots, GraphDe
     }
     __syncthreads();
   }
+  const uint64_t c1 = wall_clock64();
   // ---- canonical batch order: ascending label id
   if (nb > S.batch_cap || nb > BATCH_SORT || keep_n > S.open_cap) {
     if (threadIdx.x == 0) {
@@ -374,54 +601,59 @@ __global__ __launch_bounds__(NT_SLOT) void k_batch_finalize(Slot* slots, GraphDe
     }
     return;
   }
-  int n2 = 1;
-  while (n2 < nb) n2 <<= 1;
+  // register bitonic sort of the batch (padded with INT32_MAX)
   int32_t* V = lds;
-  for (int i = threadIdx.x; i < n2; i += NT_SLOT) V[i] = i < nb ? S.batch[i] : INT32_MAX;
-  __syncthreads();
-  for (int kk = 2; kk <= n2; kk <<= 1) {
-    for (int j = kk >> 1; j > 0; j >>= 1) {
-      for (int i = threadIdx.x; i < n2; i += NT_SLOT) {
-        const int ixj = i ^ j;
-        if (ixj > i) {
-          const int a = V[i], b = V[ixj];
-          const bool asc = (i & kk) == 0;
-          if (asc ? (b < a) : (a < b)) {
-            V[i] = b;
-            V[ixj] = a;
-          }
-        }
+  int E = 1;
+  while (E * NT_SLOT < nb) E <<= 1;
+  if (E == 1) sort_batch<1>(S, nb, V);
+  else if (E == 2) sort_batch<2>(S, nb, V);
+  else if (E == 4) sort_batch<4>(S, nb, V);
+  else sort_batch<8>(S, nb, V);
+  const uint64_t c2 = wall_clock64();
+  // ---- split into goal and regular labels (stable), mark them closed:
+  // thread t owns batch positions t*E .. t*E+E-1
+  const int goal = S.goal;
+  int cg = 0, cr = 0, cdeg = 0;
+  int flags[8], degs[8];
+  for (int e = 0; e < E; ++e) {
+    const int i = threadIdx.x * E + e;
+    flags[e] = 0;
+    degs[e] = 0;
+    if (i < nb) {
+      const int lab = V[i];
+      const int v = S.Lnode[lab];
+      if (v == goal) {
+        flags[e] = 1;
+        ++cg;
+      } else {
+        flags[e] = 2;
+        degs[e] = G.row_ptr[v + 1] - G.row_ptr[v];
+        ++cr;
+        cdeg += degs[e];
       }
-      __syncthreads();
     }
   }
-  // ---- split into goal and regular labels (stable), mark them closed
-  const int goal = S.goal;
-  int goal_total = 0, reg_total = 0, deg_carry = 0;
-  for (int base = 0; base < nb; base += NT_SLOT) {
-    const int i = base + threadIdx.x;
-    const bool valid = i < nb;
-    const int lab = valid ? V[i] : 0;
-    const int v = valid ? S.Lnode[lab] : 0;
-    const bool isg = valid && v == goal;
-    const bool isr = valid && !isg;
-    const int deg = isr ? (G.row_ptr[v + 1] - G.row_ptr[v]) : 0;
-    if (valid) S.Lstate[lab] = L_CLOSED;
-    int tg, tr, td;
-    const int pg = block_exscan<NT_SLOT>(isg ? 1 : 0, &tg, tmp);
-    const int pr = block_exscan<NT_SLOT>(isr ? 1 : 0, &tr, tmp);
-    const int pd = block_exscan<NT_SLOT>(deg, &td, tmp);
-    if (isg) S.goal_lab[goal_total + pg] = lab;
-    if (isr) {
-      S.reg[reg_total + pr] = lab;
-      S.reg_off[reg_total + pr] = deg_carry + pd;
-      S.reg_kill[reg_total + pr] = 0;
+  int goal_total, reg_total, deg_carry;
+  int pg = block_exscan<NT_SLOT>(cg, &goal_total, tmp);
+  int pr = block_exscan<NT_SLOT>(cr, &reg_total, tmp);
+  int pd = block_exscan<NT_SLOT>(cdeg, &deg_carry, tmp);
+  for (int e = 0; e < E; ++e) {
+    const int i = threadIdx.x * E + e;
+    if (flags[e] == 1) {
+      S.goal_lab[pg++] = V[i];
+    } else if (flags[e] == 2) {
+      S.reg[pr] = V[i];
+      S.reg_off[pr] = pd;
+      S.reg_kill[pr] = 0;
+      ++pr;
+      pd += degs[e];
     }
-    goal_total += tg;
-    reg_total += tr;
-    deg_carry += td;
   }
   if (threadIdx.x == 0) {
+    const uint64_t c3 = wall_clock64();
+    Sp->st[ST_T0 + 0] += c1 - c0;
+    Sp->st[ST_T0 + 1] += c2 - c1;
+    Sp->st[ST_T0 + 2] += c3 - c2;
     S.reg_off[reg_total] = deg_carry;
     Sp->goal_n = goal_total;
     Sp->reg_n = reg_total;
@@ -433,7 +665,7 @@ __global__ __launch_bounds__(NT_SLOT) void k_batch_finalize(Slot* slots, GraphDe
     if (deg_carry > S.cand_cap) {
       Sp->status = S_OVERFLOW;
       Sp->err_line = __LINE__;
-    } else if (nb == 0) {
+    } else if (nb == 0 && Sp->far_n == 0) {
       Sp->status = S_DONE;  // no live label left in OPEN
     }
   }
@@ -611,7 +843,48 @@ __global__ __launch_bounds__(NT_SLOT) void k_goal_merge(Slot* slots) {
   }
 }
 
-// ---------------------------------------------------------------- pop-time front check
+// ---------------------------------------------------------------- goal-front tests
+// A vector F is dropped when some goal-front entry p has p <= F in every
+// objective.  Front chunks are staged in LDS as int4 words; components k >= d
+// hold INT32_MIN and rows past the chunk hold INT32_MAX, so every test runs
+// over whole words with no bounds or objective-count checks, branch-free.
+template <int DM>
+struct FrontChunk {
+  static constexpr int NW = (DM + 3) / 4;
+  int4 w[PCH][NW];
+};
+
+template <int DM>
+__device__ __forceinline__ void stage_chunk(FrontChunk<DM>& ch, const int32_t* Pg, int Pc, int p0,
+                                            int npt, int d) {
+  constexpr int NW = FrontChunk<DM>::NW;
+  for (int r = threadIdx.x; r < PCH; r += blockDim.x) {
+    int32_t v[NW * 4];
+#pragma unroll
+    for (int k = 0; k < NW * 4; ++k)
+      v[k] = r < npt ? (k < d ? Pg[(size_t)k * Pc + p0 + r] : INT32_MIN) : INT32_MAX;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) ch.w[r][w] = make_int4(v[4 * w], v[4 * w + 1], v[4 * w + 2], v[4 * w + 3]);
+  }
+}
+
+template <int DM>
+__device__ __forceinline__ bool chunk_dominates(const FrontChunk<DM>& ch, const int4 (&F)[FrontChunk<DM>::NW]) {
+  constexpr int NW = FrontChunk<DM>::NW;
+  int dom = 0;
+#pragma unroll 4
+  for (int q = 0; q < PCH; ++q) {
+    int le = 1;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+      const int4 p = ch.w[q][w];
+      le &= (p.x <= F[w].x) & (p.y <= F[w].y) & (p.z <= F[w].z) & (p.w <= F[w].w);
+    }
+    dom |= le;
+  }
+  return dom != 0;
+}
+
 // The paper's PruneOPEN drops every open label whose F the goal front
 // dominates (Algorithm 1 lines 9-10); here it is applied lazily to the
 // popped regular labels (weak dominance), after this step's goal labels were
@@ -627,7 +900,8 @@ __global__ __launch_bounds__(NT_TILE) void k_popcheck(Slot* slots, GraphDev G) {
   const int nlt = (R + NT_TILE - 1) / NT_TILE, npc = (np + PCH - 1) / PCH;
   const int ntiles = nlt * npc;
   if ((int)blockIdx.x >= ntiles) return;
-  __shared__ int32_t ps[DM][PCH];
+  constexpr int NW = FrontChunk<DM>::NW;
+  __shared__ FrontChunk<DM> ch;
   const int d = S.d, pc = S.pool_cap, Pc = S.P_cap, n = G.n;
   const int32_t* Pg = pick(S.Pg, S.P_sel);
   int killed = 0;
@@ -635,21 +909,20 @@ __global__ __launch_bounds__(NT_TILE) void k_popcheck(Slot* slots, GraphDev G) {
     const int lt = t / npc, pcn = t - lt * npc;
     const int p0 = pcn * PCH, npt = min(PCH, np - p0);
     __syncthreads();
-    if ((int)threadIdx.x < npt) FOR_K(k) ps[k][threadIdx.x] = Pg[(size_t)k * Pc + p0 + threadIdx.x];
+    stage_chunk<DM>(ch, Pg, Pc, p0, npt, d);
     __syncthreads();
     const int i = lt * NT_TILE + threadIdx.x;
     if (i < R) {
       const int lab = S.reg[i];
       const int v = S.Lnode[lab];
-      int32_t F[DM];
-      FOR_K(k) F[k] = S.Lg[(size_t)k * pc + lab] + S.h[(size_t)k * n + v];
-      bool dom = false;
-      for (int q = 0; q < npt && !dom; ++q) {
-        bool le = true;
-        FOR_K(k) le = le && (ps[k][q] <= F[k]);
-        dom = le;
-      }
-      if (dom && atomicExch(&S.reg_kill[i], 1) == 0) {
+      int32_t f[NW * 4];
+#pragma unroll
+      for (int k = 0; k < NW * 4; ++k)
+        f[k] = k < d ? S.Lg[(size_t)k * pc + lab] + S.h[(size_t)k * n + v] : 0;
+      int4 F[NW];
+#pragma unroll
+      for (int w = 0; w < NW; ++w) F[w] = make_int4(f[4 * w], f[4 * w + 1], f[4 * w + 2], f[4 * w + 3]);
+      if (chunk_dominates<DM>(ch, F) && atomicExch(&S.reg_kill[i], 1) == 0) {
         S.Lstate[lab] = L_DEAD;
         ++killed;
       }
@@ -726,27 +999,27 @@ __global__ __launch_bounds__(NT_TILE) void k_pfilter(Slot* slots, GraphDev G) {
   const int nct = (M + NT_TILE - 1) / NT_TILE, npc = (np + PCH - 1) / PCH;
   const int ntiles = nct * npc;
   if ((int)blockIdx.x >= ntiles) return;
-  __shared__ int32_t ps[DM][PCH];
+  constexpr int NW = FrontChunk<DM>::NW;
+  __shared__ FrontChunk<DM> ch;
   const int d = S.d, cc = S.cand_cap, Pc = S.P_cap, n = G.n;
   const int32_t* Pg = pick(S.Pg, S.P_sel);
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const int ct = t / npc, pcn = t - ct * npc;
     const int p0 = pcn * PCH, npt = min(PCH, np - p0);
     __syncthreads();
-    if ((int)threadIdx.x < npt) FOR_K(k) ps[k][threadIdx.x] = Pg[(size_t)k * Pc + p0 + threadIdx.x];
+    stage_chunk<DM>(ch, Pg, Pc, p0, npt, d);
     __syncthreads();
     const int f = ct * NT_TILE + threadIdx.x;
     if (f < M && S.c_keep[f]) {
-      int32_t F[DM];
       const int v = S.c_node[f];
-      FOR_K(k) F[k] = S.c_g[(size_t)k * cc + f] + S.h[(size_t)k * n + v];
-      bool dom = false;
-      for (int q = 0; q < npt && !dom; ++q) {
-        bool le = true;
-        FOR_K(k) le = le && (ps[k][q] <= F[k]);
-        dom = le;
-      }
-      if (dom) S.c_keep[f] = 0;
+      int32_t x[NW * 4];
+#pragma unroll
+      for (int k = 0; k < NW * 4; ++k)
+        x[k] = k < d ? S.c_g[(size_t)k * cc + f] + S.h[(size_t)k * n + v] : 0;
+      int4 F[NW];
+#pragma unroll
+      for (int w = 0; w < NW; ++w) F[w] = make_int4(x[4 * w], x[4 * w + 1], x[4 * w + 2], x[4 * w + 3]);
+      if (chunk_dominates<DM>(ch, F)) S.c_keep[f] = 0;
     }
   }
 }
@@ -1207,24 +1480,35 @@ __global__ __launch_bounds__(NT_TILE) void k_group_finish(Slot* slots) {
 }
 
 // ---------------------------------------------------------------- insert
-__global__ __launch_bounds__(NT_SLOT) void k_accept_scan(Slot* slots) {
+__global__ __launch_bounds__(NT_SLOT) void k_accept_scan(Slot* slots, GraphDev G) {
   Slot* Sp = &slots[blockIdx.x];
   const Slot S = *Sp;
   if (S.status != S_RUN) return;
   __shared__ int tmp[NT_SLOT / WAVE];
   const int M = S.cand_n;
-  int carry = 0;
+  // label ids follow the flat candidate order; OPEN positions are ranks
+  // within the tier the label joins (c_rej is free again after the checks)
+  int carry = 0, cn = 0, cf = 0;
   for (int base = 0; base < M; base += NT_SLOT) {
     const int i = base + threadIdx.x;
-    const int v = i < M ? S.c_acc[i] : 0;
-    int tot;
-    const int ex = block_exscan<NT_SLOT>(v, &tot, tmp);
+    const int a = i < M ? S.c_acc[i] : 0;
+    bool near = false;
+    if (a) near = S.t_all || S.c_g[i] + S.h[S.c_node[i]] < S.T;
+    int tot, tn, tf;
+    const int ex = block_exscan<NT_SLOT>(a, &tot, tmp);
+    const int en = block_exscan<NT_SLOT>(a && near ? 1 : 0, &tn, tmp);
+    const int ef = block_exscan<NT_SLOT>(a && !near ? 1 : 0, &tf, tmp);
     if (i < M) S.c_rank[i] = carry + ex;
+    if (a) S.c_rej[i] = near ? cn + en : cf + ef;
     carry += tot;
+    cn += tn;
+    cf += tf;
   }
   if (threadIdx.x == 0) {
     Sp->accept_n = carry;
-    if (S.n_labels + carry > S.pool_cap || S.keep_n + carry > S.open_cap) {
+    Sp->accept_near = cn;
+    Sp->accept_far = cf;
+    if (S.n_labels + carry > S.pool_cap || S.keep_n + cn > S.open_cap || S.far_n + cf > S.open_cap) {
       Sp->status = S_OVERFLOW;
       Sp->err_line = __LINE__;
     }
@@ -1238,9 +1522,11 @@ __global__ __launch_bounds__(NT_TILE) void k_insert(Slot* slots, GraphDev G) {
   if (S.status != S_RUN) return;
   const int M = S.cand_n;
   const int d = S.d, pc = S.pool_cap, cc = S.cand_cap;
-  const int base_id = S.n_labels, keep = S.keep_n;
+  const int base_id = S.n_labels, keep = S.keep_n, far = S.far_n;
   int32_t* KF = pick(S.open_f1, S.open_sel ^ 1);
   int32_t* KL = pick(S.open_lab, S.open_sel ^ 1);
+  int32_t* FF = pick(S.far_f1, S.far_sel);
+  int32_t* FL = pick(S.far_lab, S.far_sel);
   int mn = INT32_MAX;
   for (int f = blockIdx.x * NT_TILE + threadIdx.x; f < M; f += gridDim.x * NT_TILE) {
     if (!S.c_acc[f]) continue;
@@ -1254,9 +1540,15 @@ __global__ __launch_bounds__(NT_TILE) void k_insert(Slot* slots, GraphDev G) {
     FOR_K(k) S.Lg[(size_t)k * pc + id] = S.c_g[(size_t)k * cc + f];
     S.fw[S.c_fslot[f]] = id;
     const int f1 = S.c_g[f] + S.h[v];
-    KF[keep + r] = f1;
-    KL[keep + r] = id;
-    mn = min(mn, f1);
+    const int q = S.c_rej[f];  // rank within its tier
+    if (S.t_all || f1 < S.T) {
+      KF[keep + q] = f1;
+      KL[keep + q] = id;
+      mn = min(mn, f1);
+    } else {
+      FF[far + q] = f1;
+      FL[far + q] = id;
+    }
   }
   mn = wave_min(mn);
   if (lane_id() == 0 && mn != INT32_MAX) atomicMin(&Sp->lo_next, mn);
@@ -1269,16 +1561,18 @@ __global__ void k_step_end(Slot* slots, int nslots) {
   if (S->status != S_RUN) return;
   S->n_labels += S->accept_n;
   S->st[ST_INSERTED] += S->accept_n;
-  S->open_n = S->keep_n + S->accept_n;
+  S->open_n = S->keep_n + S->accept_near;
+  S->far_n += S->accept_far;
   S->open_sel ^= 1;
   if (S->open_n > 0) S->lo = S->lo_next;
   S->st[ST_STEPS] += 1;
-  if (S->open_n == 0) S->status = S_DONE;
+  S->refill = !S->t_all && S->far_n > 0 && S->open_n < NEAR_LOW * S->B;
+  if (S->open_n == 0 && S->far_n == 0) S->status = S_DONE;
 }
 
 // ---------------------------------------------------------------- launchers
 const char* const kStepKernelNames[kStepKernels] = {
-    "k_open_hist",   "k_open_threshold", "k_open_scatter",  "k_batch_finalize", "k_goal_merge",
+    "k_far_hist",    "k_far_move",       "k_open_hist",   "k_open_threshold", "k_open_scatter",  "k_batch_finalize", "k_goal_merge",
     "k_popcheck",    "k_expand",         "k_pfilter",       "k_group_count",    "k_group_offsets",
     "k_group_scatter", "k_group_process", "k_group_pairs",  "k_group_finish",   "k_accept_scan",
     "k_insert",      "k_step_end"};
@@ -1291,6 +1585,8 @@ static void launch_step_dm(const StepArgs& a, hipStream_t st, hipEvent_t* ev) {
     if (ev) hipEventRecord(ev[i], st);
     ++i;
   };
+  mark(); hipLaunchKernelGGL(k_far_hist, tiled, dim3(NT_TILE), 0, st, a.slots, a.hist);
+  mark(); hipLaunchKernelGGL(k_far_move, tiled, dim3(NT_TILE), 0, st, a.slots);
   mark(); hipLaunchKernelGGL(k_open_hist, tiled, dim3(NT_TILE), 0, st, a.slots, a.hist);
   mark(); hipLaunchKernelGGL(k_open_threshold, per, dim3(NT_SLOT), 0, st, a.slots, a.hist);
   mark(); hipLaunchKernelGGL(k_open_scatter, tiled, dim3(NT_TILE), 0, st, a.slots);
@@ -1305,7 +1601,7 @@ static void launch_step_dm(const StepArgs& a, hipStream_t st, hipEvent_t* ev) {
   mark(); hipLaunchKernelGGL(k_group_process<DM>, tiled, dim3(NT_TILE), 0, st, a.slots);
   mark(); hipLaunchKernelGGL(k_group_pairs<DM>, tiled, dim3(NT_TILE), 0, st, a.slots);
   mark(); hipLaunchKernelGGL(k_group_finish<DM>, tiled, dim3(NT_TILE), 0, st, a.slots);
-  mark(); hipLaunchKernelGGL(k_accept_scan, per, dim3(NT_SLOT), 0, st, a.slots);
+  mark(); hipLaunchKernelGGL(k_accept_scan, per, dim3(NT_SLOT), 0, st, a.slots, a.G);
   mark(); hipLaunchKernelGGL(k_insert<DM>, tiled, dim3(NT_TILE), 0, st, a.slots, a.G);
   mark(); hipLaunchKernelGGL(k_step_end, dim3((a.nslots + 63) / 64), dim3(64), 0, st, a.slots, a.nslots);
   mark();
