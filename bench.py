@@ -37,9 +37,60 @@ def parse():
     ap.add_argument("--steps", type=int, default=200, help="timed label steps")
     ap.add_argument("--warmup", type=int, default=300, help="untimed label steps before timing")
     ap.add_argument("--batch-width", type=int, default=4096)
+    ap.add_argument("--profile-steps", type=int, default=50,
+                    help="last warm-up steps with every kernel timed (per-kernel table; "
+                         "picks the dominant kernel)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="length of the oracle sample for the CPU baseline (0 = skip)")
+    ap.add_argument("--queries", type=int, default=64,
+                    help="queries of the batched-vs-plain comparison (0 = skip)")
+    ap.add_argument("--qdist", type=int, nargs=2, default=(10, 60),
+                    help="Manhattan distance range of those queries")
+    ap.add_argument("--query-width", type=int, default=256,
+                    help="batch width B of every query in that comparison")
     return ap.parse_args()
+
+
+# Algorithmic bytes of each step kernel: what its part of the step has to move
+# through HBM at least, from the search counters (deltas over the timed steps).
+# d objectives; int32 words; label state 1 byte.
+def kernel_bytes(name, c, d, steps):
+    pops = c["pops"] + c["killed"]          # labels taken from OPEN
+    cands, acc = c["candidates"], c["inserted"]
+    fb, fb1 = c["frontier_bytes"], c["frontier_bytes_onepass"]
+    return {
+        "k_far_hist": 9 * c["far_scanned"],                 # F1, label id, state
+        "k_far_move": 17 * c["far_scanned"],                # + the entry written back
+        "k_open_hist": 9 * c["near_scanned"],
+        "k_open_threshold": 8 * 4096 * steps,               # histogram read + reset
+        "k_open_scatter": 17 * c["near_scanned"],
+        "k_batch_finalize": 28 * pops + (8 + 8 * d + 4) * c["tie_entries"],
+        "k_goal_pairs": 4 * d * c["front_reads"] + 4 * d * c["goal_pops"],
+        "k_goal_merge": (8 + 8 * d) * c["goal_pops"],
+        "k_popcheck": (8 + 8 * d) * pops,
+        "k_expand": (16 + 12 * d) * cands,
+        "k_pfilter": (4 + 8 * d) * cands,
+        "k_group_count": 8 * cands,
+        "k_group_offsets": 12 * cands,
+        "k_group_scatter": 12 * cands,
+        "k_group_process": fb1,
+        "k_group_pairs": fb - fb1,
+        "k_group_finish": fb - fb1,
+        "k_accept_scan": 4 * cands + 8 * acc,
+        "k_insert": (12 * d + 24) * acc,
+        "k_step_end": 0,
+    }.get(name, 0)
+
+
+def kernel_ops(name, c, d):
+    """int32 VALU comparisons the kernel's dominance tests need (0: none)."""
+    if name == "k_group_process":
+        return 2 * d * c["pairs_onepass"]   # <= both ways per candidate pair
+    if name in ("k_group_pairs",):
+        return 2 * d * (c["frontier_pairs"] + c["group_pairs"] - c["pairs_onepass"])
+    if name in ("k_pfilter", "k_popcheck", "k_goal_pairs"):
+        return d * c["p_pairs"]
+    return 0
 
 
 def cpu_baseline(g, s, t, seconds):
@@ -52,6 +103,28 @@ def cpu_baseline(g, s, t, seconds):
     return {"value": pairs / secs, "unit": "checks/s", "cores": 1, "kind": "oracle",
             "sample": f"first {secs:.1f} s of the sequential search of the same query "
                       f"({st['pops']} labels processed, {pairs} pair checks)"}
+
+
+def batched_vs_plain(mos, gen, G, a):
+    """Queries/s of one mos_solve_batch call against a loop of mos_solve over
+    the same start/goal list on the same grid (same B, paths included)."""
+    import numpy as np
+
+    S, T = gen.ship_queries(256, 256, a.queries, seed=1000, dmin=a.qdist[0], dmax=a.qdist[1])
+    mos.mos_solve(G, int(S[0]), int(T[0]), batch_width=a.query_width)  # engine warm-up
+    t0 = time.perf_counter()
+    res = mos.mos_solve_batch(G, S, T, batch_width=a.query_width)
+    t1 = time.perf_counter()
+    plain = [mos.mos_solve(G, int(S[q]), int(T[q]), batch_width=a.query_width)
+             for q in range(len(S))]
+    t2 = time.perf_counter()
+    same = all(st == mos.MOS_OK and np.array_equal(r.costs, p.costs)
+               for (st, r), p in zip(res, plain))
+    fronts = [len(p.costs) for p in plain]
+    return {"queries": len(S), "manhattan_distance": list(a.qdist), "batch_width": a.query_width,
+            "batched_qps": len(S) / (t1 - t0), "plain_qps": len(S) / (t2 - t1),
+            "speedup": (t2 - t1) / (t1 - t0), "same_fronts": bool(same),
+            "front_sizes": {"min": min(fronts), "median": int(np.median(fronts)), "max": max(fronts)}}
 
 
 def main():
@@ -68,10 +141,19 @@ def main():
     g, s, t = gen.config2(0)
     G = mos.Graph.from_gen(g)
     d = 3
-    sess = mos.Session(G, s, t, batch_width=a.batch_width, profile_kernels=True,
-                       steps_per_poll=16)
-    if a.warmup:
-        sess.step(a.warmup)
+    sess = mos.Session(G, s, t, batch_width=a.batch_width, steps_per_poll=16)
+    pre = max(1, min(a.profile_steps, a.warmup))
+    if a.warmup > pre:
+        sess.step(a.warmup - pre)
+    # per-kernel table from the last warm-up steps (every kernel bracketed by events)
+    sess.set_profile(-1)
+    p0 = sess.kernel_times()
+    sess.step(pre)
+    p1 = sess.kernel_times()
+    table = {n: (p1[n][0] - p0[n][0], p1[n][1] - p0[n][1]) for n in p1}
+    dom = max(table, key=lambda n: table[n][0])
+    # timed steps: only the dominant kernel is bracketed by events
+    sess.set_profile(1 << list(p1).index(dom))
     s0, k0 = sess.stats(), sess.kernel_times()
     t0 = time.perf_counter()
     done = sess.step(a.steps)
@@ -84,40 +166,28 @@ def main():
     pairs = sum(s1[k] - s0[k] for k in ("frontier_pairs", "p_pairs", "group_pairs"))
     value = pairs / wall
 
-    # per-kernel durations over the timed steps (HIP events on the search stream)
-    kern = {n: (k1[n][0] - k0[n][0], k1[n][1] - k0[n][1]) for n in k1}
-    dom = max(kern, key=lambda n: kern[n][0])
-    ms_dom, launches = kern[dom]
+    # the dominant kernel's launches over the timed steps (HIP events on the search stream)
+    ms_dom, launches = k1[dom][0] - k0[dom][0], k1[dom][1] - k0[dom][1]
     avg_s = ms_dom / 1e3 / max(launches, 1)
-    fb = s1["frontier_bytes"] - s0["frontier_bytes"]
-    fb1 = s1["frontier_bytes_onepass"] - s0["frontier_bytes_onepass"]
-    if dom == "k_group_process":
-        # algorithmic bytes: 4d per (candidate group, live frontier entry);
-        # algorithmic ops: 2d int32 comparisons per candidate pair (<= both ways)
-        nbytes = fb1
-        nops = 2 * d * (s1["pairs_onepass"] - s0["pairs_onepass"])
-    elif dom == "k_group_finish":
-        nbytes, nops = fb - fb1, 0
-    else:
-        # goal-front pairs: d int32 comparisons each, operands staged in LDS
-        nbytes, nops = 0, d * (s1["p_pairs"] - s0["p_pairs"])
+    delta = {k: s1[k] - s0[k] for k in s1 if isinstance(s1[k], int)}
+    nbytes = kernel_bytes(dom, delta, d, steps)
+    nops = kernel_ops(dom, delta, d)
     bw = nbytes / max(launches, 1) / avg_s / 1e9          # GB/s
     ops = nops / max(launches, 1) / avg_s / 1e12          # TOP/s
     # the binding roof follows the kernel's arithmetic intensity (ops per byte)
     balance = ALU_PEAK_TOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
-    intensity = nops / nbytes if nbytes else float("inf")
+    intensity = nops / nbytes if nbytes else (float("inf") if nops else 0.0)
     if intensity > balance:
         roof = {"bound": "alu", "achieved": ops, "peak": ALU_PEAK_TOPS, "unit": "TOP/s",
                 "frac": ops / ALU_PEAK_TOPS, "traffic": None}
     else:
         roof = {"bound": "hbm", "achieved": bw, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": bw / HBM_PEAK_GBS, "traffic": None}
-    roof["intensity_ops_per_byte"] = intensity
-    roof["hbm_gbs"] = bw
-    roof["alu_tops"] = ops
     roof["kernel"] = dom
     roof["avg_launch_us"] = avg_s * 1e6
     roof["launches"] = launches
+    roof["bytes_per_launch"] = nbytes / max(launches, 1)
+    roof["intensity_ops_per_byte"] = intensity
 
     out = {
         "metric": METRIC,
@@ -137,11 +207,16 @@ def main():
                    "batch_width": a.batch_width, "label_steps_timed": steps,
                    "search_finished": bool(done)},
         "roofline": roof,
-        "kernels_ms": {n: round(v[0], 3) for n, v in sorted(kern.items(), key=lambda x: -x[1][0])},
+        "kernel_us_per_step": {n: round(1e3 * v[0] / max(v[1], 1), 2)
+                               for n, v in sorted(table.items(), key=lambda x: -x[1][0])},
+        "kernel_table_steps": pre,
         "search_state": {"pops": s1["pops"], "labels": s1["inserted"], "front_so_far": s1["front"],
-                         "pairs_timed": pairs, "frontier_bytes_timed": fb},
+                         "pairs_timed": pairs,
+                         "frontier_bytes_timed": s1["frontier_bytes"] - s0["frontier_bytes"]},
     }
     sess.close()
+    if a.queries > 0:
+        out["queries_per_s"] = batched_vs_plain(mos, gen, G, a)
     if a.cpu_seconds > 0:
         out["cpu_baseline"] = cpu_baseline(g, s, t, a.cpu_seconds)
     print(json.dumps(out))

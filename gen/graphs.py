@@ -368,6 +368,6 @@ def with_costs(g: Graph, cost: np.ndarray) -> Graph:
 
 
 def overflow_bound_ok(g: Graph) -> bool:
-    """2 * sum_e c_k(e) + max_e c_k(e) <= INT32_MAX for every objective k."""
+    """2 * sum_e c_k(e) + max_e c_k(e) < INT32_MAX for every objective k."""
     c = g.cost.astype(np.int64)
-    return bool(np.all(2 * c.sum(0) + c.max(0, initial=0) <= INT32_MAX))
+    return bool(np.all(2 * c.sum(0) + c.max(0, initial=0) < INT32_MAX))

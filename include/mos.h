@@ -50,7 +50,7 @@ typedef enum {
   MOS_OK = 0,
   MOS_E_INVALID_ARG = 1,   /* bad id, size, pointer or option */
   MOS_E_NEGATIVE_COST = 2, /* an arc cost is < 0 */
-  MOS_E_OVERFLOW_RISK = 3, /* 2*sum_e c_k(e) + max_e c_k(e) > INT32_MAX for some k */
+  MOS_E_OVERFLOW_RISK = 3, /* 2*sum_e c_k(e) + max_e c_k(e) >= INT32_MAX for some k */
   MOS_E_NO_DEVICE = 4,     /* no visible HIP device */
   MOS_E_DEVICE = 5,        /* a HIP runtime call failed */
   MOS_E_OUT_OF_MEMORY = 6, /* device or host allocation failed */
@@ -73,8 +73,9 @@ typedef struct {
   void* stream;         /* hipStream_t to run on, or NULL for the library's own */
   int32_t costs_only;   /* 0 (default) = also reconstruct witness paths; 1 = costs only */
   int32_t steps_per_poll; /* device steps between host status polls; 0 = default */
-  int32_t profile_kernels; /* sessions only: 1 = time every kernel of every step with
-                              HIP events (kernels are then launched one by one) */
+  int32_t profile_kernels; /* sessions only: bit i set = time kernel i of every step with
+                              HIP events (-1 = every kernel); the kernels are then
+                              launched one by one instead of from a captured graph */
 } mos_options;
 
 /* Counters of one query (paper, Section 6: label extractions, candidate
@@ -100,6 +101,10 @@ typedef struct {
   int64_t frontier_bytes_onepass; /* part of frontier_bytes from groups checked by one
                                      wave in a single pass */
   int64_t pairs_onepass;   /* frontier + same-group pairs of those groups */
+  int64_t near_scanned;    /* OPEN entries (near tier) scanned to select the batches */
+  int64_t far_scanned;     /* OPEN entries (far tier) scanned to refill the near tier */
+  int64_t tie_entries;     /* entries of the threshold F1 value ordered by full key */
+  int64_t front_reads;     /* goal-front entries read by the goal-front updates */
   double search_ms;        /* device time of the label steps */
   double heuristic_ms;     /* device time of the heuristic (reverse SSSP) */
 } mos_stats;
@@ -109,8 +114,9 @@ typedef struct {
  * targets), cost[n_arcs * D] arc-major (cost[e*D + k] = objective k of arc e),
  * 1 <= D <= MOS_MAX_OBJECTIVES.  Parallel arcs, self-loops and zero costs are
  * allowed.  Fails with MOS_E_NEGATIVE_COST for a negative cost and with
- * MOS_E_OVERFLOW_RISK when int32 sums could overflow (every accepted label is
- * a simple path, so g_k <= sum of c_k and F_k <= 2*sum + max).  The arrays are
+ * MOS_E_OVERFLOW_RISK when int32 sums could reach INT32_MAX (every accepted
+ * label is a simple path, so g_k <= sum of c_k and F_k <= 2*sum + max; INT32_MAX
+ * itself is kept free as a sentinel above every cost).  The arrays are
  * copied; the caller keeps ownership.  The graph is immutable afterwards and
  * may be shared by several threads and streams. */
 mos_status mos_graph_create(int32_t n_nodes, int64_t n_arcs, int32_t D, const int64_t* row_ptr,
@@ -180,7 +186,7 @@ void mos_server_destroy(mos_server* s);
  * size is that of the goal front so far); mos_session_result runs the search
  * to completion and returns the exact front (MOS_E_LABEL_LIMIT if the
  * reservation is outgrown).  Kernel times are kept when
- * options.profile_kernels = 1: entry i of mos_session_kernel_times gives the
+ * options.profile_kernels has bit i set: entry i of mos_session_kernel_times gives the
  * kernel's name, its summed duration in ms and its launch count; i ranges
  * over 0 .. mos_session_kernel_count()-1. */
 typedef struct mos_session mos_session;
@@ -190,6 +196,9 @@ mos_status mos_session_step(mos_session* s, int64_t nsteps, int32_t* done);
 mos_status mos_session_stats(const mos_session* s, mos_stats* out);
 mos_status mos_session_result(mos_session* s, mos_result** out);
 int32_t mos_session_kernel_count(void);
+/* Change which kernels are timed from the next step on (same mask as
+ * options.profile_kernels; 0 = none, steps then replay a captured graph). */
+mos_status mos_session_set_profile(mos_session* s, int32_t mask);
 mos_status mos_session_kernel_times(const mos_session* s, int32_t i, const char** name, double* ms,
                                     int64_t* launches);
 void mos_session_destroy(mos_session* s);

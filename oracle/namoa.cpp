@@ -241,11 +241,11 @@ struct Search {
     if (!reachable(s)) return;  // no s -> t path: empty front
 
     auto t0 = std::chrono::steady_clock::now();
-    // Alg. 1, lines 1-2
+    // Algorithm 1: empty OPEN, goal front and per-node label sets
     std::set<int, Cmp> OPEN(Cmp{this});
     std::vector<int> P;
     std::vector<std::vector<int>> Gop(n), Gcl(n);
-    // lines 3-4
+    // the start label (g = 0) opens the search
     std::vector<i64> zero(d, 0), gp(d), Fp(d), Fl(d);
     int ls = new_label(s, zero.data(), -1, -1);
     OPEN.insert(ls);
@@ -253,7 +253,7 @@ struct Search {
     R.inserted++;
 
     i64 iter = 0;
-    while (!OPEN.empty()) {  // line 5
+    while (!OPEN.empty()) {
       if ((++iter & 4095) == 0) {
         double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         if (time_limit > 0 && el > time_limit) {
@@ -263,7 +263,7 @@ struct Search {
         }
       }
       R.max_open = std::max<i64>(R.max_open, (i64)OPEN.size());
-      int l = *OPEN.begin();  // line 6
+      int l = *OPEN.begin();  // lexicographically smallest open label
       OPEN.erase(OPEN.begin());
       int v = lv[l];
       // copy g(l): the label store may grow (and move) while l is expanded
@@ -285,13 +285,13 @@ struct Search {
         }
       }
       R.pops++;
-      remove_from(Gop[v], l);  // line 7
+      remove_from(Gop[v], l);  // the label moves from G_OP to G_CL
       Gcl[v].push_back(l);
 
-      if (v == t) {  // line 8
+      if (v == t) {  // a label at the goal updates the goal front
         R.goal_pops++;
         if (!(flags & ORACLE_LAZY_PRUNEOPEN)) {
-          // lines 9-10: PruneOPEN(l) -- full scan of OPEN
+          // PruneOPEN(l): full scan of OPEN
           std::vector<int> killed;
           for (int x : OPEN) {
             R.open_pairs++;
@@ -305,14 +305,14 @@ struct Search {
             R.killed++;
           }
         }
-        // line 11: Prune(P, l)
+        // Prune(P, l)
         std::vector<int> keep;
         for (int p : P) {
           R.p_pairs++;
           if (!dominates(gl, &lg[(i64)p * d])) keep.push_back(p);
         }
         P.swap(keep);
-        // lines 12-13: NotDominated(l, P) (cost-unique: an equal vector also blocks)
+        // NotDominated(l, P) (cost-unique: an equal vector also blocks)
         bool ok = true;
         for (int p : P) {
           R.p_pairs++;
@@ -323,12 +323,12 @@ struct Search {
         continue;
       }
 
-      // lines 15-31: expand l
+      // expansion of l over its out-arcs
       for (i64 e = g.row_ptr[v]; e < g.row_ptr[v + 1]; ++e) {
         int w = g.col[e];
         R.candidates++;
         if (!reachable(w)) { R.unreachable++; continue; }
-        for (int k = 0; k < d; ++k) {  // lines 16-17
+        for (int k = 0; k < d; ++k) {  // g' = g + c(e), F' = g' + h(v')
           gp[k] = gl[k] + g.cost[e * g.D + k];
           Fp[k] = gp[k] + h[(i64)k * n + w];
           if (gp[k] >= LIM || Fp[k] >= LIM) throw std::overflow_error("cost above 2^31");
@@ -338,27 +338,27 @@ struct Search {
         i64 asz = (i64)op.size() + (i64)cl.size();
         R.max_alpha = std::max(R.max_alpha, asz);
         bool insert = false;
-        if (asz == 0) {  // line 18: not Visited(v')
+        if (asz == 0) {  // not Visited(v')
           insert = true;
         } else {
           R.frontier_pairs += asz;
-          // lines 22-23: Duplicate(l')
+          // Duplicate(l')
           bool dup = false;
           for (int x : op) if (equal(&lg[(i64)x * d], gp.data())) { dup = true; break; }
           if (!dup) for (int x : cl) if (equal(&lg[(i64)x * d], gp.data())) { dup = true; break; }
           if (dup) continue;
-          // lines 24-25: NotDominated(l', G_OP) and NotDominated(l', G_CL)
+          // NotDominated(l', G_OP) and NotDominated(l', G_CL)
           bool domd = false;
           for (int x : op) if (dominates(&lg[(i64)x * d], gp.data())) { domd = true; break; }
           if (!domd) for (int x : cl) if (dominates(&lg[(i64)x * d], gp.data())) { domd = true; break; }
           if (domd) continue;
-          // line 26: Prune(G_CL(v'), l')
+          // Prune(G_CL(v'), l')
           for (size_t i = 0; i < cl.size();) {
             if (dominates(gp.data(), &lg[(i64)cl[i] * d])) {
               cl[i] = cl.back(); cl.pop_back(); R.pruned++;
             } else ++i;
           }
-          // lines 27-28: Prune(G_OP(v'), l') and remove the pruned labels from OPEN
+          // Prune(G_OP(v'), l') and remove the pruned labels from OPEN
           for (size_t i = 0; i < op.size();) {
             if (dominates(gp.data(), &lg[(i64)op[i] * d])) {
               OPEN.erase(op[i]);
@@ -368,7 +368,7 @@ struct Search {
           insert = true;
         }
         if (insert) {
-          // lines 19 / 29: NotDominated(F(l'), P)
+          // NotDominated(F(l'), P)
           bool ok = true;
           for (int p : P) {
             R.p_pairs++;
@@ -379,7 +379,7 @@ struct Search {
             R.status = ORACLE_LABEL_LIMIT;
             return;
           }
-          int nl = new_label(w, gp.data(), l, (int)e);  // lines 20-21 / 30-31
+          int nl = new_label(w, gp.data(), l, (int)e);  // into OPEN and G_OP(v')
           OPEN.insert(nl);
           Gop[w].push_back(nl);
           R.inserted++;
@@ -389,7 +389,7 @@ struct Search {
     R.search_seconds =
         std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
 
-    // line 32: return P (sorted lexicographically), with parent-chain paths
+    // the result: P sorted lexicographically, with parent-chain paths
     std::sort(P.begin(), P.end(), [&](int a, int b) {
       for (int k = 0; k < d; ++k)
         if (lg[(i64)a * d + k] != lg[(i64)b * d + k]) return lg[(i64)a * d + k] < lg[(i64)b * d + k];

@@ -48,7 +48,8 @@ class mos_stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in
                 ("pops", "goal_pops", "candidates", "p_pairs", "group_pairs", "frontier_pairs",
                  "inserted", "pruned", "steps", "front", "frontier_bytes", "killed",
-                 "frontier_bytes_onepass", "pairs_onepass")] + \
+                 "frontier_bytes_onepass", "pairs_onepass", "near_scanned", "far_scanned",
+                 "tie_entries", "front_reads")] + \
                [("search_ms", ctypes.c_double), ("heuristic_ms", ctypes.c_double)]
 
 
@@ -90,6 +91,7 @@ _SIGS = {
     "mos_session_stats": (ctypes.c_int, [_vp, ctypes.POINTER(mos_stats)]),
     "mos_session_result": (ctypes.c_int, [_vp, ctypes.POINTER(_vp)]),
     "mos_session_kernel_count": (ctypes.c_int32, []),
+    "mos_session_set_profile": (ctypes.c_int, [_vp, ctypes.c_int32]),
     "mos_session_kernel_times": (ctypes.c_int, [_vp, ctypes.c_int32,
                                                 ctypes.POINTER(ctypes.c_char_p),
                                                 ctypes.POINTER(ctypes.c_double), _i64p]),
@@ -226,7 +228,8 @@ def make_options(n_objectives=0, batch_width=0, max_slots=0, label_limit=0, mem_
     o.stream = _stream_ptr(stream)
     o.costs_only = 1 if costs_only else 0
     o.steps_per_poll = int(steps_per_poll)
-    o.profile_kernels = 1 if profile_kernels else 0
+    # True = every kernel of the step; an int = bit mask over the step's kernels
+    o.profile_kernels = -1 if profile_kernels is True else int(profile_kernels)
     return o
 
 
@@ -293,6 +296,14 @@ class Session:
         h = _vp()
         _check(_lib.mos_session_result(self._h, ctypes.byref(h)), "mos_session_result")
         return _take_result(h)
+
+    def set_profile(self, mask: int) -> None:
+        """Time the kernels whose bit is set (kernel order of kernel_times); 0 = none."""
+        _check(_lib.mos_session_set_profile(self._h, ctypes.c_int32(mask & 0xffffffff).value),
+               "mos_session_set_profile")
+
+    def kernel_names(self) -> list:
+        return list(self.kernel_times().keys())
 
     def kernel_times(self) -> dict:
         out = {}

@@ -273,7 +273,7 @@ static bool plan_layout(const mos_graph* g, int d, int B, int64_t budget, int64_
   b += 3 * al(4 * pool) + al(4 * (int64_t)d * pool) + al(pool);  // pool
   b += 8 * al(4 * pool);                                          // OPEN near + far tiers
   b += 3 * al(4 * pool);                                          // tie set
-  b += 2 * (al(4 * (int64_t)d * L->P_cap) + al(4 * (int64_t)L->P_cap)) + al(8 * ((int64_t)L->P_cap + 1));
+  b += 2 * (al(4 * (int64_t)d * L->P_cap) + al(4 * (int64_t)L->P_cap));
   b += al(4 * L->fw_cap);
   L->bytes = al(b);
   return L->bytes <= budget;
@@ -331,7 +331,6 @@ static void carve(Slot& s, char* base, const Layout& L, int64_t n, int d) {
     s.Pg[b] = (int32_t*)take(4 * (int64_t)d * L.P_cap);
     s.Plab[b] = (int32_t*)take(4 * (int64_t)L.P_cap);
   }
-  s.pscr = (int32_t*)take(8 * ((int64_t)L.P_cap + 1));
   s.fw = (int32_t*)take(4 * L.fw_cap);
   if (p - base > L.bytes) throw MosError(MOS_E_DEVICE, "slot layout overrun");
 }
@@ -384,6 +383,11 @@ class Engine {
     HIPCHK(hipMemsetAsync(hist_.p, 0, (size_t)S_ * NB * 4, st_));
     sh_.resize(S_);
     gx_ = std::max(1, 2048 / S_);
+    // tuning knobs of the step's launch shape (defaults otherwise):
+    // MOS_GX workgroups per slot of the tiled kernels, MOS_BIG_WORK pair
+    // checks above which a group is split into pair tiles
+    if (const char* x = std::getenv("MOS_GX")) gx_ = std::max(1, std::min(65535, std::atoi(x)));
+    if (const char* x = std::getenv("MOS_BIG_WORK")) big_work_ = std::max(64, std::atoi(x));
     HIPCHK(hipEventCreate(&ev0_));
     HIPCHK(hipEventCreate(&ev1_));
     HIPCHK(hipStreamSynchronize(st_));
@@ -503,6 +507,7 @@ class Engine {
       s.goal = q.goal;
       s.d = q.d;
       s.B = L.B;
+      s.big_work = big_work_;
       s.batch_cap = L.batch_cap;
       s.cand_cap = L.cand_cap;
       s.tie_cap = L.tie_cap;
@@ -582,7 +587,10 @@ class Engine {
   }
   const Slot& slot0() const { return hslots_[0]; }
   const SlotHost& host0() const { return sh_[0]; }
-  void set_profile(bool on) { profile_ = on; }
+  void set_profile(uint32_t mask) {
+    drain_profile();
+    profile_ = mask;
+  }
   double kernel_ms(int i) const { return kms_[i]; }
   int64_t kernel_launches(int i) const { return klaunch_[i]; }
   mos_result* harvest_slot0() {
@@ -602,11 +610,15 @@ class Engine {
     o.inserted = d.st[ST_INSERTED];
     o.pruned = d.st[ST_PRUNED];
     o.steps = d.st[ST_STEPS];
-    o.front = d.P_n;
+    o.front = d.P_n - d.P_dead;
     o.frontier_bytes = d.st[ST_FBYTES];
     o.killed = d.st[ST_KILLED];
     o.frontier_bytes_onepass = d.st[ST_FBYTES_WAVE];
     o.pairs_onepass = d.st[ST_PAIRS_WAVE];
+    o.near_scanned = d.st[ST_NEAR_SCAN];
+    o.far_scanned = d.st[ST_FAR_SCAN];
+    o.tie_entries = d.st[ST_TIE];
+    o.front_reads = d.st[ST_PREAD];
     o.search_ms = sh_[s].search_ms;
     o.heuristic_ms = sh_[s].heur_ms;
     return o;
@@ -762,7 +774,7 @@ class Engine {
     }
     if (ring_used_ == RING) drain_one();
     hipEvent_t* set = &pev_[(size_t)((ring_head_ + ring_used_) % RING) * NE];
-    launch_step(a, st_, set);
+    launch_step(a, st_, set, profile_);
     HIPCHK(hipGetLastError());
     ++ring_used_;
   }
@@ -771,6 +783,7 @@ class Engine {
     hipEvent_t* set = &pev_[(size_t)ring_head_ * NE];
     HIPCHK(hipEventSynchronize(set[kStepKernels]));
     for (int i = 0; i < kStepKernels; ++i) {
+      if (!((profile_ >> i) & 1u)) continue;
       float ms = 0;
       HIPCHK(hipEventElapsedTime(&ms, set[i], set[i + 1]));
       kms_[i] += ms;
@@ -783,43 +796,61 @@ class Engine {
     while (ring_used_ > 0) drain_one();
   }
 
+  // The goal front of slot s: live entries (tombstones dropped), sorted
+  // lexicographically ascending, with their witness paths.
   mos_result* harvest(int s) {
     const Slot& d = hslots_[s];
     std::unique_ptr<mos_result> r(new mos_result());
     const int dd = d.d;
-    const int64_t np = d.P_n;
+    const int64_t nall = d.P_n;
+    std::vector<int32_t> planes((size_t)nall * dd), lab(nall);
+    for (int k = 0; k < dd && nall > 0; ++k)
+      HIPCHK(hipMemcpyAsync(planes.data() + (size_t)k * nall, d.Pg[d.P_sel] + (size_t)k * d.P_cap,
+                            nall * 4, hipMemcpyDeviceToHost, st_));
+    if (nall > 0)
+      HIPCHK(hipMemcpyAsync(lab.data(), d.Plab[d.P_sel], nall * 4, hipMemcpyDeviceToHost, st_));
+    HIPCHK(hipStreamSynchronize(st_));
+    std::vector<int64_t> idx;
+    for (int64_t i = 0; i < nall; ++i)
+      if (planes[i] != INT32_MAX) idx.push_back(i);
+    std::sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) {
+      for (int k = 0; k < dd; ++k) {
+        const int32_t x = planes[(size_t)k * nall + a], y = planes[(size_t)k * nall + b];
+        if (x != y) return x < y;
+      }
+      return false;
+    });
+    const int64_t np = (int64_t)idx.size();
     r->d = dd;
     r->size = np;
     r->costs.resize((size_t)np * dd);
-    if (np > 0) {
-      std::vector<int32_t> planes((size_t)np * dd);
-      for (int k = 0; k < dd; ++k)
-        HIPCHK(hipMemcpyAsync(planes.data() + (size_t)k * np, d.Pg[d.P_sel] + (size_t)k * d.P_cap,
-                              np * 4, hipMemcpyDeviceToHost, st_));
+    std::vector<int32_t> sl(np);
+    for (int64_t j = 0; j < np; ++j) {
+      for (int k = 0; k < dd; ++k) r->costs[(size_t)j * dd + k] = planes[(size_t)k * nall + idx[j]];
+      sl[j] = lab[idx[j]];
+    }
+    if (want_paths_ && np > 0) {
+      DevBuf labs, len, off, arcs;
+      labs.alloc(np * 4, st_);
+      len.alloc(np * 4, st_);
+      HIPCHK(hipMemcpyAsync(labs.p, sl.data(), np * 4, hipMemcpyHostToDevice, st_));
+      launch_path_len(slots_.as<Slot>(), s, labs.as<int32_t>(), (int)np, len.as<int32_t>(), st_);
+      std::vector<int32_t> hl(np);
+      HIPCHK(hipMemcpyAsync(hl.data(), len.p, np * 4, hipMemcpyDeviceToHost, st_));
       HIPCHK(hipStreamSynchronize(st_));
-      for (int64_t i = 0; i < np; ++i)
-        for (int k = 0; k < dd; ++k) r->costs[(size_t)i * dd + k] = planes[(size_t)k * np + i];
-      if (want_paths_) {
-        DevBuf len, off, arcs;
-        len.alloc(np * 4, st_);
-        launch_path_len(slots_.as<Slot>(), s, (int)np, len.as<int32_t>(), st_);
-        std::vector<int32_t> hl(np);
-        HIPCHK(hipMemcpyAsync(hl.data(), len.p, np * 4, hipMemcpyDeviceToHost, st_));
-        HIPCHK(hipStreamSynchronize(st_));
-        r->path_off.assign(np + 1, 0);
-        for (int64_t i = 0; i < np; ++i) r->path_off[i + 1] = r->path_off[i] + hl[i];
-        const int64_t tot = r->path_off[np];
-        r->arcs.resize(tot);
-        if (tot > 0) {
-          off.alloc((np + 1) * 8, st_);
-          arcs.alloc(tot * 4, st_);
-          HIPCHK(hipMemcpyAsync(off.p, r->path_off.data(), (np + 1) * 8, hipMemcpyHostToDevice, st_));
-          launch_path_write(slots_.as<Slot>(), s, (int)np, off.as<int64_t>(), arcs.as<int32_t>(),
-                            st_);
-          HIPCHK(hipMemcpyAsync(r->arcs.data(), arcs.p, tot * 4, hipMemcpyDeviceToHost, st_));
-        }
-        HIPCHK(hipStreamSynchronize(st_));
+      r->path_off.assign(np + 1, 0);
+      for (int64_t i = 0; i < np; ++i) r->path_off[i + 1] = r->path_off[i] + hl[i];
+      const int64_t tot = r->path_off[np];
+      r->arcs.resize(tot);
+      if (tot > 0) {
+        off.alloc((np + 1) * 8, st_);
+        arcs.alloc(tot * 4, st_);
+        HIPCHK(hipMemcpyAsync(off.p, r->path_off.data(), (np + 1) * 8, hipMemcpyHostToDevice, st_));
+        launch_path_write(slots_.as<Slot>(), s, labs.as<int32_t>(), (int)np, off.as<int64_t>(),
+                          arcs.as<int32_t>(), st_);
+        HIPCHK(hipMemcpyAsync(r->arcs.data(), arcs.p, tot * 4, hipMemcpyDeviceToHost, st_));
       }
+      HIPCHK(hipStreamSynchronize(st_));
     } else if (want_paths_) {
       r->path_off.assign(1, 0);
     }
@@ -840,13 +871,14 @@ class Engine {
   RangeAlloc ra_;
   std::vector<SlotHost> sh_;
   int gx_ = 1;
+  int big_work_ = (int)BIG_WORK;
   hipEvent_t ev0_ = nullptr, ev1_ = nullptr;
   hipGraphExec_t graph_exec_ = nullptr;
   bool graph_failed_ = false;
   bool use_graph_ = true;
   bool progress_ = false;
   int progress_level_ = 0;
-  bool profile_ = false;
+  uint32_t profile_ = 0;  // kernels of the step timed with events (bit i = kernel i)
   std::vector<hipEvent_t> pev_;
   int ring_head_ = 0, ring_used_ = 0;
   double kms_[kStepKernels] = {};
@@ -887,7 +919,8 @@ static void release_engine(const mos_graph* gc, const EngineKey& k, Engine* e) {
 
 // ------------------------------------------------------------ option helpers
 struct Opts {
-  int n_objectives = 0, B = 256, max_slots = 0, want_paths = 1, steps = 8, profile = 0;
+  int n_objectives = 0, B = 256, max_slots = 0, want_paths = 1, steps = 8;
+  uint32_t profile = 0;
   int64_t label_limit = 0, mem_budget = 0;
   hipStream_t stream = nullptr;
 };
@@ -906,7 +939,7 @@ static mos_status read_opts(const mos_options* o, Opts* out) {
     if (o->struct_size >= offsetof(mos_options, steps_per_poll)) r.want_paths = o->costs_only ? 0 : 1;
     if (o->struct_size >= offsetof(mos_options, profile_kernels) && o->steps_per_poll > 0)
       r.steps = o->steps_per_poll;
-    if (o->struct_size >= sizeof(mos_options)) r.profile = o->profile_kernels != 0;
+    if (o->struct_size >= sizeof(mos_options)) r.profile = (uint32_t)o->profile_kernels;
   }
   if (r.B < 1 || r.B > BATCH_SORT / 2)
     return set_err(MOS_E_INVALID_ARG, "batch_width must lie in [1, 4096]");
@@ -985,8 +1018,8 @@ mos_status mos_graph_create(int32_t n, int64_t m, int32_t D, const int64_t* row_
       sum += c;
       mx = std::max(mx, c);
     }
-    if (2 * sum + mx > (int64_t)INT32_MAX)
-      return set_err(MOS_E_OVERFLOW_RISK, "2*sum+max of an objective exceeds INT32_MAX");
+    if (2 * sum + mx >= (int64_t)INT32_MAX)
+      return set_err(MOS_E_OVERFLOW_RISK, "2*sum+max of an objective reaches INT32_MAX");
   }
   return guarded([&]() -> mos_status {
     const int dev = ensure_device();
@@ -1203,7 +1236,7 @@ mos_status mos_session_create(const mos_graph* g, int32_t start, int32_t goal,
     s->g = g;
     s->eng.reset(new Engine(g, 1, dm_for(d), default_budget(o.mem_budget), o.stream, o.B,
                             o.label_limit, o.want_paths != 0, o.steps));
-    s->eng->set_profile(o.profile != 0);
+    s->eng->set_profile(o.profile);
     QueryReq q;
     q.id = 0;
     q.start = start;
@@ -1252,6 +1285,15 @@ mos_status mos_session_result(mos_session* s, mos_result** out) {
 }
 
 int32_t mos_session_kernel_count(void) { return kStepKernels; }
+
+mos_status mos_session_set_profile(mos_session* s, int32_t mask) {
+  if (!s) return set_err(MOS_E_INVALID_ARG, "NULL session");
+  return guarded([&]() -> mos_status {
+    HIPCHK(hipSetDevice(s->g->device));
+    s->eng->set_profile((uint32_t)mask);
+    return MOS_OK;
+  });
+}
 
 mos_status mos_session_kernel_times(const mos_session* s, int32_t i, const char** name, double* ms,
                                     int64_t* launches) {

@@ -20,19 +20,22 @@ struct StepArgs {
 int dm_for(int d);
 
 // One batched label step over every resident slot: a fixed sequence of
-// kStepKernels kernels.  With ev != nullptr, ev[i] is recorded before kernel i
-// and ev[kStepKernels] after the last one (kStepKernels + 1 events).
-constexpr int kStepKernels = 19;
+// kStepKernels kernels.  With ev != nullptr, the kernels i whose bit is set in
+// `mask` are bracketed by events: ev[i] is recorded before kernel i and
+// ev[i + 1] after it; ev[kStepKernels] is always recorded after the last one.
+constexpr int kStepKernels = 20;
 extern const char* const kStepKernelNames[kStepKernels];
-void launch_step(const StepArgs& a, hipStream_t st, hipEvent_t* ev = nullptr);
+void launch_step(const StepArgs& a, hipStream_t st, hipEvent_t* ev = nullptr,
+                 uint32_t mask = 0xffffffffu);
 
 void launch_heur_init(Slot* slots, const int32_t* slot_of, int njobs, const GraphDev& G,
                       int32_t* hs, int32_t* cnt, hipStream_t st);
 void launch_heur_round(Slot* slots, const int32_t* slot_of, int njobs, const GraphDev& G,
                        int32_t* hs, int32_t* cnt, int r, int gx, hipStream_t st);
 void launch_slot_init(Slot* slots, int s, const GraphDev& G, hipStream_t st);
-void launch_path_len(const Slot* slots, int s, int np, int32_t* len, hipStream_t st);
-void launch_path_write(const Slot* slots, int s, int np, const int64_t* off, int32_t* arcs,
-                       hipStream_t st);
+void launch_path_len(const Slot* slots, int s, const int32_t* labs, int np, int32_t* len,
+                     hipStream_t st);
+void launch_path_write(const Slot* slots, int s, const int32_t* labs, int np, const int64_t* off,
+                       int32_t* arcs, hipStream_t st);
 
 }  // namespace mos

@@ -73,7 +73,7 @@ __global__ void k_heur_round(Slot* slots, const int32_t* slot_of, GraphDev G, in
 }
 
 // Reset the per-node structures of a slot and seed the start label
-// (Algorithm 1 lines 3-4).  A start that cannot reach the goal finishes the
+// (the start of Algorithm 1).  A start that cannot reach the goal finishes the
 // query at once with an empty front.
 __global__ void k_slot_init(Slot* slots, int s, GraphDev G) {
   Slot* S = &slots[s];
@@ -96,7 +96,7 @@ __global__ void k_slot_seed(Slot* slots, int s, GraphDev G) {
   for (int k = 0; k < d; ++k) reach = reach && S->h[(size_t)k * n + st] != UNREACH;
   S->P_n = 0;
   S->P_sel = 0;
-  S->cur_min = INT32_MAX;
+  S->P_dead = 0;
   S->lo_next = INT32_MAX;
   if (!reach) {
     S->n_labels = 0;
@@ -134,25 +134,24 @@ __global__ void k_slot_seed(Slot* slots, int s, GraphDev G) {
   S->status = S_RUN;
 }
 
-// Witness paths (paper, Section 3: parent pointers allow path reconstruction).
-__global__ void k_path_len(const Slot* slots, int s, int32_t* len) {
+// Witness paths (paper, Section 3: parent pointers allow path reconstruction)
+// of the goal labels labs[0 .. np): lengths, then arc ids written backwards
+// from the end of each path's range.
+__global__ void k_path_len(const Slot* slots, int s, const int32_t* labs, int np, int32_t* len) {
   const Slot* S = &slots[s];
-  const int np = S->P_n;
-  const int32_t* Pl = S->Plab[S->P_sel];
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < np; i += gridDim.x * blockDim.x) {
     int c = 0;
-    for (int x = Pl[i]; S->Lpar[x] >= 0; x = S->Lpar[x]) ++c;
+    for (int x = labs[i]; S->Lpar[x] >= 0; x = S->Lpar[x]) ++c;
     len[i] = c;
   }
 }
 
-__global__ void k_path_write(const Slot* slots, int s, const int64_t* off, int32_t* arcs) {
+__global__ void k_path_write(const Slot* slots, int s, const int32_t* labs, int np,
+                             const int64_t* off, int32_t* arcs) {
   const Slot* S = &slots[s];
-  const int np = S->P_n;
-  const int32_t* Pl = S->Plab[S->P_sel];
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < np; i += gridDim.x * blockDim.x) {
     int64_t pos = off[i + 1];
-    for (int x = Pl[i]; S->Lpar[x] >= 0; x = S->Lpar[x]) arcs[--pos] = S->Larc[x];
+    for (int x = labs[i]; S->Lpar[x] >= 0; x = S->Lpar[x]) arcs[--pos] = S->Larc[x];
   }
 }
 
@@ -176,15 +175,16 @@ void launch_slot_init(Slot* slots, int s, const GraphDev& G, hipStream_t st) {
   hipLaunchKernelGGL(k_slot_seed, dim3(1), dim3(1), 0, st, slots, s, G);
 }
 
-void launch_path_len(const Slot* slots, int s, int np, int32_t* len, hipStream_t st) {
+void launch_path_len(const Slot* slots, int s, const int32_t* labs, int np, int32_t* len,
+                     hipStream_t st) {
   const int gx = std::max(1, std::min(1024, (np + 255) / 256));
-  hipLaunchKernelGGL(k_path_len, dim3(gx), dim3(256), 0, st, slots, s, len);
+  hipLaunchKernelGGL(k_path_len, dim3(gx), dim3(256), 0, st, slots, s, labs, np, len);
 }
 
-void launch_path_write(const Slot* slots, int s, int np, const int64_t* off, int32_t* arcs,
-                       hipStream_t st) {
+void launch_path_write(const Slot* slots, int s, const int32_t* labs, int np, const int64_t* off,
+                       int32_t* arcs, hipStream_t st) {
   const int gx = std::max(1, std::min(1024, (np + 255) / 256));
-  hipLaunchKernelGGL(k_path_write, dim3(gx), dim3(256), 0, st, slots, s, off, arcs);
+  hipLaunchKernelGGL(k_path_write, dim3(gx), dim3(256), 0, st, slots, s, labs, np, off, arcs);
 }
 
 }  // namespace mos

@@ -24,7 +24,7 @@ constexpr int BATCH_SORT = 8192;  // largest popped batch (LDS sort by label id)
 constexpr int NEAR_LOW = 4, NEAR_TARGET = 16, NEAR_HIGH = 48;
 constexpr int32_t UNREACH = INT32_MAX;  // heuristic of a node that cannot reach the goal
 constexpr int WAVE = 64;
-constexpr int64_t BIG_WORK = 64 * 1024;  // pair checks above which a group is split across waves
+constexpr int64_t BIG_WORK = 4096;  // pair checks above which a group is split across waves
 constexpr int32_t PRUNED_BIT = (int32_t)0x80000000;  // marks a pruned entry in a label-id slot
 
 enum SlotStatus : int32_t {
@@ -52,8 +52,12 @@ enum Stat {
   ST_KILLED,
   ST_FBYTES_WAVE,  // frontier bytes of the groups checked in one pass by one wave
   ST_PAIRS_WAVE,   // candidate pairs (frontier + same group) of those groups
-  ST_T0 = 16,      // ST_T0..ST_T0+7: phase timers (constant-rate device clock ticks)
-  NSTAT = 24
+  ST_NEAR_SCAN,    // near-tier OPEN entries scanned by pops
+  ST_FAR_SCAN,     // far-tier OPEN entries scanned by refills
+  ST_TIE,          // entries of threshold bins refined by full key
+  ST_PREAD,        // goal-front entries read by goal merges
+  ST_T0 = 24,      // ST_T0..ST_T0+7: phase timers and diagnostics
+  NSTAT = 32
 };
 
 // Frontier record of one node: the node's live labels are entries [0, count)
@@ -97,9 +101,9 @@ struct Slot {
   int32_t* open_lab[2];//   label id of the entry
   int32_t* far_f1[2];  // open_cap each: far tier of OPEN (F1 >= T)
   int32_t* far_lab[2];
-  int32_t* Pg[2];      // d planes of P_cap each: goal front, lexicographically ascending
+  int32_t* Pg[2];      // d planes of P_cap each: goal front (unordered; a removed
+                       //   entry holds INT32_MAX in every plane until compaction)
   int32_t* Plab[2];    //   label id of each goal-front entry
-  int32_t* pscr;       // 2*(P_cap+1): goal-merge scratch (prune flags, survivor prefix)
   int32_t* batch;      // batch_cap: popped labels
   int32_t* reg;        // batch_cap: popped regular labels (ascending label id)
   int32_t* reg_off;    // batch_cap+1: exclusive prefix of their out-degrees
@@ -127,9 +131,9 @@ struct Slot {
 
   // ---------------- dynamic (device-updated)
   int32_t n_labels, open_n, open_sel, P_n;
-  int32_t P_sel, lo, lo_next, cur_min;
+  int32_t P_sel, lo, lo_next, P_dead;  // P_dead: removed entries among the first P_n
   int64_t fw_top;
-  int32_t t_star, r_tie, tie_mode, pad0;
+  int32_t t_star, r_tie, tie_mode, big_work;  // big_work: set at admission
   int32_t batch_n, goal_n, reg_n, cand_n;
   int32_t ngroups, tie_n, keep_n, accept_n;
   int32_t nsmall, nbig, big_tiles, err_line;

@@ -5,16 +5,18 @@
 //   pop      k_open_hist, k_open_threshold, k_open_scatter, k_batch_finalize:
 //            the B lexicographically smallest live OPEN labels (labels pruned
 //            since they were queued are skipped lazily, Section 5.1)
-//   goal     k_goal_merge: lines 11-13, P <- minimal(P + popped goal labels)
-//   prune    k_popcheck: lines 9-10 (PruneOPEN) applied to the popped labels
-//   expand   k_expand: lines 15-17, g' = g + c, F' = g' + h
-//   filter   k_pfilter: lines 19 / 29, drop F' that the goal front dominates
+//   goal     k_goal_pairs, k_goal_merge: Prune(P, l) and NotDominated(l, P),
+//            P <- minimal(P + goal labels)
+//   prune    k_popcheck: PruneOPEN applied to the popped labels
+//   expand   k_expand: g' = g + c, F' = g' + h over the out-arcs
+//   filter   k_pfilter: NotDominated(F', P), drop F' that the goal front dominates
 //   group    k_group_count, k_group_offsets, k_group_scatter: candidates by node
 //   check    k_group_process (one wave per group, one streamed pass over the
 //            node's frontier) or k_group_pairs + k_group_finish (large groups
-//            split into pair tiles): lines 22-28 plus dominance among the
+//            split into pair tiles): Duplicate, NotDominated and Prune against
+//            the node's labels (G_OP and G_CL together) plus dominance among the
 //            candidates of the same step
-//   insert   k_accept_scan, k_insert, k_step_end: lines 20-21 / 30-31
+//   insert   k_accept_scan, k_insert, k_step_end: new labels into OPEN and G_OP
 //
 // All arithmetic is exact int32.  Tiled kernels run on a (gx, slots) grid and
 // grid-stride over the slot's items; per-slot kernels run one 1024-thread
@@ -28,7 +30,8 @@ namespace mos {
 constexpr int NT_SLOT = 1024;  // threads of the one-workgroup-per-slot kernels
 constexpr int NT_TILE = 256;   // threads of the tiled kernels
 constexpr int GP_WAVES = NT_TILE / WAVE;
-constexpr int PCH = 256;       // goal-front entries per LDS chunk
+constexpr int PCH = 256;       // goal-front entries per LDS chunk (one per tiled thread)
+static_assert(PCH == NT_TILE, "goal tiles map one label to one thread");
 
 #define FOR_K(k) _Pragma("unroll") for (int k = 0; k < DM; ++k) if (k < d)
 
@@ -109,6 +112,41 @@ __device__ void bitonic_sort_blocked(int (&v)[E], int* lds) {
   }
 }
 
+// Workgroup-aggregated append of NQ flags per thread: one atomic per counter
+// and workgroup; pos[q] is the thread's position for counter q (-1 if !p[q]).
+// Every thread of the workgroup calls it (it synchronises the workgroup).
+template <int NQ>
+__device__ __forceinline__ void block_append(int32_t* const (&ctr)[NQ], const bool (&p)[NQ],
+                                             int (&pos)[NQ]) {
+  constexpr int NW = NT_TILE / WAVE;
+  __shared__ int sh[NQ][NW + 1];
+  const int w = threadIdx.x / WAVE;
+  uint64_t m[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    m[q] = ballot(p[q]);
+    if (lane_id() == 0) sh[q][w] = __popcll(m[q]);
+  }
+  __syncthreads();
+  if (threadIdx.x < NQ) {
+    const int q = threadIdx.x;
+    int tot = 0;
+#pragma unroll
+    for (int x = 0; x < NW; ++x) tot += sh[q][x];
+    sh[q][NW] = tot ? atomicAdd(ctr[q], tot) : 0;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    int base = sh[q][NW];
+#pragma unroll
+    for (int x = 0; x < NW; ++x)
+      if (x < w) base += sh[q][x];
+    pos[q] = p[q] ? base + rank_below(m[q]) : -1;
+  }
+  __syncthreads();
+}
+
 // ---------------------------------------------------------------- OPEN tiers
 // OPEN is split by a threshold T on F1: the near tier (F1 < T) is scanned by
 // every pop; the far tier (F1 >= T) is only touched when the near tier runs
@@ -178,6 +216,7 @@ __global__ __launch_bounds__(NT_TILE) void k_far_hist(Slot* slots, int32_t* hist
       }
       r_T = T + min(lo_i + 1, NB - 1);
     }
+    Sp->st[ST_FAR_SCAN] += n;
     Sp->r_all = r_all;
     Sp->r_T = r_T;
     Sp->r_moved = 0;
@@ -213,13 +252,17 @@ __global__ __launch_bounds__(NT_TILE) void k_far_move(Slot* slots) {
     }
     const bool move = live && (r_all || f < r_T);
     const bool keep = live && !move;
-    int p = agg_append(&Sp->r_moved, move);
+    int32_t* const ctr[2] = {&Sp->r_moved, &Sp->r_keep};
+    const bool fl[2] = {move, keep};
+    int pos[2];
+    block_append<2>(ctr, fl, pos);
+    int p = pos[0];
     if (move && base + p < S.open_cap) {
       NF[base + p] = f;
       NLb[base + p] = lab;
       mn = min(mn, f);
     }
-    p = agg_append(&Sp->r_keep, keep);
+    p = pos[1];
     if (keep && p < S.open_cap) {
       KF[p] = f;
       KL[p] = lab;
@@ -333,6 +376,7 @@ __global__ __launch_bounds__(NT_SLOT) void k_open_threshold(Slot* slots, int32_t
         Sp->t_all = 0;
       }
     }
+    Sp->st[ST_NEAR_SCAN] += Sp->open_n;
     Sp->t_star = t_star;
     Sp->r_tie = r;
     Sp->tie_mode = mode;
@@ -373,22 +417,26 @@ __global__ __launch_bounds__(NT_TILE) void k_open_scatter(Slot* slots) {
     const bool to_batch = live && b < t_star;
     const bool to_tie = live && mode && b == t_star;
     const bool to_keep = live && !to_batch && !to_tie;
-    int p = agg_append(&Sp->batch_n, to_batch);
+    const bool to_far = to_keep && !S.t_all && f >= S.T;  // spilled this step
+    const bool to_near = to_keep && !to_far;
+    int32_t* const ctr[4] = {&Sp->batch_n, &Sp->tie_n, &Sp->keep_n, &Sp->far_n};
+    const bool fl[4] = {to_batch, to_tie, to_near, to_far};
+    int pos[4];
+    block_append<4>(ctr, fl, pos);
+    int p = pos[0];
     if (to_batch && p < S.batch_cap) S.batch[p] = lab;
-    p = agg_append(&Sp->tie_n, to_tie);
+    p = pos[1];
     if (to_tie && p < S.tie_cap) {
       S.tie_f1[p] = f;
       S.tie_lab[p] = lab;
     }
-    const bool to_far = to_keep && !S.t_all && f >= S.T;  // spilled this step
-    const bool to_near = to_keep && !to_far;
-    p = agg_append(&Sp->keep_n, to_near);
+    p = pos[2];
     if (to_near && p < S.open_cap) {
       KF[p] = f;
       KL[p] = lab;
       kmin = min(kmin, f);
     }
-    p = agg_append(&Sp->far_n, to_far);
+    p = pos[3];
     if (to_far && p < S.open_cap) {
       FF[p] = f;
       FL[p] = lab;
@@ -444,14 +492,23 @@ __global__ __launch_bounds__(NT_SLOT) void k_batch_finalize(Slot* slots, GraphDe
     int32_t* TS = S.tie_st;  // 0 undecided, 1 taken, 2 not taken
     for (int i = threadIdx.x; i < n; i += NT_SLOT) TS[i] = 0;
     __syncthreads();
-    int und = n, word = 0;
-    int32_t* hist = lds;  // NB ints
+    // an inner bin holds a single F1 value: refinement starts at F2
+    int und = n, word = (S.t_star > 0 && S.t_star < NB - 1) ? 1 : 0, levels = 0;
+    int32_t* hist = lds;        // NB ints
+    int32_t* kc = lds + NB;     // the current key word of each entry, when they fit
+    constexpr int KC = 10240 - NB;
+    const bool cache = n <= KC;
     while (und > TIECAP && need > 0 && need < und) {
+      ++levels;
       if (threadIdx.x == 0) sh_a = INT32_MAX;
       __syncthreads();
       int mn = INT32_MAX;
       for (int i = threadIdx.x; i < n; i += NT_SLOT)
-        if (TS[i] == 0) mn = min(mn, key_word(S, G, S.tie_lab[i], word));
+        if (TS[i] == 0) {
+          const int x = key_word(S, G, S.tie_lab[i], word);
+          if (cache) kc[i] = x;
+          mn = min(mn, x);
+        }
       mn = wave_min(mn);
       if (lane_id() == 0) atomicMin(&sh_a, mn);
       for (int i = threadIdx.x; i < NB; i += NT_SLOT) hist[i] = 0;
@@ -459,7 +516,7 @@ __global__ __launch_bounds__(NT_SLOT) void k_batch_finalize(Slot* slots, GraphDe
       const int m = sh_a;
       for (int i = threadIdx.x; i < n; i += NT_SLOT)
         if (TS[i] == 0) {
-          const int64_t b = (int64_t)key_word(S, G, S.tie_lab[i], word) - m;
+          const int64_t b = (int64_t)(cache ? kc[i] : key_word(S, G, S.tie_lab[i], word)) - m;
           atomicAdd(&hist[b < NB - 1 ? (int)b : NB - 1], 1);
         }
       __syncthreads();
@@ -492,7 +549,7 @@ __global__ __launch_bounds__(NT_SLOT) void k_batch_finalize(Slot* slots, GraphDe
       const int inb = hist[bstar] - below;
       for (int i = threadIdx.x; i < n; i += NT_SLOT)
         if (TS[i] == 0) {
-          const int64_t b64 = (int64_t)key_word(S, G, S.tie_lab[i], word) - m;
+          const int64_t b64 = (int64_t)(cache ? kc[i] : key_word(S, G, S.tie_lab[i], word)) - m;
           const int b = b64 < NB - 1 ? (int)b64 : NB - 1;
           if (b < bstar) TS[i] = 1;
           else if (b > bstar) TS[i] = 2;
@@ -501,6 +558,11 @@ __global__ __launch_bounds__(NT_SLOT) void k_batch_finalize(Slot* slots, GraphDe
       und = inb;
       if (bstar < NB - 1) ++word;  // the undecided now share this word's value
       __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      Sp->st[ST_TIE] += n;
+      Sp->st[ST_T0 + 4] += levels;
+      Sp->st[ST_T0 + 5] += 1;
     }
     if (need == 0 || need >= und) {
       const int fill = need == 0 ? 2 : 1;
@@ -640,6 +702,7 @@ __global__ __launch_bounds__(NT_SLOT) void k_batch_finalize(Slot* slots, GraphDe
   for (int e = 0; e < E; ++e) {
     const int i = threadIdx.x * E + e;
     if (flags[e] == 1) {
+      if (pg < S.cand_cap) S.c_rej[pg] = 0;  // goal-step flag of this goal label
       S.goal_lab[pg++] = V[i];
     } else if (flags[e] == 2) {
       S.reg[pr] = V[i];
@@ -662,184 +725,12 @@ __global__ __launch_bounds__(NT_SLOT) void k_batch_finalize(Slot* slots, GraphDe
     Sp->accept_n = 0;
     Sp->st[ST_POPS] += nb;
     Sp->st[ST_GOAL_POPS] += goal_total;
-    if (deg_carry > S.cand_cap) {
+    if (deg_carry > S.cand_cap || goal_total > S.cand_cap) {
       Sp->status = S_OVERFLOW;
       Sp->err_line = __LINE__;
     } else if (nb == 0 && Sp->far_n == 0) {
       Sp->status = S_DONE;  // no live label left in OPEN
     }
-  }
-}
-
-// ---------------------------------------------------------------- goal step
-// P <- minimal(P ∪ G) for the goal labels G popped this step (Algorithm 1
-// lines 11-13).  A goal label is dropped if an old P entry weakly dominates it
-// or another goal label dominates it (equal vectors: the smaller label id
-// stays); an old entry is dropped if some goal label strictly dominates it.
-// The new front is written lexicographically sorted into the other buffer.
-template <int DM>
-__device__ __forceinline__ bool lex_less(const int32_t* a, const int32_t* b, int d) {
-  bool decided = false, less = false;
-#pragma unroll
-  for (int k = 0; k < DM; ++k)
-    if (k < d && !decided && a[k] != b[k]) {
-      decided = true;
-      less = a[k] < b[k];
-    }
-  return less;
-}
-
-template <int DM>
-__global__ __launch_bounds__(NT_SLOT) void k_goal_merge(Slot* slots) {
-  Slot* Sp = &slots[blockIdx.x];
-  const Slot S = *Sp;
-  if (S.status != S_RUN || S.goal_n == 0) return;
-  constexpr int GT = 256;  // goal labels per pass
-  __shared__ int32_t gv[DM][GT];
-  __shared__ int32_t glab[GT];
-  __shared__ int32_t gacc[GT];
-  __shared__ int tmp[NT_SLOT / WAVE];
-  const int d = S.d, pc = S.pool_cap, Pc = S.P_cap;
-  const int ng = S.goal_n;
-  const int np = S.P_n;
-  const int32_t* Pg = pick(S.Pg, S.P_sel);
-  const int32_t* Pl = pick(S.Plab, S.P_sel);
-  int32_t* Qg = pick(S.Pg, S.P_sel ^ 1);
-  int32_t* Ql = pick(S.Plab, S.P_sel ^ 1);
-  // scratch: prune flags of old entries and their survivor prefix; accepted
-  // goal labels are collected in `batch` (free after the pop)
-  int32_t* pflag = S.pscr;
-  int32_t* sprefix = S.pscr + (Pc + 1);
-  int32_t* acc_lab = S.batch;
-  if (np + ng > Pc) {
-    if (threadIdx.x == 0) {
-      Sp->status = S_OVERFLOW;
-      Sp->err_line = __LINE__;
-    }
-    return;
-  }
-  for (int i = threadIdx.x; i < np; i += NT_SLOT) pflag[i] = 0;
-  int na = 0;
-  int64_t pairs = 0;
-  for (int t0 = 0; t0 < ng; t0 += GT) {
-    const int nt = min(GT, ng - t0);
-    __syncthreads();
-    if ((int)threadIdx.x < nt) {
-      const int lab = S.goal_lab[t0 + threadIdx.x];
-      glab[threadIdx.x] = lab;
-      FOR_K(k) gv[k][threadIdx.x] = S.Lg[(size_t)k * pc + lab];
-      gacc[threadIdx.x] = 1;
-    }
-    __syncthreads();
-    // old entries against this tile of goal labels
-    for (int i = threadIdx.x; i < np; i += NT_SLOT) {
-      int32_t p[DM];
-      FOR_K(k) p[k] = Pg[(size_t)k * Pc + i];
-      bool pruned = false;
-      for (int j = 0; j < nt; ++j) {
-        bool le = true, ge = true, anylt = false;
-        FOR_K(k) {
-          const int gk = gv[k][j];
-          le = le && (p[k] <= gk);
-          ge = ge && (gk <= p[k]);
-          anylt = anylt || (gk < p[k]);
-        }
-        if (le) gacc[j] = 0;  // benign race: every writer stores 0
-        if (ge && anylt) pruned = true;
-      }
-      if (pruned) pflag[i] = 1;
-    }
-    __syncthreads();
-    // goal labels of this tile against every goal label
-    if ((int)threadIdx.x < nt && gacc[threadIdx.x]) {
-      const int me = threadIdx.x;
-      int32_t a[DM];
-      FOR_K(k) a[k] = gv[k][me];
-      const int mylab = glab[me];
-      bool rej = false;
-      for (int j = 0; j < ng && !rej; ++j) {
-        const int lb = S.goal_lab[j];
-        if (lb == mylab) continue;
-        bool le = true, eq = true;
-        FOR_K(k) {
-          const int bk = S.Lg[(size_t)k * pc + lb];
-          le = le && (bk <= a[k]);
-          eq = eq && (bk == a[k]);
-        }
-        if (le && (!eq || lb < mylab)) rej = true;
-      }
-      if (rej) gacc[me] = 0;
-    }
-    __syncthreads();
-    const int v = ((int)threadIdx.x < nt) ? gacc[threadIdx.x] : 0;
-    int tot;
-    const int pos = block_exscan<NT_SLOT>(v, &tot, tmp);
-    if (v) acc_lab[na + pos] = glab[threadIdx.x];
-    na += tot;
-    pairs += (int64_t)nt * np + (int64_t)nt * ng;
-  }
-  __syncthreads();
-  int carry = 0;
-  for (int base = 0; base < np; base += NT_SLOT) {
-    const int i = base + threadIdx.x;
-    const int alive = (i < np && !pflag[i]) ? 1 : 0;
-    int tot;
-    const int ex = block_exscan<NT_SLOT>(alive, &tot, tmp);
-    if (i < np) sprefix[i] = carry + ex;
-    carry += tot;
-  }
-  const int nsurv = carry;
-  if (threadIdx.x == 0) sprefix[np] = nsurv;
-  __syncthreads();
-  // output position of an old survivor i: sprefix[i] + #(accepted goal vectors
-  // below it); of an accepted goal vector q: #(old survivors below q) +
-  // #(accepted goal vectors below q).  All these vectors are distinct.
-  for (int i = threadIdx.x; i < np; i += NT_SLOT) {
-    if (pflag[i]) continue;
-    int32_t p[DM];
-    FOR_K(k) p[k] = Pg[(size_t)k * Pc + i];
-    int c = 0;
-    for (int j = 0; j < na; ++j) {
-      int32_t q[DM];
-      const int lb = acc_lab[j];
-      FOR_K(k) q[k] = S.Lg[(size_t)k * pc + lb];
-      if (lex_less<DM>(q, p, d)) ++c;
-    }
-    const int outpos = sprefix[i] + c;
-    FOR_K(k) Qg[(size_t)k * Pc + outpos] = p[k];
-    Ql[outpos] = Pl[i];
-  }
-  for (int j = threadIdx.x; j < na; j += NT_SLOT) {
-    const int lb = acc_lab[j];
-    int32_t q[DM];
-    FOR_K(k) q[k] = S.Lg[(size_t)k * pc + lb];
-    int lo_i = 0, hi_i = np;  // old entries lexicographically below q
-    while (lo_i < hi_i) {
-      const int mid = (lo_i + hi_i) >> 1;
-      int32_t p[DM];
-      FOR_K(k) p[k] = Pg[(size_t)k * Pc + mid];
-      if (lex_less<DM>(p, q, d)) lo_i = mid + 1; else hi_i = mid;
-    }
-    int c = 0;
-    for (int i = 0; i < na; ++i) {
-      if (i == j) continue;
-      const int lb2 = acc_lab[i];
-      int32_t r[DM];
-      FOR_K(k) r[k] = S.Lg[(size_t)k * pc + lb2];
-      if (lex_less<DM>(r, q, d)) ++c;
-    }
-    const int outpos = sprefix[lo_i] + c;
-    FOR_K(k) Qg[(size_t)k * Pc + outpos] = q[k];
-    Ql[outpos] = lb;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    Sp->P_n = nsurv + na;
-    Sp->P_sel = S.P_sel ^ 1;
-    Sp->st[ST_PPAIRS] += pairs;
-    // goal labels the front already covers were not processed (lazy PruneOPEN)
-    Sp->st[ST_POPS] -= ng - na;
-    Sp->st[ST_KILLED] += ng - na;
   }
 }
 
@@ -885,8 +776,208 @@ __device__ __forceinline__ bool chunk_dominates(const FrontChunk<DM>& ch, const 
   return dom != 0;
 }
 
+// ---------------------------------------------------------------- goal step
+// P <- minimal(P ∪ G) for the goal labels G popped this step (Prune(P, l) and
+// NotDominated(l, P) of Algorithm 1, for the whole batch of goal labels):
+//  * a goal label is rejected if an entry of P is <= it (dominated or equal),
+//    or another goal label of the step is <= it (equal vectors: the smaller
+//    label id stays);
+//  * an entry of P is removed if a goal label is strictly below it.
+// Removal writes INT32_MAX into every plane of the entry (a tombstone: no cost
+// reaches INT32_MAX, so it dominates nothing and is never matched); the front
+// is compacted once half of its entries are tombstones.  P is kept unordered;
+// the result is sorted when it is read out.
+//
+// k_goal_pairs: work items are (goal tile, chunk) pairs, the chunk being a
+// chunk of P or a tile of the step's goal labels, both staged in LDS.  A
+// tombstone written while another item reads the entry changes no outcome:
+// the goal label that removed it is itself <= every goal label the entry was
+// <= (and no entry of P is <= it, P being an antichain).
+template <int DM>
+__device__ __forceinline__ void pack_query(const int32_t (&x)[FrontChunk<DM>::NW * 4],
+                                           int4 (&Q)[FrontChunk<DM>::NW]) {
+#pragma unroll
+  for (int w = 0; w < FrontChunk<DM>::NW; ++w)
+    Q[w] = make_int4(x[4 * w], x[4 * w + 1], x[4 * w + 2], x[4 * w + 3]);
+}
+
+template <int DM>
+__device__ __forceinline__ void le_ne(const int4 (&r)[FrontChunk<DM>::NW], const int4 (&Q)[FrontChunk<DM>::NW],
+                                      int& le, int& ne) {
+  le = 1;
+  ne = 0;
+#pragma unroll
+  for (int w = 0; w < FrontChunk<DM>::NW; ++w) {
+    le &= (r[w].x <= Q[w].x) & (r[w].y <= Q[w].y) & (r[w].z <= Q[w].z) & (r[w].w <= Q[w].w);
+    ne |= (r[w].x != Q[w].x) | (r[w].y != Q[w].y) | (r[w].z != Q[w].z) | (r[w].w != Q[w].w);
+  }
+}
+
+template <int DM>
+__global__ __launch_bounds__(NT_TILE) void k_goal_pairs(Slot* slots) {
+  Slot* Sp = &slots[blockIdx.y];
+  const Slot S = *Sp;
+  if (S.status != S_RUN) return;
+  const int ng = S.goal_n, np = S.P_n;
+  if (ng == 0) return;
+  constexpr int NW = FrontChunk<DM>::NW;
+  const int ngt = (ng + PCH - 1) / PCH, npc = (np + PCH - 1) / PCH;
+  const int per = npc + ngt;  // per goal tile: the chunks of P, then the goal tiles
+  const int items = ngt * per;
+  if ((int)blockIdx.x >= items) return;
+  __shared__ FrontChunk<DM> other;   // chunk of P or tile of goal labels
+  __shared__ FrontChunk<DM> mine;    // this item's goal tile
+  __shared__ int32_t olab[PCH];
+  const int d = S.d, pc = S.pool_cap, Pc = S.P_cap;
+  int32_t* Pg = pick(S.Pg, S.P_sel);
+  int32_t* gflag = S.c_rej;  // per goal label: rejected (zeroed at the pop)
+  const int t = threadIdx.x;
+  int64_t pairs = 0;
+  int dead = 0;
+  for (int it = blockIdx.x; it < items; it += gridDim.x) {
+    const int gt = it / per, oc = it - gt * per;
+    const int t0 = gt * PCH, nt = min(PCH, ng - t0);
+    int32_t x[NW * 4];
+    int mylab = -1;
+    if (t < nt) {
+      mylab = S.goal_lab[t0 + t];
+#pragma unroll
+      for (int k = 0; k < NW * 4; ++k) x[k] = k < d ? S.Lg[(size_t)k * pc + mylab] : INT32_MIN;
+    } else {
+#pragma unroll
+      for (int k = 0; k < NW * 4; ++k) x[k] = INT32_MAX;
+    }
+    int4 G[NW];
+    pack_query<DM>(x, G);
+    __syncthreads();  // the previous item is done with the LDS tiles
+    bool rej = false;
+    if (oc < npc) {
+      const int p0 = oc * PCH, npt = min(PCH, np - p0);
+#pragma unroll
+      for (int w = 0; w < NW; ++w) mine.w[t][w] = G[w];
+      stage_chunk<DM>(other, Pg, Pc, p0, npt, d);
+      __syncthreads();
+      if (t < nt) rej = chunk_dominates<DM>(other, G);
+      if (t < npt && other.w[t][0].x != INT32_MAX) {
+        int4 Q[NW];
+#pragma unroll
+        for (int w = 0; w < NW; ++w) Q[w] = other.w[t][w];
+        int hit = 0;
+#pragma unroll 4
+        for (int r = 0; r < PCH; ++r) {
+          int4 R[NW];
+#pragma unroll
+          for (int w = 0; w < NW; ++w) R[w] = mine.w[r][w];
+          int le, ne;
+          le_ne<DM>(R, Q, le, ne);
+          hit |= le & ne;
+        }
+        if (hit && atomicExch(&Pg[p0 + t], INT32_MAX) != INT32_MAX) {
+          for (int k = 1; k < d; ++k) Pg[(size_t)k * Pc + p0 + t] = INT32_MAX;
+          ++dead;
+        }
+      }
+      pairs += (int64_t)nt * npt;
+    } else {
+      const int u0 = (oc - npc) * PCH, nu = min(PCH, ng - u0);
+      if (t < nu) {
+        const int lb = S.goal_lab[u0 + t];
+        olab[t] = lb;
+        int32_t y[NW * 4];
+#pragma unroll
+        for (int k = 0; k < NW * 4; ++k) y[k] = k < d ? S.Lg[(size_t)k * pc + lb] : INT32_MIN;
+#pragma unroll
+        for (int w = 0; w < NW; ++w)
+          other.w[t][w] = make_int4(y[4 * w], y[4 * w + 1], y[4 * w + 2], y[4 * w + 3]);
+      }
+      __syncthreads();
+      if (t < nt) {
+        for (int r = 0; r < nu; ++r) {
+          int4 R[NW];
+#pragma unroll
+          for (int w = 0; w < NW; ++w) R[w] = other.w[r][w];
+          int le, ne;
+          le_ne<DM>(R, G, le, ne);
+          const int lb = olab[r];
+          rej = rej | (le && lb != mylab && (ne || lb < mylab));
+        }
+      }
+      pairs += (int64_t)nt * nu;
+    }
+    if (rej) gflag[t0 + t] = 1;
+  }
+  // pairs are block-uniform; tombstones are counted per thread
+  const int64_t dsum = wave_sum64(dead);
+  if (lane_id() == 0 && dsum) atomicAdd(&Sp->P_dead, (int)dsum);
+  if (t == 0 && pairs) atomicAdd((unsigned long long*)&Sp->st[ST_PPAIRS], (unsigned long long)pairs);
+}
+
+// Append the accepted goal labels to P (in batch order) and compact P once
+// half of its entries are tombstones (stable, into the other buffer).
+template <int DM>
+__global__ __launch_bounds__(NT_SLOT) void k_goal_merge(Slot* slots) {
+  Slot* Sp = &slots[blockIdx.x];
+  const Slot S = *Sp;
+  if (S.status != S_RUN || S.goal_n == 0) return;
+  __shared__ int tmp[NT_SLOT / WAVE];
+  const int d = S.d, pc = S.pool_cap, Pc = S.P_cap;
+  const int ng = S.goal_n, np = S.P_n;
+  int32_t* Pg = pick(S.Pg, S.P_sel);
+  int32_t* Pl = pick(S.Plab, S.P_sel);
+  if (np + ng > Pc) {
+    if (threadIdx.x == 0) {
+      Sp->status = S_OVERFLOW;
+      Sp->err_line = __LINE__;
+    }
+    return;
+  }
+  int na = 0;
+  for (int base = 0; base < ng; base += NT_SLOT) {
+    const int i = base + threadIdx.x;
+    const int a = (i < ng && !S.c_rej[i]) ? 1 : 0;
+    int tot;
+    const int pos = block_exscan<NT_SLOT>(a, &tot, tmp);
+    if (a) {
+      const int lab = S.goal_lab[i];
+      FOR_K(k) Pg[(size_t)k * Pc + np + na + pos] = S.Lg[(size_t)k * pc + lab];
+      Pl[np + na + pos] = lab;
+    }
+    na += tot;
+  }
+  const int n1 = np + na, dead = S.P_dead;
+  int live = n1, sel = S.P_sel;
+  if (dead > 0 && 2 * dead >= n1) {
+    __syncthreads();  // appended entries visible to the whole workgroup
+    int32_t* Qg = pick(S.Pg, S.P_sel ^ 1);
+    int32_t* Ql = pick(S.Plab, S.P_sel ^ 1);
+    int carry = 0;
+    for (int base = 0; base < n1; base += NT_SLOT) {
+      const int i = base + threadIdx.x;
+      const int a = (i < n1 && Pg[i] != INT32_MAX) ? 1 : 0;
+      int tot;
+      const int pos = block_exscan<NT_SLOT>(a, &tot, tmp);
+      if (a) {
+        FOR_K(k) Qg[(size_t)k * Pc + carry + pos] = Pg[(size_t)k * Pc + i];
+        Ql[carry + pos] = Pl[i];
+      }
+      carry += tot;
+    }
+    live = carry;
+    sel ^= 1;
+  }
+  if (threadIdx.x == 0) {
+    Sp->P_n = live;
+    Sp->P_sel = sel;
+    if (live != n1) Sp->P_dead = 0;
+    Sp->st[ST_PREAD] += (int64_t)np * ((ng + PCH - 1) / PCH);
+    // goal labels the front already covers were not processed (lazy PruneOPEN)
+    Sp->st[ST_POPS] -= ng - na;
+    Sp->st[ST_KILLED] += ng - na;
+  }
+}
+
 // The paper's PruneOPEN drops every open label whose F the goal front
-// dominates (Algorithm 1 lines 9-10); here it is applied lazily to the
+// dominates (Algorithm 1); here it is applied lazily to the
 // popped regular labels (weak dominance), after this step's goal labels were
 // merged into the front.  A dropped label is not expanded.  Work items are
 // (label tile, front chunk) pairs.
@@ -937,7 +1028,7 @@ __global__ __launch_bounds__(NT_TILE) void k_popcheck(Slot* slots, GraphDev G) {
 
 // ---------------------------------------------------------------- expand
 // One thread per candidate (flat index over the regular labels' out-arcs):
-// g' = g + c(e), F' = g' + h(v') (Algorithm 1 lines 16-17).  A target that
+// g' = g + c(e), F' = g' + h(v') (Algorithm 1, expansion).  A target that
 // cannot reach the goal is dropped at once.
 template <int DM>
 __global__ __launch_bounds__(NT_TILE) void k_expand(Slot* slots, GraphDev G) {
@@ -947,7 +1038,7 @@ __global__ __launch_bounds__(NT_TILE) void k_expand(Slot* slots, GraphDev G) {
   const int M = S.cand_n;
   const int d = S.d, pc = S.pool_cap, cc = S.cand_cap, n = G.n;
   const int reg_n = S.reg_n;
-  const int np = S.P_n;
+  const int np = S.P_n - S.P_dead;  // live goal-front entries
   int64_t ncand = 0, npairs = 0;
   for (int f = blockIdx.x * NT_TILE + threadIdx.x; f < M; f += gridDim.x * NT_TILE) {
     int lo_i = 0, hi_i = reg_n - 1;  // regular label owning flat index f
@@ -987,7 +1078,7 @@ __global__ __launch_bounds__(NT_TILE) void k_expand(Slot* slots, GraphDev G) {
 
 // ---------------------------------------------------------------- goal-front filter
 // Drop a candidate whose F' is weakly dominated by a goal-front entry
-// (Algorithm 1 lines 19 and 29; weak dominance: a completion of F' = p
+// (NotDominated(F', P) of Algorithm 1; weak dominance: a completion of F' = p
 // cannot improve on p).  Work items are (candidate tile, front chunk) pairs so
 // that a large front spreads over the whole chip; every writer stores 0.
 template <int DM>
@@ -1061,7 +1152,7 @@ __global__ __launch_bounds__(NT_SLOT) void k_group_offsets(Slot* slots) {
       sz = S.grp_cnt[v];
       cnt = S.node[v].count;
     }
-    const bool big = i < ng && (sz > WAVE || (int64_t)sz * (cnt + sz) > BIG_WORK);
+    const bool big = i < ng && (sz > WAVE || (int64_t)sz * (cnt + sz) > S.big_work);
     const bool small = i < ng && !big;
     const int nct = (sz + WAVE - 1) / WAVE, nft = (cnt + WAVE - 1) / WAVE;
     const int tiles = big ? nct * nct + nft * nct : 0;
@@ -1082,6 +1173,8 @@ __global__ __launch_bounds__(NT_SLOT) void k_group_offsets(Slot* slots) {
     nt += tt;
   }
   if (threadIdx.x == 0) {
+    Sp->st[ST_T0 + 6] += nb;
+    Sp->st[ST_T0 + 7] += nt;
     S.big_toff[nb] = nt;
     Sp->nsmall = ns;
     Sp->nbig = nb;
@@ -1099,6 +1192,11 @@ __global__ __launch_bounds__(NT_TILE) void k_group_scatter(Slot* slots) {
     const int gid = S.grp_id[S.c_node[f]];
     S.order[S.grp_off[gid] + S.c_rank[f]] = f;
   }
+}
+
+// OPEN tier an accepted candidate joins, by its F1: 1 near (F1 < T), 2 far.
+__device__ __forceinline__ int open_tier(const Slot& S, int f1) {
+  return (S.t_all || f1 < S.T) ? 1 : 2;
 }
 
 // Take a new frontier block when `need` entries do not fit the node's block.
@@ -1135,8 +1233,8 @@ __device__ __forceinline__ bool frontier_dest(Slot* Sp, const Slot& S, const Nod
 //  B. survivors against the live frontier of v, U entries per lane per pass
 //     (the next pass is loaded before the current one is compared); each
 //     surviving candidate is broadcast from its lane: it is rejected if an entry
-//     weakly dominates it (dominated or duplicate, Algorithm 1 lines 22-25); an
-//     entry is pruned if a candidate strictly dominates it (lines 26-28; a
+//     weakly dominates it (dominated or duplicate: Duplicate and NotDominated); an
+//     entry is pruned if a candidate strictly dominates it (Prune; a
 //     rejected candidate can dominate no live entry because the frontier is an
 //     antichain, so no test on rejection is needed); pruned entries are marked
 //     dead in the pool and the block is compacted as it is streamed;
@@ -1276,7 +1374,7 @@ __global__ __launch_bounds__(NT_TILE) void k_group_process(Slot* slots) {
         if (kk < d) fw[w + (int64_t)kk * dcap] = ci[kk];
       fw[w + (int64_t)d * dcap] = -1;
       S.c_fslot[fi] = w + (int64_t)d * dcap;
-      S.c_acc[fi] = 1;
+      S.c_acc[fi] = open_tier(S, ci[0] + S.h[v]);
     }
     cursor += __popcll(accm);
     if (lane == 0) {
@@ -1458,7 +1556,7 @@ __global__ __launch_bounds__(NT_TILE) void k_group_finish(Slot* slots) {
         FOR_K(kk) fw[w + (int64_t)kk * dcap] = S.c_g[(size_t)kk * cc + fj];
         fw[w + (int64_t)d * dcap] = -1;
         S.c_fslot[fj] = w + (int64_t)d * dcap;
-        S.c_acc[fj] = 1;
+        S.c_acc[fj] = open_tier(S, S.c_g[fj] + S.h[v]);
       }
       cursor += __popcll(m);
     }
@@ -1480,35 +1578,76 @@ __global__ __launch_bounds__(NT_TILE) void k_group_finish(Slot* slots) {
 }
 
 // ---------------------------------------------------------------- insert
-__global__ __launch_bounds__(NT_SLOT) void k_accept_scan(Slot* slots, GraphDev G) {
+// Ranks of the accepted candidates in flat order: c_rank = rank among all
+// accepted (label id offset), c_rej = rank within the OPEN tier it joins
+// (c_acc: 0 rejected, 1 near, 2 far).  Wave w owns a contiguous segment; one
+// counting pass, one exchange of per-wave totals, one writing pass.
+__global__ __launch_bounds__(NT_SLOT) void k_accept_scan(Slot* slots) {
   Slot* Sp = &slots[blockIdx.x];
   const Slot S = *Sp;
   if (S.status != S_RUN) return;
-  __shared__ int tmp[NT_SLOT / WAVE];
+  constexpr int NW = NT_SLOT / WAVE;
+  __shared__ int wn[NW], wf[NW];
   const int M = S.cand_n;
-  // label ids follow the flat candidate order; OPEN positions are ranks
-  // within the tier the label joins (c_rej is free again after the checks)
-  int carry = 0, cn = 0, cf = 0;
-  for (int base = 0; base < M; base += NT_SLOT) {
-    const int i = base + threadIdx.x;
-    const int a = i < M ? S.c_acc[i] : 0;
-    bool near = false;
-    if (a) near = S.t_all || S.c_g[i] + S.h[S.c_node[i]] < S.T;
-    int tot, tn, tf;
-    const int ex = block_exscan<NT_SLOT>(a, &tot, tmp);
-    const int en = block_exscan<NT_SLOT>(a && near ? 1 : 0, &tn, tmp);
-    const int ef = block_exscan<NT_SLOT>(a && !near ? 1 : 0, &tf, tmp);
-    if (i < M) S.c_rank[i] = carry + ex;
-    if (a) S.c_rej[i] = near ? cn + en : cf + ef;
-    carry += tot;
-    cn += tn;
-    cf += tf;
+  const int w = threadIdx.x / WAVE, lane = lane_id();
+  const int seg = ((M + NW - 1) / NW + WAVE - 1) / WAVE * WAVE;
+  const int lo = min(M, w * seg), hi = min(M, lo + seg);
+  // counting pass: AU independent loads per lane in flight
+  constexpr int AU = 8;
+  int cn = 0, cf = 0;
+  for (int b = lo; b < hi; b += AU * WAVE) {
+    int a[AU];
+#pragma unroll
+    for (int u = 0; u < AU; ++u) {
+      const int i = b + u * WAVE + lane;
+      a[u] = i < hi ? S.c_acc[i] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < AU; ++u) {
+      cn += __popcll(ballot(a[u] == 1));
+      cf += __popcll(ballot(a[u] == 2));
+    }
+  }
+  if (lane == 0) {
+    wn[w] = cn;
+    wf[w] = cf;
+  }
+  __syncthreads();
+  int bn = 0, bf = 0, tn = 0, tf = 0;
+#pragma unroll
+  for (int x = 0; x < NW; ++x) {
+    if (x < w) {
+      bn += wn[x];
+      bf += wf[x];
+    }
+    tn += wn[x];
+    tf += wf[x];
+  }
+  for (int b = lo; b < hi; b += AU * WAVE) {
+    int a[AU];
+#pragma unroll
+    for (int u = 0; u < AU; ++u) {
+      const int i = b + u * WAVE + lane;
+      a[u] = i < hi ? S.c_acc[i] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < AU; ++u) {
+      const int i = b + u * WAVE + lane;
+      const uint64_t mn = ballot(a[u] == 1), mf = ballot(a[u] == 2);
+      if (a[u]) {
+        const int rn = bn + rank_below(mn), rf = bf + rank_below(mf);
+        S.c_rank[i] = rn + rf;
+        S.c_rej[i] = a[u] == 1 ? rn : rf;
+      }
+      bn += __popcll(mn);
+      bf += __popcll(mf);
+    }
   }
   if (threadIdx.x == 0) {
-    Sp->accept_n = carry;
-    Sp->accept_near = cn;
-    Sp->accept_far = cf;
-    if (S.n_labels + carry > S.pool_cap || S.keep_n + cn > S.open_cap || S.far_n + cf > S.open_cap) {
+    Sp->accept_n = tn + tf;
+    Sp->accept_near = tn;
+    Sp->accept_far = tf;
+    if (S.n_labels + tn + tf > S.pool_cap || S.keep_n + tn > S.open_cap || S.far_n + tf > S.open_cap) {
       Sp->status = S_OVERFLOW;
       Sp->err_line = __LINE__;
     }
@@ -1541,7 +1680,7 @@ __global__ __launch_bounds__(NT_TILE) void k_insert(Slot* slots, GraphDev G) {
     S.fw[S.c_fslot[f]] = id;
     const int f1 = S.c_g[f] + S.h[v];
     const int q = S.c_rej[f];  // rank within its tier
-    if (S.t_all || f1 < S.T) {
+    if (S.c_acc[f] == 1) {
       KF[keep + q] = f1;
       KL[keep + q] = id;
       mn = min(mn, f1);
@@ -1572,17 +1711,18 @@ __global__ void k_step_end(Slot* slots, int nslots) {
 
 // ---------------------------------------------------------------- launchers
 const char* const kStepKernelNames[kStepKernels] = {
-    "k_far_hist",    "k_far_move",       "k_open_hist",   "k_open_threshold", "k_open_scatter",  "k_batch_finalize", "k_goal_merge",
+    "k_far_hist",    "k_far_move",       "k_open_hist",   "k_open_threshold", "k_open_scatter",  "k_batch_finalize", "k_goal_pairs", "k_goal_merge",
     "k_popcheck",    "k_expand",         "k_pfilter",       "k_group_count",    "k_group_offsets",
     "k_group_scatter", "k_group_process", "k_group_pairs",  "k_group_finish",   "k_accept_scan",
     "k_insert",      "k_step_end"};
 
 template <int DM>
-static void launch_step_dm(const StepArgs& a, hipStream_t st, hipEvent_t* ev) {
+static void launch_step_dm(const StepArgs& a, hipStream_t st, hipEvent_t* ev, uint32_t mask) {
   const dim3 tiled(a.gx, a.nslots), per(a.nslots);
   int i = 0;
   auto mark = [&]() {
-    if (ev) hipEventRecord(ev[i], st);
+    const bool need = i == kStepKernels || ((mask >> i) & 1u) || (i > 0 && ((mask >> (i - 1)) & 1u));
+    if (ev && need) hipEventRecord(ev[i], st);
     ++i;
   };
   mark(); hipLaunchKernelGGL(k_far_hist, tiled, dim3(NT_TILE), 0, st, a.slots, a.hist);
@@ -1591,6 +1731,7 @@ static void launch_step_dm(const StepArgs& a, hipStream_t st, hipEvent_t* ev) {
   mark(); hipLaunchKernelGGL(k_open_threshold, per, dim3(NT_SLOT), 0, st, a.slots, a.hist);
   mark(); hipLaunchKernelGGL(k_open_scatter, tiled, dim3(NT_TILE), 0, st, a.slots);
   mark(); hipLaunchKernelGGL(k_batch_finalize<DM>, per, dim3(NT_SLOT), 0, st, a.slots, a.G);
+  mark(); hipLaunchKernelGGL(k_goal_pairs<DM>, tiled, dim3(NT_TILE), 0, st, a.slots);
   mark(); hipLaunchKernelGGL(k_goal_merge<DM>, per, dim3(NT_SLOT), 0, st, a.slots);
   mark(); hipLaunchKernelGGL(k_popcheck<DM>, tiled, dim3(NT_TILE), 0, st, a.slots, a.G);
   mark(); hipLaunchKernelGGL(k_expand<DM>, tiled, dim3(NT_TILE), 0, st, a.slots, a.G);
@@ -1601,7 +1742,7 @@ static void launch_step_dm(const StepArgs& a, hipStream_t st, hipEvent_t* ev) {
   mark(); hipLaunchKernelGGL(k_group_process<DM>, tiled, dim3(NT_TILE), 0, st, a.slots);
   mark(); hipLaunchKernelGGL(k_group_pairs<DM>, tiled, dim3(NT_TILE), 0, st, a.slots);
   mark(); hipLaunchKernelGGL(k_group_finish<DM>, tiled, dim3(NT_TILE), 0, st, a.slots);
-  mark(); hipLaunchKernelGGL(k_accept_scan, per, dim3(NT_SLOT), 0, st, a.slots, a.G);
+  mark(); hipLaunchKernelGGL(k_accept_scan, per, dim3(NT_SLOT), 0, st, a.slots);
   mark(); hipLaunchKernelGGL(k_insert<DM>, tiled, dim3(NT_TILE), 0, st, a.slots, a.G);
   mark(); hipLaunchKernelGGL(k_step_end, dim3((a.nslots + 63) / 64), dim3(64), 0, st, a.slots, a.nslots);
   mark();
@@ -1616,14 +1757,14 @@ int dm_for(int d) {
   return 8;
 }
 
-void launch_step(const StepArgs& a, hipStream_t st, hipEvent_t* ev) {
+void launch_step(const StepArgs& a, hipStream_t st, hipEvent_t* ev, uint32_t mask) {
   switch (a.dm) {
-    case 2: launch_step_dm<2>(a, st, ev); break;
-    case 3: launch_step_dm<3>(a, st, ev); break;
-    case 4: launch_step_dm<4>(a, st, ev); break;
-    case 5: launch_step_dm<5>(a, st, ev); break;
-    case 6: launch_step_dm<6>(a, st, ev); break;
-    default: launch_step_dm<8>(a, st, ev); break;
+    case 2: launch_step_dm<2>(a, st, ev, mask); break;
+    case 3: launch_step_dm<3>(a, st, ev, mask); break;
+    case 4: launch_step_dm<4>(a, st, ev, mask); break;
+    case 5: launch_step_dm<5>(a, st, ev, mask); break;
+    case 6: launch_step_dm<6>(a, st, ev, mask); break;
+    default: launch_step_dm<8>(a, st, ev, mask); break;
   }
 }
 

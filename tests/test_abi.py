@@ -41,6 +41,15 @@ def test_validation_precedes_device(mos):
     # overflow risk: 2*sum + max > INT32_MAX
     c = g.cost.copy(); c[0, 0] = 2**30
     assert _create(mos, g.n, g.row_ptr, g.col, c, 3)[0] == mos.MOS_E_OVERFLOW_RISK
+    # the bound is strict: 2*sum + max == INT32_MAX is refused, one less is not
+    rp2 = np.array([0, 1, 2], dtype=np.int64)
+    col2 = np.array([1, 0], dtype=np.int32)
+    edge = np.array([[715827881], [2]], dtype=np.int32)   # 2*(a+b) + a == 2**31 - 1
+    assert _create(mos, 2, rp2, col2, edge, 1)[0] == mos.MOS_E_OVERFLOW_RISK
+    st, h = _create(mos, 2, rp2, col2, edge - np.array([[1], [0]], dtype=np.int32), 1)
+    assert st != mos.MOS_E_OVERFLOW_RISK
+    if st == mos.MOS_OK:
+        mos.raw.mos_graph_destroy(h)
     # target out of range
     col = g.col.copy(); col[5] = g.n
     assert _create(mos, g.n, g.row_ptr, col, g.cost, 3)[0] == mos.MOS_E_INVALID_ARG
