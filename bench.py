@@ -48,6 +48,9 @@ def parse():
                     help="Manhattan distance range of those queries")
     ap.add_argument("--query-width", type=int, default=256,
                     help="batch width B of every query in that comparison")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB 4 times (a kernel of known "
+                         "HBM traffic, to scale hardware byte counters) and exit")
     return ap.parse_args()
 
 
@@ -137,6 +140,19 @@ def main():
 
     import gen
     import paper_2411_16667_amd as mos
+
+    if a.copy_calibration > 0:
+        import torch
+
+        n = a.copy_calibration << 18  # int32 elements
+        src = torch.ones(n, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(4):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_read": 4 * n, "bytes_written": 4 * n,
+                          "dispatches": 4}))
+        return
 
     g, s, t = gen.config2(0)
     G = mos.Graph.from_gen(g)

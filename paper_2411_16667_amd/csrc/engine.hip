@@ -49,7 +49,10 @@ static void hip_check(hipError_t e, const char* what, int line) {
                        hipGetErrorString(e));
   }
 }
-#define HIPCHK(x) hip_check((x), #x, __LINE__)
+// line of the HIP call in progress (or last finished), for errors raised
+// inside the runtime as C++ exceptions
+static thread_local int g_site = 0;
+#define HIPCHK(x) (g_site = __LINE__, hip_check((x), #x, __LINE__))
 
 static mos_status set_err(mos_status s, const std::string& m) {
   g_last_error = m;
@@ -65,7 +68,8 @@ static mos_status guarded(F&& f) {
   } catch (const std::bad_alloc&) {
     return set_err(MOS_E_OUT_OF_MEMORY, "host allocation failed");
   } catch (const std::exception& e) {
-    return set_err(MOS_E_DEVICE, e.what());
+    return set_err(MOS_E_DEVICE, std::string(e.what()) + " (raised inside the HIP runtime; last "
+                                     "HIP call at engine line " + std::to_string(g_site) + ")");
   }
 }
 
@@ -252,7 +256,7 @@ static int64_t fixed_bytes(int64_t n, int d, int batch_cap, int cand_cap, int ti
 static bool plan_layout(const mos_graph* g, int d, int B, int64_t budget, int64_t label_limit,
                         Layout* L) {
   L->B = B;
-  L->batch_cap = std::min(2 * B, BATCH_SORT);
+  L->batch_cap = std::min(2 * B, BATCH_MAX);
   L->cand_cap = L->batch_cap * std::max(1, g->maxdeg);
   L->tie_cap = TIECAP;
   const int64_t fixed = fixed_bytes(g->n, d, L->batch_cap, L->cand_cap, 0);
@@ -646,7 +650,9 @@ class Engine {
       const Slot& d = hslots_[0];
       std::fprintf(stderr, "[mos] phase ticks:");
       for (int i = 0; i < 8; ++i) std::fprintf(stderr, " %lld", (long long)d.st[ST_T0 + i]);
-      std::fprintf(stderr, "\n");
+      std::fprintf(stderr, " | near %lld far %lld tie %lld front-reads %lld\n",
+                   (long long)d.st[ST_NEAR_SCAN], (long long)d.st[ST_FAR_SCAN],
+                   (long long)d.st[ST_TIE], (long long)d.st[ST_PREAD]);
     }
     std::fprintf(stderr, "[mos] resident %d\n", busy_count());
     std::fflush(stderr);
@@ -941,8 +947,8 @@ static mos_status read_opts(const mos_options* o, Opts* out) {
       r.steps = o->steps_per_poll;
     if (o->struct_size >= sizeof(mos_options)) r.profile = (uint32_t)o->profile_kernels;
   }
-  if (r.B < 1 || r.B > BATCH_SORT / 2)
-    return set_err(MOS_E_INVALID_ARG, "batch_width must lie in [1, 4096]");
+  if (r.B < 1 || r.B > BATCH_MAX)
+    return set_err(MOS_E_INVALID_ARG, "batch_width must lie in [1, 16384]");
   if (r.max_slots < 0 || r.label_limit < 0 || r.mem_budget < 0 || r.n_objectives < 0)
     return set_err(MOS_E_INVALID_ARG, "negative option");
   if (r.steps > 1024) return set_err(MOS_E_INVALID_ARG, "steps_per_poll too large");

@@ -18,7 +18,7 @@ constexpr int NB = 4096;          // OPEN histogram bins: exact F1 values lo..lo
 constexpr int TIECAP = 256;       // tie sets up to this size are ranked in LDS; larger ones
                                   // are first narrowed by exact radix refinement
 constexpr int MINCAP = 8;         // smallest frontier block, in entries
-constexpr int BATCH_SORT = 8192;  // largest popped batch (LDS sort by label id)
+constexpr int BATCH_MAX = 16384;  // largest popped batch (16 entries per thread of one workgroup)
 // near-tier sizing, in multiples of B: refill below LOW, refill up to TARGET,
 // spill to far above HIGH (keeping TARGET)
 constexpr int NEAR_LOW = 4, NEAR_TARGET = 16, NEAR_HIGH = 48;

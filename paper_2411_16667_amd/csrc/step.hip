@@ -64,54 +64,6 @@ __device__ int block_exscan(int v, int* total, int* tmp /* >= NT/64 ints */) {
   return before + x - v;
 }
 
-// Bitonic sort of E*NT int keys held in registers (thread t holds elements
-// t*E .. t*E+E-1): partners inside a thread are compared in registers,
-// partners in the same wave through lane shuffles, and only partners in other
-// waves through LDS (lds: E*NT ints).
-template <int E, int NT>
-__device__ void bitonic_sort_blocked(int (&v)[E], int* lds) {
-  const int t = threadIdx.x;
-  constexpr int n = E * NT;
-  for (int k = 2; k <= n; k <<= 1) {
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      if (j < E) {
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-          const int p = e ^ j;
-          if (p > e) {
-            const bool asc = ((t * E + e) & k) == 0;
-            const int a = v[e], b = v[p];
-            const bool sw = asc ? (b < a) : (a < b);
-            v[e] = sw ? b : a;
-            v[p] = sw ? a : b;
-          }
-        }
-      } else if (j < E * WAVE) {
-        const int lm = j / E;
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-          const int i = t * E + e;
-          const int other = __shfl_xor(v[e], lm);
-          const bool keep_min = (((i & j) == 0) == ((i & k) == 0));
-          v[e] = keep_min ? min(v[e], other) : max(v[e], other);
-        }
-      } else {
-#pragma unroll
-        for (int e = 0; e < E; ++e) lds[t * E + e] = v[e];
-        __syncthreads();
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-          const int i = t * E + e;
-          const int other = lds[i ^ j];
-          const bool keep_min = (((i & j) == 0) == ((i & k) == 0));
-          v[e] = keep_min ? min(v[e], other) : max(v[e], other);
-        }
-        __syncthreads();
-      }
-    }
-  }
-}
-
 // Workgroup-aggregated append of NQ flags per thread: one atomic per counter
 // and workgroup; pos[q] is the thread's position for counter q (-1 if !p[q]).
 // Every thread of the workgroup calls it (it synchronises the workgroup).
@@ -453,23 +405,56 @@ __device__ __forceinline__ int key_word(const Slot& S, const GraphDev& G, int la
   return S.Lg[(size_t)w * S.pool_cap + lab] + S.h[(size_t)w * G.n + v];
 }
 
-// Sort the popped label ids ascending into V[0 .. E*NT_SLOT) (padding at the end).
+// Goal/regular split of the nb popped labels (thread t owns batch positions
+// t*E .. t*E+E-1): goal labels to goal_lab (their goal-step flags cleared),
+// regular labels to reg with the exclusive prefix of their out-degrees.
 template <int E>
-__device__ void sort_batch(const Slot& S, int nb, int32_t* V) {
-  int v[E];
+__device__ void split_batch(const Slot& S, const GraphDev& G, int nb, int* tmp, int* goal_total,
+                            int* reg_total, int* deg_total) {
+  const int goal = S.goal;
+  int cg = 0, cr = 0, cdeg = 0;
+  int labs[E], kind[E], degs[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int i = threadIdx.x * E + e;
-    v[e] = i < nb ? S.batch[i] : INT32_MAX;
+    labs[e] = 0;
+    kind[e] = 0;
+    degs[e] = 0;
+    if (i < nb) {
+      const int lab = S.batch[i];
+      const int v = S.Lnode[lab];
+      labs[e] = lab;
+      if (v == goal) {
+        kind[e] = 1;
+        ++cg;
+      } else {
+        kind[e] = 2;
+        degs[e] = G.row_ptr[v + 1] - G.row_ptr[v];
+        ++cr;
+        cdeg += degs[e];
+      }
+    }
   }
-  bitonic_sort_blocked<E, NT_SLOT>(v, V);
+  int pg = block_exscan<NT_SLOT>(cg, goal_total, tmp);
+  int pr = block_exscan<NT_SLOT>(cr, reg_total, tmp);
+  int pd = block_exscan<NT_SLOT>(cdeg, deg_total, tmp);
 #pragma unroll
-  for (int e = 0; e < E; ++e) V[threadIdx.x * E + e] = v[e];
-  __syncthreads();
+  for (int e = 0; e < E; ++e) {
+    if (kind[e] == 1) {
+      if (pg < S.cand_cap) S.c_rej[pg] = 0;  // goal-step flag of this goal label
+      S.goal_lab[pg++] = labs[e];
+    } else if (kind[e] == 2) {
+      S.reg[pr] = labs[e];
+      S.reg_off[pr] = pd;
+      S.reg_kill[pr] = 0;
+      ++pr;
+      pd += degs[e];
+    }
+  }
 }
 
-// Finish the pop: exact selection inside the tie bin, canonical batch order
-// (ascending label id), goal/regular split, out-degree prefix of the regular labels.
+// Finish the pop: exact selection inside the tie bin, goal/regular split,
+// out-degree prefix of the regular labels.
 template <int DM>
 __global__ __launch_bounds__(NT_SLOT) void k_batch_finalize(Slot* slots, GraphDev G) {
   Slot* Sp = &slots[blockIdx.x];
@@ -655,68 +640,27 @@ __global__ __launch_bounds__(NT_SLOT) void k_batch_finalize(Slot* slots, GraphDe
     __syncthreads();
   }
   const uint64_t c1 = wall_clock64();
-  // ---- canonical batch order: ascending label id
-  if (nb > S.batch_cap || nb > BATCH_SORT || keep_n > S.open_cap) {
+  if (nb > S.batch_cap || nb > BATCH_MAX || keep_n > S.open_cap) {
     if (threadIdx.x == 0) {
       Sp->status = S_OVERFLOW;
       Sp->err_line = __LINE__;
     }
     return;
   }
-  // register bitonic sort of the batch (padded with INT32_MAX)
-  int32_t* V = lds;
-  int E = 1;
-  while (E * NT_SLOT < nb) E <<= 1;
-  if (E == 1) sort_batch<1>(S, nb, V);
-  else if (E == 2) sort_batch<2>(S, nb, V);
-  else if (E == 4) sort_batch<4>(S, nb, V);
-  else sort_batch<8>(S, nb, V);
-  const uint64_t c2 = wall_clock64();
-  // ---- split into goal and regular labels (stable), mark them closed:
-  // thread t owns batch positions t*E .. t*E+E-1
-  const int goal = S.goal;
-  int cg = 0, cr = 0, cdeg = 0;
-  int flags[8], degs[8];
-  for (int e = 0; e < E; ++e) {
-    const int i = threadIdx.x * E + e;
-    flags[e] = 0;
-    degs[e] = 0;
-    if (i < nb) {
-      const int lab = V[i];
-      const int v = S.Lnode[lab];
-      if (v == goal) {
-        flags[e] = 1;
-        ++cg;
-      } else {
-        flags[e] = 2;
-        degs[e] = G.row_ptr[v + 1] - G.row_ptr[v];
-        ++cr;
-        cdeg += degs[e];
-      }
-    }
-  }
+  // ---- split into goal and regular labels.  The order of the batch is
+  // immaterial: no decision of the step depends on label ids or positions
+  // (ties between equal candidates go to the smaller arc id, which is unique
+  // among them).
   int goal_total, reg_total, deg_carry;
-  int pg = block_exscan<NT_SLOT>(cg, &goal_total, tmp);
-  int pr = block_exscan<NT_SLOT>(cr, &reg_total, tmp);
-  int pd = block_exscan<NT_SLOT>(cdeg, &deg_carry, tmp);
-  for (int e = 0; e < E; ++e) {
-    const int i = threadIdx.x * E + e;
-    if (flags[e] == 1) {
-      if (pg < S.cand_cap) S.c_rej[pg] = 0;  // goal-step flag of this goal label
-      S.goal_lab[pg++] = V[i];
-    } else if (flags[e] == 2) {
-      S.reg[pr] = V[i];
-      S.reg_off[pr] = pd;
-      S.reg_kill[pr] = 0;
-      ++pr;
-      pd += degs[e];
-    }
-  }
+  if (nb <= NT_SLOT) split_batch<1>(S, G, nb, tmp, &goal_total, &reg_total, &deg_carry);
+  else if (nb <= 2 * NT_SLOT) split_batch<2>(S, G, nb, tmp, &goal_total, &reg_total, &deg_carry);
+  else if (nb <= 4 * NT_SLOT) split_batch<4>(S, G, nb, tmp, &goal_total, &reg_total, &deg_carry);
+  else if (nb <= 8 * NT_SLOT) split_batch<8>(S, G, nb, tmp, &goal_total, &reg_total, &deg_carry);
+  else split_batch<16>(S, G, nb, tmp, &goal_total, &reg_total, &deg_carry);
   if (threadIdx.x == 0) {
     const uint64_t c3 = wall_clock64();
     Sp->st[ST_T0 + 0] += c1 - c0;
-    Sp->st[ST_T0 + 1] += c2 - c1;
-    Sp->st[ST_T0 + 2] += c3 - c2;
+    Sp->st[ST_T0 + 2] += c3 - c1;
     S.reg_off[reg_total] = deg_carry;
     Sp->goal_n = goal_total;
     Sp->reg_n = reg_total;
@@ -913,7 +857,7 @@ __global__ __launch_bounds__(NT_TILE) void k_goal_pairs(Slot* slots) {
 }
 
 // Append the accepted goal labels to P (in batch order) and compact P once
-// half of its entries are tombstones (stable, into the other buffer).
+// a quarter of its entries are tombstones (stable, into the other buffer).
 template <int DM>
 __global__ __launch_bounds__(NT_SLOT) void k_goal_merge(Slot* slots) {
   Slot* Sp = &slots[blockIdx.x];
@@ -946,7 +890,7 @@ __global__ __launch_bounds__(NT_SLOT) void k_goal_merge(Slot* slots) {
   }
   const int n1 = np + na, dead = S.P_dead;
   int live = n1, sel = S.P_sel;
-  if (dead > 0 && 2 * dead >= n1) {
+  if (dead > 0 && 4 * dead >= n1) {
     __syncthreads();  // appended entries visible to the whole workgroup
     int32_t* Qg = pick(S.Pg, S.P_sel ^ 1);
     int32_t* Ql = pick(S.Plab, S.P_sel ^ 1);
@@ -1229,7 +1173,9 @@ __device__ __forceinline__ bool frontier_dest(Slot* Sp, const Slot& S, const Nod
 // One wave per group (all candidates of this step with the same target node v,
 // candidate i held by lane i, k <= 64):
 //  A. candidates against each other: c_i is dropped if some c_j <= c_i in every
-//     objective and (c_j != c_i or j precedes i in flat order);
+//     objective and (c_j != c_i or c_j's arc id is smaller; two distinct
+//     candidates with equal vectors always differ in their arc, because the
+//     labels popped at one node have distinct vectors);
 //  B. survivors against the live frontier of v, U entries per lane per pass
 //     (the next pass is loaded before the current one is compared); each
 //     surviving candidate is broadcast from its lane: it is rejected if an entry
@@ -1275,6 +1221,7 @@ __global__ __launch_bounds__(NT_TILE) void k_group_process(Slot* slots) {
     const int32_t* ord = S.order + S.grp_off[gid];
     const bool have = lane < k;
     const int fi = have ? ord[lane] : 0;
+    const int ai = have ? S.c_arc[fi] : 0;
     int32_t ci[DM];
 #pragma unroll
     for (int kk = 0; kk < DM; ++kk) ci[kk] = (have && kk < d) ? S.c_g[(size_t)kk * cc + fi] : 0;
@@ -1295,8 +1242,8 @@ __global__ __launch_bounds__(NT_TILE) void k_group_process(Slot* slots) {
           le = le & (b <= ci[kk]);
           eq = eq & (b == ci[kk]);
         }
-        const int fj = bcast(fi, jj);
-        rej = rej | (jj != lane && le && (!eq || fj < fi));
+        const int aj = bcast(ai, jj);
+        rej = rej | (jj != lane && le && (!eq || aj < ai));
       }
     }
     const uint64_t surv = ballot(have && !rej);
@@ -1404,7 +1351,7 @@ __global__ __launch_bounds__(NT_TILE) void k_group_process(Slot* slots) {
 // ---------------------------------------------------------------- big groups
 // Pair tiles of the big groups, one wave per tile, both operands in lanes:
 //   A-tiles (candidate tile I x candidate tile J): a candidate of I is rejected
-//     if a candidate of J weakly dominates it (ties: smaller flat index stays);
+//     if a candidate of J weakly dominates it (ties: the smaller arc id stays);
 //   B-tiles (frontier tile T x candidate tile J): a candidate is rejected if an
 //     entry of T weakly dominates it; an entry is pruned if a candidate strictly
 //     dominates it.  Any candidate may prune: the minimal candidates below a
@@ -1441,6 +1388,7 @@ __global__ __launch_bounds__(NT_TILE) void k_group_pairs(Slot* slots) {
     const int j = J * WAVE + lane;
     const bool hj = j < k;
     const int fj = hj ? ord[j] : 0;
+    const int aj = hj ? S.c_arc[fj] : 0;
     int32_t cj[DM];
 #pragma unroll
     for (int kk = 0; kk < DM; ++kk) cj[kk] = (hj && kk < d) ? S.c_g[(size_t)kk * cc + fj] : 0;
@@ -1449,6 +1397,7 @@ __global__ __launch_bounds__(NT_TILE) void k_group_pairs(Slot* slots) {
       const int i = I * WAVE + lane;
       const bool hi = i < k;
       const int fi = hi ? ord[i] : 0;
+      const int ai = hi ? S.c_arc[fi] : 0;
       int32_t ci[DM];
 #pragma unroll
       for (int kk = 0; kk < DM; ++kk) ci[kk] = (hi && kk < d) ? S.c_g[(size_t)kk * cc + fi] : 0;
@@ -1462,7 +1411,8 @@ __global__ __launch_bounds__(NT_TILE) void k_group_pairs(Slot* slots) {
           eq = eq & (b == ci[kk]);
         }
         const int fb = bcast(fj, jj);
-        rej = rej | (fb != fi && le && (!eq || fb < fi));
+        const int ab = bcast(aj, jj);
+        rej = rej | (fb != fi && le && (!eq || ab < ai));
       }
       if (hi && rej) S.c_rej[fi] = 1;
     } else {

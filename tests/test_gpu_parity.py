@@ -104,6 +104,17 @@ def test_ship_grid_front(mos, size):
     check_paths(g, s, t, r.costs, r.paths, 3)
 
 
+@pytest.mark.parametrize("B", [4096, 16384])
+def test_widest_batches(mos, B):
+    """Batches up to the largest width (16 popped labels per thread of the
+    per-query workgroup) on the 32x32 grid and the 96x96 ship grid."""
+    for g, s, t in (gen.config1(0), gen.config2(0, size=96)):
+        r = _front(mos, g, s, t, batch_width=B)
+        ref = oracle.solve(g, s, t, flags=oracle.WEAK_P | oracle.LAZY_PRUNEOPEN)
+        assert np.array_equal(r.costs.astype(np.int64), ref.costs)
+        check_paths(g, s, t, r.costs, r.paths, 3)
+
+
 def test_diamond_chain_large_front(mos):
     g, s, t = gen.diamond_chain(12)
     r = _front(mos, g, s, t, batch_width=256)
