@@ -10,9 +10,16 @@ the device throughout.  The value is dominance pair checks per second: every
 (candidate, stored vector) comparison the method makes against the goal front,
 against same-step candidates of the same node, and against node frontiers.
 
-Prints one JSON line.  Also reports the roofline of the dominant kernel (kernel
-durations from HIP events over the timed steps) and the CPU oracle's check
-rate on a bounded sample of the same query.
+Prints one JSON line.  Also reports the roofline of the dominant kernel (its
+durations from HIP events over the timed steps, its algorithmic bytes from the
+search counters, its measured HBM traffic from the committed PMC summary when
+that summary matches the current kernel sources), the CPU oracle's check rate
+on a bounded sample of the same query, and queries/s of one batched call
+against a loop of single solves on short-range queries of the same grid.
+
+`--workload served` instead runs the request loop on the 1M-node road-like
+graph (saturation and Poisson arrivals, p50/p99 latency) and prints its own
+JSON line.
 """
 from __future__ import annotations
 
@@ -35,8 +42,10 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200, help="timed label steps")
-    ap.add_argument("--warmup", type=int, default=300, help="untimed label steps before timing")
-    ap.add_argument("--batch-width", type=int, default=4096)
+    ap.add_argument("--warmup", type=int, default=2000,
+                    help="untimed label steps before timing (2000 steps of B = 8192 take the "
+                         "search about 16M labels deep)")
+    ap.add_argument("--batch-width", type=int, default=8192)
     ap.add_argument("--profile-steps", type=int, default=50,
                     help="last warm-up steps with every kernel timed (per-kernel table; "
                          "picks the dominant kernel)")
@@ -48,6 +57,14 @@ def parse():
                     help="Manhattan distance range of those queries")
     ap.add_argument("--query-width", type=int, default=256,
                     help="batch width B of every query in that comparison")
+    ap.add_argument("--workload", choices=("steps", "served"), default="steps",
+                    help="steps: label steps of the ship-routing query (the headline line); "
+                         "served: the request loop on the 1M-node road-like graph")
+    ap.add_argument("--served-queries", type=int, default=600,
+                    help="queries per arrival-rate point of the served workload")
+    ap.add_argument("--radius", type=float, default=0.02,
+                    help="served workload: goals within this distance of the start")
+    ap.add_argument("--slots", type=int, default=64, help="served workload: resident queries")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB 4 times (a kernel of known "
                          "HBM traffic, to scale hardware byte counters) and exit")
@@ -96,6 +113,45 @@ def kernel_ops(name, c, d):
     return 0
 
 
+KERNEL_SOURCES = ("paper_2411_16667_amd/csrc/step.hip", "paper_2411_16667_amd/csrc/mos_core.h",
+                  "paper_2411_16667_amd/csrc/kernels.h")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_ship256_steps.md")
+
+
+def kernel_source_digest() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, batch_width):
+    """HBM bytes per launch of `kernel` from the committed PMC summary, or None
+    when there is none for this kernel and batch width or the kernel sources
+    have changed since the counters were taken."""
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    meta = dict(line[2:].split(": ", 1) for line in text.splitlines()
+                if line.startswith("- ") and ": " in line)
+    if meta.get("kernel sources sha256/16") != kernel_source_digest():
+        return None
+    if meta.get("batch width") != str(batch_width):
+        return None
+    for line in text.splitlines():
+        cells = [c.strip() for c in line.strip().strip("|").split("|")]
+        if len(cells) == 4 and cells[0] == kernel:
+            try:
+                return float(cells[3])
+            except ValueError:
+                return None
+    return None
+
+
 def cpu_baseline(g, s, t, seconds):
     import oracle
 
@@ -130,6 +186,110 @@ def batched_vs_plain(mos, gen, G, a):
             "front_sizes": {"min": min(fronts), "median": int(np.median(fronts)), "max": max(fronts)}}
 
 
+def run_stream(srv, S, T, D, arrivals):
+    """Submit query i at time arrivals[i] (seconds from now); a poller thread
+    collects results.  Returns (latencies in s from arrival, wall seconds, results)."""
+    import threading
+
+    n = len(S)
+    tickets = [None] * n
+    done_at = [None] * n
+    res = [None] * n
+    submitted = threading.Event()
+    t0 = time.perf_counter()
+
+    def poller():
+        pending = set()
+        nxt = 0
+        while True:
+            while nxt < n and tickets[nxt] is not None:
+                pending.add(nxt)
+                nxt += 1
+            for i in list(pending):
+                r = srv.poll(tickets[i])
+                if r is not None:
+                    done_at[i] = time.perf_counter()
+                    res[i] = r
+                    pending.discard(i)
+            if submitted.is_set() and nxt == n and not pending:
+                return
+            time.sleep(0.0002)
+
+    th = threading.Thread(target=poller)
+    th.start()
+    for i in range(n):
+        delay = t0 + arrivals[i] - time.perf_counter()
+        if delay > 0:
+            time.sleep(delay)
+        tickets[i] = srv.submit(int(S[i]), int(T[i]), int(D[i]))
+    submitted.set()
+    th.join()
+    wall = max(done_at) - t0
+    lat = [done_at[i] - (t0 + arrivals[i]) for i in range(n)]
+    return lat, wall, res
+
+
+def served_bench(a):
+    """The served workload: 1M-node 8-NN road-like graph, five stored objectives,
+    queries with d ~ U{3,4,5} and goals within a radius of the start; one
+    saturation run (all queries submitted at once), then Poisson arrivals at
+    fractions of the measured saturation rate; plus the plain path (one
+    mos_solve at a time) on the same queries."""
+    import numpy as np
+
+    import gen
+    import paper_2411_16667_amd as mos
+
+    t0 = time.perf_counter()
+    g, rng, comp = gen.config5_graph(0)
+    nq = a.served_queries
+    S, T, D = gen.local_queries(g, comp, 6 * nq, seed=0, radius=a.radius)
+    G = mos.Graph.from_gen(g)
+    print(f"served: graph and {6 * nq} queries ready in {time.perf_counter() - t0:.1f} s",
+          file=sys.stderr, flush=True)
+    # plain: one query at a time through mos_solve
+    npl = min(nq, 200)
+    mos.mos_solve(G, int(S[0]), int(T[0]), n_objectives=int(D[0]))
+    tp = time.perf_counter()
+    plain = [mos.mos_solve(G, int(S[i]), int(T[i]), n_objectives=int(D[i])) for i in range(npl)]
+    plain_qps = npl / (time.perf_counter() - tp)
+    print(f"served: plain {plain_qps:.1f} q/s", file=sys.stderr, flush=True)
+    srv = mos.Server(G, max_slots=a.slots)
+    lat, wall, res = run_stream(srv, S[:nq], T[:nq], D[:nq], np.zeros(nq))
+    sat = nq / wall
+    same = all(r is not None and r[0] == mos.MOS_OK and np.array_equal(r[1].costs, p.costs)
+               for r, p in zip(res[:npl], plain))
+    points = [{"rate_frac": "all at once", "offered_qps": None, "qps": sat,
+               "p50_ms": 1e3 * float(np.percentile(lat, 50)),
+               "p99_ms": 1e3 * float(np.percentile(lat, 99))}]
+    print(f"served: saturation {sat:.1f} q/s", file=sys.stderr, flush=True)
+    for k, frac in enumerate((0.25, 0.5, 0.75, 0.9, 1.1)):
+        rate = frac * sat
+        lo = (k + 1) * nq
+        arr = gen.poisson_arrivals(nq, rate, seed=k)
+        lat, wall, res = run_stream(srv, S[lo:lo + nq], T[lo:lo + nq], D[lo:lo + nq], arr)
+        ok = all(r is not None and r[0] == mos.MOS_OK for r in res)
+        points.append({"rate_frac": frac, "offered_qps": rate, "qps": nq / wall,
+                       "p50_ms": 1e3 * float(np.percentile(lat, 50)),
+                       "p99_ms": 1e3 * float(np.percentile(lat, 99)), "all_ok": ok})
+        print(f"served: {points[-1]}", file=sys.stderr, flush=True)
+    c = srv.counters()
+    srv.close()
+    fronts = [len(p.costs) for p in plain]
+    out = {"metric": "served queries/s with p50/p99 latency (Poisson arrivals), exact Pareto "
+                     "front, 1 GPU",
+           "value": sat, "unit": "queries/s", "n_gpus": 1, "higher_is_better": True,
+           "dtype": "int32", "data": "synthetic",
+           "config": {"workload": f"1M-node 8-NN geometric graph, 5 stored objectives, d~U{{3,4,5}}, "
+                                  f"goals within {a.radius} of the start", "slots": a.slots,
+                      "batch_width": 256, "queries_per_point": nq},
+           "plain_qps": plain_qps, "served_vs_plain": sat / plain_qps,
+           "same_fronts_as_plain": bool(same), "points": points, "server_counters": c,
+           "front_sizes": {"min": min(fronts), "median": int(np.median(fronts)),
+                           "max": max(fronts)}}
+    print(json.dumps(out))
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -141,6 +301,9 @@ def main():
     import gen
     import paper_2411_16667_amd as mos
 
+    if a.workload == "served":
+        served_bench(a)
+        return
     if a.copy_calibration > 0:
         import torch
 
@@ -159,8 +322,12 @@ def main():
     d = 3
     sess = mos.Session(G, s, t, batch_width=a.batch_width, steps_per_poll=16)
     pre = max(1, min(a.profile_steps, a.warmup))
-    if a.warmup > pre:
-        sess.step(a.warmup - pre)
+    left = a.warmup - pre
+    while left > 0:  # in chunks, with a progress line each
+        n = min(left, 500)
+        sess.step(n)
+        left -= n
+        print(f"bench: warm-up, {a.warmup - pre - left} steps", file=sys.stderr, flush=True)
     # per-kernel table from the last warm-up steps (every kernel bracketed by events)
     sess.set_profile(-1)
     p0 = sess.kernel_times()
@@ -199,6 +366,7 @@ def main():
     else:
         roof = {"bound": "hbm", "achieved": bw, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": bw / HBM_PEAK_GBS, "traffic": None}
+    roof["traffic"] = measured_traffic(dom, a.batch_width)
     roof["kernel"] = dom
     roof["avg_launch_us"] = avg_s * 1e6
     roof["launches"] = launches

@@ -304,6 +304,30 @@ def served_queries(g: Graph, comp: np.ndarray, nq: int, seed: int, dmin: int = 3
     return s.astype(np.int32), t.astype(np.int32), dq.astype(np.int32)
 
 
+def local_queries(g: Graph, comp: np.ndarray, nq: int, seed: int, radius: float,
+                  dmin: int = 3, dmax: int = 5):
+    """nq (s, t, d) queries in the giant component with t drawn uniformly among
+    the nodes within Euclidean distance `radius` of s (t != s), d ~ U{dmin..dmax}.
+    The tractable stand-in for random pairs on large geometric graphs."""
+    from scipy.spatial import cKDTree
+
+    rng = np.random.default_rng(seed + 6000)
+    giant = np.bincount(comp).argmax()
+    nodes = np.flatnonzero(comp == giant)
+    tree = cKDTree(g.coords)
+    S, T = np.empty(nq, np.int32), np.empty(nq, np.int32)
+    i = 0
+    while i < nq:
+        s = int(nodes[rng.integers(0, nodes.size)])
+        near = [x for x in tree.query_ball_point(g.coords[s], radius) if x != s and comp[x] == giant]
+        if not near:
+            continue
+        S[i], T[i] = s, int(near[rng.integers(0, len(near))])
+        i += 1
+    dq = rng.integers(dmin, dmax + 1, nq).astype(np.int32)
+    return S, T, dq
+
+
 def poisson_arrivals(nq: int, rate: float, seed: int) -> np.ndarray:
     """Arrival times (seconds) of a Poisson process with the given rate."""
     rng = np.random.default_rng(seed + 7000)

@@ -76,6 +76,11 @@ typedef struct {
   int32_t profile_kernels; /* sessions only: bit i set = time kernel i of every step with
                               HIP events (-1 = every kernel); the kernels are then
                               launched one by one instead of from a captured graph */
+  int32_t heuristic_radius; /* heuristic (Section 4's reverse SSSP per objective): the
+                              reverse search is cut at r * h_k(start) for r > 0, nodes
+                              beyond the cut get the admissible lower bound cut + 1;
+                              0 = default (r = 4); negative = exact on the whole graph.
+                              The front does not depend on it, only the work does. */
 } mos_options;
 
 /* Counters of one query (paper, Section 6: label extractions, candidate

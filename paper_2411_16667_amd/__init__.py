@@ -41,7 +41,8 @@ class mos_options(ctypes.Structure):
                 ("batch_width", ctypes.c_int32), ("max_slots", ctypes.c_int32),
                 ("label_limit", ctypes.c_int64), ("mem_budget", ctypes.c_int64),
                 ("stream", ctypes.c_void_p), ("costs_only", ctypes.c_int32),
-                ("steps_per_poll", ctypes.c_int32), ("profile_kernels", ctypes.c_int32)]
+                ("steps_per_poll", ctypes.c_int32), ("profile_kernels", ctypes.c_int32),
+                ("heuristic_radius", ctypes.c_int32)]
 
 
 class mos_stats(ctypes.Structure):
@@ -217,7 +218,7 @@ def _stream_ptr(stream):
 
 def make_options(n_objectives=0, batch_width=0, max_slots=0, label_limit=0, mem_budget=0,
                  stream=None, costs_only=False, steps_per_poll=0,
-                 profile_kernels=False) -> mos_options:
+                 profile_kernels=False, heuristic_radius=0) -> mos_options:
     o = mos_options()
     o.struct_size = ctypes.sizeof(mos_options)
     o.n_objectives = int(n_objectives)
@@ -230,6 +231,7 @@ def make_options(n_objectives=0, batch_width=0, max_slots=0, label_limit=0, mem_
     o.steps_per_poll = int(steps_per_poll)
     # True = every kernel of the step; an int = bit mask over the step's kernels
     o.profile_kernels = -1 if profile_kernels is True else int(profile_kernels)
+    o.heuristic_radius = int(heuristic_radius)
     return o
 
 

@@ -159,6 +159,7 @@ struct EngineKey {
 struct mos_graph {
   int32_t n = 0, D = 0, maxdeg = 0, device = 0;
   int64_t m = 0;
+  int32_t csum[MAXD] = {};
   DevBuf row_ptr, col, cost, rrow, rsrc, rarc;
   std::mutex pool_mu;
   std::vector<std::pair<EngineKey, Engine*>> pool;  // idle engines, oldest first
@@ -168,6 +169,7 @@ struct mos_graph {
     g.m = (int32_t)m;
     g.D = D;
     g.maxdeg = maxdeg;
+    for (int k = 0; k < MAXD; ++k) g.csum[k] = csum[k];
     g.row_ptr = row_ptr.as<int32_t>();
     g.col = col.as<int32_t>();
     g.cost = cost.as<int32_t>();
@@ -340,9 +342,12 @@ static void carve(Slot& s, char* base, const Layout& L, int64_t n, int d) {
 }
 
 // ------------------------------------------------------------------ engine
+constexpr int kDefaultHeurFactor = 4;  // heuristic radius: 4 x h(start), per objective
+
 struct QueryReq {
   int64_t id = 0;
   int32_t start = 0, goal = 0, d = 0;
+  int32_t heur_factor = kDefaultHeurFactor;  // 0 = exact heuristic on the whole graph
   int64_t reserve = 0;  // bytes of the next admission attempt
   int attempts = 0;
 };
@@ -520,6 +525,7 @@ class Engine {
       s.P_cap = L.P_cap;
       s.fw_cap = L.fw_cap;
       s.query_id = (int32_t)q.id;
+      s.heur_factor = q.heur_factor;
       carve(s, arena_.as<char>() + off * 256, L, g_->n, q.d);
       HIPCHK(hipMemcpyAsync((char*)slots_.p + (size_t)free_slot * sizeof(Slot), &s, sizeof(Slot),
                             hipMemcpyHostToDevice, st_));
@@ -718,6 +724,7 @@ class Engine {
       }
       if (r > 4 * g_->n + 64) throw MosError(MOS_E_DEVICE, "heuristic did not converge");
     }
+    launch_heur_clamp(slots_.as<Slot>(), hjob_.as<int32_t>(), nj, G, st_);
     if (seed)
       for (int s : fresh) launch_slot_init(slots_.as<Slot>(), s, G, st_);
     HIPCHK(hipGetLastError());
@@ -926,6 +933,7 @@ static void release_engine(const mos_graph* gc, const EngineKey& k, Engine* e) {
 // ------------------------------------------------------------ option helpers
 struct Opts {
   int n_objectives = 0, B = 256, max_slots = 0, want_paths = 1, steps = 8;
+  int heur_factor = kDefaultHeurFactor;
   uint32_t profile = 0;
   int64_t label_limit = 0, mem_budget = 0;
   hipStream_t stream = nullptr;
@@ -945,7 +953,10 @@ static mos_status read_opts(const mos_options* o, Opts* out) {
     if (o->struct_size >= offsetof(mos_options, steps_per_poll)) r.want_paths = o->costs_only ? 0 : 1;
     if (o->struct_size >= offsetof(mos_options, profile_kernels) && o->steps_per_poll > 0)
       r.steps = o->steps_per_poll;
-    if (o->struct_size >= sizeof(mos_options)) r.profile = (uint32_t)o->profile_kernels;
+    if (o->struct_size >= offsetof(mos_options, heuristic_radius)) r.profile = (uint32_t)o->profile_kernels;
+    if (o->struct_size >= sizeof(mos_options))
+      r.heur_factor = o->heuristic_radius == 0 ? kDefaultHeurFactor
+                                               : (o->heuristic_radius < 0 ? 0 : o->heuristic_radius);
   }
   if (r.B < 1 || r.B > BATCH_MAX)
     return set_err(MOS_E_INVALID_ARG, "batch_width must lie in [1, 16384]");
@@ -1016,6 +1027,7 @@ mos_status mos_graph_create(int32_t n, int64_t m, int32_t D, const int64_t* row_
   }
   for (int64_t e = 0; e < m; ++e)
     if (col[e] < 0 || col[e] >= n) return set_err(MOS_E_INVALID_ARG, "arc target out of range");
+  int32_t csum[MAXD] = {};
   for (int32_t k = 0; k < D; ++k) {
     int64_t sum = 0, mx = 0;
     for (int64_t e = 0; e < m; ++e) {
@@ -1026,6 +1038,7 @@ mos_status mos_graph_create(int32_t n, int64_t m, int32_t D, const int64_t* row_
     }
     if (2 * sum + mx >= (int64_t)INT32_MAX)
       return set_err(MOS_E_OVERFLOW_RISK, "2*sum+max of an objective reaches INT32_MAX");
+    csum[k] = (int32_t)sum;
   }
   return guarded([&]() -> mos_status {
     const int dev = ensure_device();
@@ -1035,6 +1048,7 @@ mos_status mos_graph_create(int32_t n, int64_t m, int32_t D, const int64_t* row_
     g->D = D;
     g->maxdeg = maxdeg;
     g->device = dev;
+    for (int k = 0; k < MAXD; ++k) g->csum[k] = csum[k];
     std::vector<int32_t> rp(n + 1), planes((size_t)D * std::max<int64_t>(m, 1));
     for (int32_t v = 0; v <= n; ++v) rp[v] = (int32_t)row_ptr[v];
     for (int64_t e = 0; e < m; ++e)
@@ -1100,9 +1114,14 @@ mos_status mos_solve_batch(const mos_graph* g, int32_t nq, const int32_t* starts
   if (nq == 0) return MOS_OK;
   return guarded([&]() -> mos_status {
     HIPCHK(hipSetDevice(g->device));
-    const int S = o.max_slots > 0 ? std::min(o.max_slots, nq) : std::min(nq, 256);
-    const int dmax = *std::max_element(dq.begin(), dq.end());
-    const EngineKey key{S, dm_for(dmax), o.mem_budget, (void*)o.stream, o.B, o.label_limit,
+    // engines are cached per graph: slot counts are rounded up to a power of
+    // two and the kernels are built for the graph's objective count (queries
+    // with fewer objectives run in the same engine), so repeated calls with
+    // varying sizes and objective counts reuse one engine and its arena
+    const int want = o.max_slots > 0 ? std::min(o.max_slots, nq) : std::min(nq, 256);
+    int S = 1;
+    while (S < want) S <<= 1;
+    const EngineKey key{S, dm_for(g->D), o.mem_budget, (void*)o.stream, o.B, o.label_limit,
                         o.want_paths != 0, o.steps};
     Engine* ep = acquire_engine(g, key, default_budget(o.mem_budget), o.stream);
     std::unique_ptr<Engine> guard(ep);
@@ -1114,6 +1133,7 @@ mos_status mos_solve_batch(const mos_graph* g, int32_t nq, const int32_t* starts
       q.start = starts[i];
       q.goal = goals[i];
       q.d = dq[i];
+      q.heur_factor = o.heur_factor;
       q.reserve = eng.default_reserve();
       pending.push_back(q);
       out[i] = nullptr;
@@ -1248,6 +1268,7 @@ mos_status mos_session_create(const mos_graph* g, int32_t start, int32_t goal,
     q.start = start;
     q.goal = goal;
     q.d = d;
+    q.heur_factor = o.heur_factor;
     q.reserve = s->eng->arena_bytes();
     std::string msg;
     mos_status st = s->eng->session_admit(q, &msg);

@@ -32,6 +32,8 @@ void launch_heur_init(Slot* slots, const int32_t* slot_of, int njobs, const Grap
                       int32_t* hs, int32_t* cnt, hipStream_t st);
 void launch_heur_round(Slot* slots, const int32_t* slot_of, int njobs, const GraphDev& G,
                        int32_t* hs, int32_t* cnt, int r, int gx, hipStream_t st);
+void launch_heur_clamp(Slot* slots, const int32_t* slot_of, int njobs, const GraphDev& G,
+                       hipStream_t st);
 void launch_slot_init(Slot* slots, int s, const GraphDev& G, hipStream_t st);
 void launch_path_len(const Slot* slots, int s, const int32_t* labs, int np, int32_t* len,
                      hipStream_t st);

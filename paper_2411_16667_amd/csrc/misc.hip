@@ -55,6 +55,11 @@ __global__ void k_heur_round(Slot* slots, const int32_t* slot_of, GraphDev G, in
   int32_t* ncnt = &c[(r + 1) % 3];
   if (blockIdx.x == 0 && threadIdx.x == 0) c[(r + 2) % 3] = 0;
   const int32_t* cost = G.cost + (size_t)k * G.m;
+  // radius: only nodes within heur_factor * h(start) are propagated further
+  // (h(start) only decreases, so the cut never grows)
+  const int h0 = h[S->start];
+  const int64_t cut = (S->heur_factor > 0 && h0 != UNREACH) ? (int64_t)S->heur_factor * h0
+                                                            : INT64_MAX;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < ncur; i += gridDim.x * blockDim.x) {
     const int v = cur[i];
     const int dv = h[v];
@@ -63,13 +68,36 @@ __global__ void k_heur_round(Slot* slots, const int32_t* slot_of, GraphDev G, in
       const int nd = dv + cost[G.rarc[p]];
       if (nd < h[u]) {
         const int old = atomicMin(&h[u], nd);
-        if (nd < old && atomicMax(&stamp[u], r + 1) < r + 1) {
+        if (nd < old && nd <= cut && atomicMax(&stamp[u], r + 1) < r + 1) {
           const int pos = atomicAdd(ncnt, 1);
           nxt[pos] = u;
         }
       }
     }
   }
+}
+
+// After the reverse search: with a radius cut R = heur_factor * h(start) below
+// the largest possible distance (the objective's total over all arcs), every
+// node with distance <= R holds its exact distance (its whole shortest path
+// lies within R and was propagated) and every other node has distance > R,
+// so it gets R + 1: an admissible lower bound.  Inside the cut the heuristic
+// stays consistent; across it, F may decrease along an arc, which the search
+// tolerates (its result does not depend on the pop order).
+__global__ void k_heur_clamp(Slot* slots, const int32_t* slot_of, GraphDev G) {
+  const int j = blockIdx.z, k = blockIdx.y;
+  Slot* S = &slots[slot_of[j]];
+  if (k >= S->d) return;
+  const int n = G.n;
+  int32_t* h = S->h + (size_t)k * n;
+  const int hs = h[S->start];
+  if (S->heur_factor <= 0 || hs == UNREACH) return;
+  const int64_t cut = (int64_t)S->heur_factor * hs;
+  if (cut >= G.csum[k]) return;  // no reachable distance exceeds the cut: exact
+  const int lb = (int)cut + 1;
+  if (blockIdx.x == 0 && threadIdx.x == 0) S->heur_bounded = 1;
+  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
+    if (h[v] > cut) h[v] = lb;
 }
 
 // Reset the per-node structures of a slot and seed the start label
@@ -167,6 +195,12 @@ void launch_heur_round(Slot* slots, const int32_t* slot_of, int njobs, const Gra
                        int32_t* hs, int32_t* cnt, int r, int gx, hipStream_t st) {
   hipLaunchKernelGGL(k_heur_round, dim3(gx, MAXD, njobs), dim3(NT_H), 0, st, slots, slot_of, G,
                      hs, cnt, r);
+}
+
+void launch_heur_clamp(Slot* slots, const int32_t* slot_of, int njobs, const GraphDev& G,
+                       hipStream_t st) {
+  const int gx = std::min(1024, (G.n + NT_H - 1) / NT_H);
+  hipLaunchKernelGGL(k_heur_clamp, dim3(gx, MAXD, njobs), dim3(NT_H), 0, st, slots, slot_of, G);
 }
 
 void launch_slot_init(Slot* slots, int s, const GraphDev& G, hipStream_t st) {

@@ -72,6 +72,7 @@ struct NodeRec {
 
 struct GraphDev {
   int32_t n, m, D, maxdeg;
+  int32_t csum[MAXD];      // sum of each objective over all arcs (bounds every simple path)
   const int32_t* row_ptr;  // n+1
   const int32_t* col;      // m
   const int32_t* cost;     // D planes of m: cost[k*m + e]
@@ -86,6 +87,8 @@ struct Slot {
   int32_t start, goal, d;
   int32_t B, batch_cap, cand_cap, tie_cap;
   int32_t pool_cap, open_cap, P_cap, query_id;
+  int32_t heur_factor;  // heuristic radius as a multiple of h(start); 0 = exact everywhere
+  int32_t heur_bounded; // set when the radius cut the reverse search (h is then a lower bound outside it)
   int64_t fw_cap;  // words of the frontier region
 
   int32_t* h;          // d planes of n: heuristic

@@ -50,3 +50,16 @@ def test_config4_queries():
 def test_diamond_chain_structure():
     g, s, t = gen.diamond_chain(4)
     assert (s, t) == (0, 8) and g.n == 13 and g.n_arcs == 16
+
+
+def test_local_queries_stay_within_radius():
+    g, rng, comp = gen.geometric_graph(5000, 8, 5, 1)
+    S, T, D = gen.local_queries(g, comp, 200, seed=3, radius=0.05)
+    giant = np.bincount(comp).argmax()
+    assert np.all(S != T)
+    assert np.all(comp[S] == giant) and np.all(comp[T] == giant)
+    dist = np.linalg.norm(g.coords[S] - g.coords[T], axis=1)
+    assert np.all(dist <= 0.05 + 1e-12)
+    assert set(np.unique(D)) <= {3, 4, 5}
+    S2, T2, D2 = gen.local_queries(g, comp, 200, seed=3, radius=0.05)
+    assert np.array_equal(S, S2) and np.array_equal(T, T2) and np.array_equal(D, D2)

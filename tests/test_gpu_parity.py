@@ -80,7 +80,7 @@ def test_batch_of_one_pops_like_the_oracle(mos, seed):
     label, so the GPU processes exactly the labels sequential NAMOA* processes
     (weak goal-front tests, PruneOPEN applied when a label is popped)."""
     g = gen.grid_uniform(10, 10, 3, 1, 10, seed=seed)
-    r = _front(mos, g, 0, g.n - 1, batch_width=1)
+    r = _front(mos, g, 0, g.n - 1, batch_width=1, heuristic_radius=-1)
     ref = oracle.solve(g, 0, g.n - 1, flags=oracle.WEAK_P | oracle.LAZY_PRUNEOPEN)
     assert np.array_equal(r.costs.astype(np.int64), ref.costs)
     assert r.stats["pops"] == ref.stats["pops"]
@@ -110,6 +110,22 @@ def test_widest_batches(mos, B):
     per-query workgroup) on the 32x32 grid and the 96x96 ship grid."""
     for g, s, t in (gen.config1(0), gen.config2(0, size=96)):
         r = _front(mos, g, s, t, batch_width=B)
+        ref = oracle.solve(g, s, t, flags=oracle.WEAK_P | oracle.LAZY_PRUNEOPEN)
+        assert np.array_equal(r.costs.astype(np.int64), ref.costs)
+        check_paths(g, s, t, r.costs, r.paths, 3)
+
+
+@pytest.mark.parametrize("radius", [-1, 1, 2])
+def test_front_does_not_depend_on_heuristic_radius(mos, radius):
+    """Exact heuristic (-1) or a reverse search cut at radius x h(start) with the
+    lower bound beyond it: same front, only the work differs."""
+    g64, _, _ = gen.config2(0, size=64)
+    g1, s1, t1 = gen.config1(3)
+    # interior queries: with radius 1 most of the grid lies beyond the cut
+    cases = ((g1, s1, t1), (g64, 0, 64 * 64 - 1), (g1, 10 * 32 + 10, 16 * 32 + 16),
+             (g1, 12 * 32 + 8, 18 * 32 + 20))
+    for g, s, t in cases:
+        r = _front(mos, g, s, t, batch_width=512, heuristic_radius=radius)
         ref = oracle.solve(g, s, t, flags=oracle.WEAK_P | oracle.LAZY_PRUNEOPEN)
         assert np.array_equal(r.costs.astype(np.int64), ref.costs)
         check_paths(g, s, t, r.costs, r.paths, 3)
