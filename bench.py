@@ -89,7 +89,7 @@ def kernel_bytes(name, c, d, steps):
         "k_goal_merge": (8 + 8 * d) * c["goal_pops"],
         "k_popcheck": (8 + 8 * d) * pops,
         "k_expand": (16 + 12 * d) * cands,
-        "k_pfilter": (4 + 8 * d) * cands,
+        "k_pfilter": (4 + 8 * d) * acc,                     # labels inserted this step
         "k_group_count": 8 * cands,
         "k_group_offsets": 12 * cands,
         "k_group_scatter": 12 * cands,

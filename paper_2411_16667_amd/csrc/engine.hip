@@ -264,8 +264,10 @@ static bool plan_layout(const mos_graph* g, int d, int B, int64_t budget, int64_
   const int64_t fixed = fixed_bytes(g->n, d, L->batch_cap, L->cand_cap, 0);
   if (budget <= fixed) return false;
   // bytes per pooled label: pool (node, parent, arc, g, state) + OPEN 2x(F1,
-  // lab) + tie set (F1, lab, state) + frontier 3*(d+1) words + goal front share
-  const double per = (12.0 + 4.0 * d + 1.0) + 32.0 + 12.0 + 12.0 * (d + 1) + (8.0 * (d + 1) + 8.0) / 8.0;
+  // lab) + tie set (F1, lab, state, d key words) + frontier 3*(d+1) words + goal
+  // front share
+  const double per = (12.0 + 4.0 * d + 1.0) + 32.0 + 12.0 + 4.0 * d + 12.0 * (d + 1) +
+                     (8.0 * (d + 1) + 8.0) / 8.0;
   int64_t pool = (int64_t)((double)(budget - fixed - 32 * 256) / per);
   pool = std::min<int64_t>(pool, (int64_t)1 << 30);
   if (label_limit > 0) pool = std::min<int64_t>(pool, label_limit);
@@ -278,7 +280,7 @@ static bool plan_layout(const mos_graph* g, int d, int B, int64_t budget, int64_
   int64_t b = fixed;
   b += 3 * al(4 * pool) + al(4 * (int64_t)d * pool) + al(pool);  // pool
   b += 8 * al(4 * pool);                                          // OPEN near + far tiers
-  b += 3 * al(4 * pool);                                          // tie set
+  b += 3 * al(4 * pool) + al(4 * (int64_t)d * pool);             // tie set and its keys
   b += 2 * (al(4 * (int64_t)d * L->P_cap) + al(4 * (int64_t)L->P_cap));
   b += al(4 * L->fw_cap);
   L->bytes = al(b);
@@ -333,6 +335,7 @@ static void carve(Slot& s, char* base, const Layout& L, int64_t n, int d) {
   s.tie_f1 = (int32_t*)take(4 * (int64_t)L.tie_cap);
   s.tie_lab = (int32_t*)take(4 * (int64_t)L.tie_cap);
   s.tie_st = (int32_t*)take(4 * (int64_t)L.tie_cap);
+  s.tie_key = (int32_t*)take(4 * (int64_t)d * L.tie_cap);
   for (int b = 0; b < 2; ++b) {
     s.Pg[b] = (int32_t*)take(4 * (int64_t)d * L.P_cap);
     s.Plab[b] = (int32_t*)take(4 * (int64_t)L.P_cap);
@@ -526,6 +529,7 @@ class Engine {
       s.fw_cap = L.fw_cap;
       s.query_id = (int32_t)q.id;
       s.heur_factor = q.heur_factor;
+      s.hn = g_->n;
       carve(s, arena_.as<char>() + off * 256, L, g_->n, q.d);
       HIPCHK(hipMemcpyAsync((char*)slots_.p + (size_t)free_slot * sizeof(Slot), &s, sizeof(Slot),
                             hipMemcpyHostToDevice, st_));

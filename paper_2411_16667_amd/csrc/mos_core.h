@@ -26,6 +26,10 @@ constexpr int32_t UNREACH = INT32_MAX;  // heuristic of a node that cannot reach
 constexpr int WAVE = 64;
 constexpr int64_t BIG_WORK = 4096;  // pair checks above which a group is split across waves
 constexpr int32_t PRUNED_BIT = (int32_t)0x80000000;  // marks a pruned entry in a label-id slot
+// label-id slot of a frontier entry whose label the goal front dominated after
+// it was inserted: the entry takes part in no test and goes at the next
+// compaction of its block (PRUNED_BIT | label cannot produce this value)
+constexpr int32_t FW_REMOVED = -2;
 
 enum SlotStatus : int32_t {
   S_IDLE = 0,
@@ -90,6 +94,7 @@ struct Slot {
   int32_t heur_factor;  // heuristic radius as a multiple of h(start); 0 = exact everywhere
   int32_t heur_bounded; // set when the radius cut the reverse search (h is then a lower bound outside it)
   int64_t fw_cap;  // words of the frontier region
+  int32_t hn, pad3;  // nodes of the graph (stride of the heuristic planes)
 
   int32_t* h;          // d planes of n: heuristic
   NodeRec* node;       // n
@@ -115,6 +120,7 @@ struct Slot {
   int32_t* tie_f1;     // tie_cap (= open_cap): entries of the threshold F1 bin
   int32_t* tie_lab;    // tie_cap
   int32_t* tie_st;     // tie_cap: refinement state of each tie entry
+  int32_t* tie_key;    // d planes of tie_cap: F_2..F_d and the node of each tie entry
   int32_t* c_node;     // cand_cap: candidate target node
   int32_t* c_par;      //   parent label
   int32_t* c_arc;      //   arc

@@ -9,7 +9,6 @@
 //            P <- minimal(P + goal labels)
 //   prune    k_popcheck: PruneOPEN applied to the popped labels
 //   expand   k_expand: g' = g + c, F' = g' + h over the out-arcs
-//   filter   k_pfilter: NotDominated(F', P), drop F' that the goal front dominates
 //   group    k_group_count, k_group_offsets, k_group_scatter: candidates by node
 //   check    k_group_process (one wave per group, one streamed pass over the
 //            node's frontier) or k_group_pairs + k_group_finish (large groups
@@ -17,6 +16,7 @@
 //            the node's labels (G_OP and G_CL together) plus dominance among the
 //            candidates of the same step
 //   insert   k_accept_scan, k_insert, k_step_end: new labels into OPEN and G_OP
+//   filter   k_pfilter: NotDominated(F', P) for the labels inserted this step
 //
 // All arithmetic is exact int32.  Tiled kernels run on a (gx, slots) grid and
 // grid-stride over the slot's items; per-slot kernels run one 1024-thread
@@ -31,6 +31,8 @@ constexpr int NT_SLOT = 1024;  // threads of the one-workgroup-per-slot kernels
 constexpr int NT_TILE = 256;   // threads of the tiled kernels
 constexpr int GP_WAVES = NT_TILE / WAVE;
 constexpr int PCH = 256;       // goal-front entries per LDS chunk (one per tiled thread)
+constexpr int BT_U = 4;        // frontier entries per lane in a pair tile of a large group
+constexpr int BT_ENTRIES = BT_U * WAVE;
 static_assert(PCH == NT_TILE, "goal tiles map one label to one thread");
 
 #define FOR_K(k) _Pragma("unroll") for (int k = 0; k < DM; ++k) if (k < d)
@@ -381,6 +383,11 @@ __global__ __launch_bounds__(NT_TILE) void k_open_scatter(Slot* slots) {
     if (to_tie && p < S.tie_cap) {
       S.tie_f1[p] = f;
       S.tie_lab[p] = lab;
+      const int v = S.Lnode[lab];
+      for (int k = 1; k < S.d; ++k)
+        S.tie_key[(size_t)(k - 1) * S.tie_cap + p] = S.Lg[(size_t)k * S.pool_cap + lab] +
+                                                     S.h[(size_t)k * S.hn + v];
+      S.tie_key[(size_t)(S.d - 1) * S.tie_cap + p] = v;
     }
     p = pos[2];
     if (to_near && p < S.open_cap) {
@@ -398,11 +405,10 @@ __global__ __launch_bounds__(NT_TILE) void k_open_scatter(Slot* slots) {
   if (lane_id() == 0 && kmin != INT32_MAX) atomicMin(&Sp->lo_next, kmin);
 }
 
-// Word w of the lexicographic key of a label: F_{w+1} for w < d, the node for w = d.
-__device__ __forceinline__ int key_word(const Slot& S, const GraphDev& G, int lab, int w) {
-  const int v = S.Lnode[lab];
-  if (w >= S.d) return v;
-  return S.Lg[(size_t)w * S.pool_cap + lab] + S.h[(size_t)w * G.n + v];
+// Word w of the full key of tie entry i: F_{w+1} for w < d, the node for w = d
+// (words 1..d were gathered into tie_key when the entry joined the tie set).
+__device__ __forceinline__ int key_word(const Slot& S, int i, int w) {
+  return w == 0 ? S.tie_f1[i] : S.tie_key[(size_t)(w - 1) * S.tie_cap + i];
 }
 
 // Goal/regular split of the nb popped labels (thread t owns batch positions
@@ -490,7 +496,7 @@ __global__ __launch_bounds__(NT_SLOT) void k_batch_finalize(Slot* slots, GraphDe
       int mn = INT32_MAX;
       for (int i = threadIdx.x; i < n; i += NT_SLOT)
         if (TS[i] == 0) {
-          const int x = key_word(S, G, S.tie_lab[i], word);
+          const int x = key_word(S, i, word);
           if (cache) kc[i] = x;
           mn = min(mn, x);
         }
@@ -501,7 +507,7 @@ __global__ __launch_bounds__(NT_SLOT) void k_batch_finalize(Slot* slots, GraphDe
       const int m = sh_a;
       for (int i = threadIdx.x; i < n; i += NT_SLOT)
         if (TS[i] == 0) {
-          const int64_t b = (int64_t)(cache ? kc[i] : key_word(S, G, S.tie_lab[i], word)) - m;
+          const int64_t b = (int64_t)(cache ? kc[i] : key_word(S, i, word)) - m;
           atomicAdd(&hist[b < NB - 1 ? (int)b : NB - 1], 1);
         }
       __syncthreads();
@@ -534,7 +540,7 @@ __global__ __launch_bounds__(NT_SLOT) void k_batch_finalize(Slot* slots, GraphDe
       const int inb = hist[bstar] - below;
       for (int i = threadIdx.x; i < n; i += NT_SLOT)
         if (TS[i] == 0) {
-          const int64_t b64 = (int64_t)(cache ? kc[i] : key_word(S, G, S.tie_lab[i], word)) - m;
+          const int64_t b64 = (int64_t)(cache ? kc[i] : key_word(S, i, word)) - m;
           const int b = b64 < NB - 1 ? (int)b64 : NB - 1;
           if (b < bstar) TS[i] = 1;
           else if (b > bstar) TS[i] = 2;
@@ -572,13 +578,9 @@ __global__ __launch_bounds__(NT_SLOT) void k_batch_finalize(Slot* slots, GraphDe
       __syncthreads();
       if (threadIdx.x < cnt) {
         const int i = threadIdx.x;
-        const int lab = S.tie_lab[idx[i]];
-        const int v = S.Lnode[lab];
         int32_t key[KW * 4];
 #pragma unroll
-        for (int k = 0; k < KW * 4; ++k)
-          key[k] = k < d ? S.Lg[(size_t)k * S.pool_cap + lab] + S.h[(size_t)k * G.n + v]
-                         : (k == d ? v : 0);
+        for (int k = 0; k < KW * 4; ++k) key[k] = k <= d ? key_word(S, idx[i], k) : 0;
 #pragma unroll
         for (int w = 0; w < KW; ++w)
           K4[i * KW + w] = make_int4(key[4 * w], key[4 * w + 1], key[4 * w + 2], key[4 * w + 3]);
@@ -982,8 +984,7 @@ __global__ __launch_bounds__(NT_TILE) void k_expand(Slot* slots, GraphDev G) {
   const int M = S.cand_n;
   const int d = S.d, pc = S.pool_cap, cc = S.cand_cap, n = G.n;
   const int reg_n = S.reg_n;
-  const int np = S.P_n - S.P_dead;  // live goal-front entries
-  int64_t ncand = 0, npairs = 0;
+  int64_t ncand = 0;
   for (int f = blockIdx.x * NT_TILE + threadIdx.x; f < M; f += gridDim.x * NT_TILE) {
     int lo_i = 0, hi_i = reg_n - 1;  // regular label owning flat index f
     while (lo_i < hi_i) {
@@ -1010,51 +1011,61 @@ __global__ __launch_bounds__(NT_TILE) void k_expand(Slot* slots, GraphDev G) {
     S.c_arc[f] = e;
     S.c_keep[f] = alive ? 1 : 0;
     ncand++;
-    if (alive) npairs += np;
   }
   ncand = wave_sum64(ncand);
-  npairs = wave_sum64(npairs);
-  if (lane_id() == 0) {
-    if (ncand) atomicAdd((unsigned long long*)&Sp->st[ST_CANDS], (unsigned long long)ncand);
-    if (npairs) atomicAdd((unsigned long long*)&Sp->st[ST_PPAIRS], (unsigned long long)npairs);
-  }
+  if (lane_id() == 0 && ncand)
+    atomicAdd((unsigned long long*)&Sp->st[ST_CANDS], (unsigned long long)ncand);
 }
 
 // ---------------------------------------------------------------- goal-front filter
-// Drop a candidate whose F' is weakly dominated by a goal-front entry
-// (NotDominated(F', P) of Algorithm 1; weak dominance: a completion of F' = p
-// cannot improve on p).  Work items are (candidate tile, front chunk) pairs so
-// that a large front spreads over the whole chip; every writer stores 0.
+// NotDominated(F', P) of Algorithm 1 for the labels inserted this step (pool
+// ids n_labels .. n_labels + accept_n - 1): a label whose F is weakly
+// dominated by a goal-front entry is marked dead, so OPEN drops it at its
+// next scan and it is never expanded, and its frontier entry is marked
+// removed.  The test runs after the frontier test instead of before it: it
+// then covers only the candidates that survived (a small fraction), and what
+// such a candidate did in this step's frontier test is harmless: every label
+// it rejected or pruned has a g no better than its own, so the goal front
+// dominates that label's F as well.  Weak dominance: a completion of F = p
+// cannot improve on p.  Work items are (label tile, front chunk) pairs so that
+// a large front spreads over the whole chip.
 template <int DM>
 __global__ __launch_bounds__(NT_TILE) void k_pfilter(Slot* slots, GraphDev G) {
-  const Slot S = slots[blockIdx.y];
+  Slot* Sp = &slots[blockIdx.y];
+  const Slot S = *Sp;
   if (S.status != S_RUN) return;
-  const int M = S.cand_n, np = S.P_n;
-  if (M == 0 || np == 0) return;
-  const int nct = (M + NT_TILE - 1) / NT_TILE, npc = (np + PCH - 1) / PCH;
-  const int ntiles = nct * npc;
+  const int R = S.accept_n, np = S.P_n, base = S.n_labels;
+  if (R == 0 || np == 0) return;
+  if (blockIdx.x == 0 && threadIdx.x == 0)
+    atomicAdd((unsigned long long*)&Sp->st[ST_PPAIRS], (unsigned long long)((int64_t)R * (np - S.P_dead)));
+  const int nlt = (R + NT_TILE - 1) / NT_TILE, npc = (np + PCH - 1) / PCH;
+  const int ntiles = nlt * npc;
   if ((int)blockIdx.x >= ntiles) return;
   constexpr int NW = FrontChunk<DM>::NW;
   __shared__ FrontChunk<DM> ch;
-  const int d = S.d, cc = S.cand_cap, Pc = S.P_cap, n = G.n;
+  const int d = S.d, pc = S.pool_cap, Pc = S.P_cap, n = G.n;
   const int32_t* Pg = pick(S.Pg, S.P_sel);
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    const int ct = t / npc, pcn = t - ct * npc;
+    const int lt = t / npc, pcn = t - lt * npc;
     const int p0 = pcn * PCH, npt = min(PCH, np - p0);
     __syncthreads();
     stage_chunk<DM>(ch, Pg, Pc, p0, npt, d);
     __syncthreads();
-    const int f = ct * NT_TILE + threadIdx.x;
-    if (f < M && S.c_keep[f]) {
-      const int v = S.c_node[f];
+    const int i = lt * NT_TILE + threadIdx.x;
+    if (i < R) {
+      const int id = base + i;
+      const int v = S.Lnode[id];
       int32_t x[NW * 4];
 #pragma unroll
       for (int k = 0; k < NW * 4; ++k)
-        x[k] = k < d ? S.c_g[(size_t)k * cc + f] + S.h[(size_t)k * n + v] : 0;
+        x[k] = k < d ? S.Lg[(size_t)k * pc + id] + S.h[(size_t)k * n + v] : 0;
       int4 F[NW];
 #pragma unroll
       for (int w = 0; w < NW; ++w) F[w] = make_int4(x[4 * w], x[4 * w + 1], x[4 * w + 2], x[4 * w + 3]);
-      if (chunk_dominates<DM>(ch, F)) S.c_keep[f] = 0;
+      if (chunk_dominates<DM>(ch, F)) {
+        S.Lstate[id] = L_DEAD;
+        S.fw[S.c_fslot[S.order[i]]] = FW_REMOVED;  // leaves its node's frontier
+      }
     }
   }
 }
@@ -1098,7 +1109,7 @@ __global__ __launch_bounds__(NT_SLOT) void k_group_offsets(Slot* slots) {
     }
     const bool big = i < ng && (sz > WAVE || (int64_t)sz * (cnt + sz) > S.big_work);
     const bool small = i < ng && !big;
-    const int nct = (sz + WAVE - 1) / WAVE, nft = (cnt + WAVE - 1) / WAVE;
+    const int nct = (sz + WAVE - 1) / WAVE, nft = (cnt + BT_ENTRIES - 1) / BT_ENTRIES;
     const int tiles = big ? nct * nct + nft * nct : 0;
     int tot, ts, tb, tt;
     const int ex = block_exscan<NT_SLOT>(sz, &tot, tmp);
@@ -1253,10 +1264,8 @@ __global__ __launch_bounds__(NT_TILE) void k_group_process(Slot* slots) {
     int dcap;
     if (!frontier_dest(Sp, S, nr, cnt + ks, d, &doff, &dcap)) break;
     const bool moved = doff != nr.off;
-    fpairs += (int64_t)ks * cnt;
-    fbytes += (int64_t)cnt * 4 * d;
     uint64_t rejm = 0;  // surviving candidates rejected by the frontier
-    int cursor = 0;
+    int cursor = 0, nlive = 0;
     for (int t = 0; t < cnt; t += U * WAVE) {
       int32_t cv[U][DM], clab[U];
 #pragma unroll
@@ -1284,7 +1293,7 @@ __global__ __launch_bounds__(NT_TILE) void k_group_process(Slot* slots) {
             ge = ge & (c[kk] <= cv[u][kk]);
             lt = lt | (c[kk] < cv[u][kk]);
           }
-          const bool has = t + u * WAVE + lane < cnt;
+          const bool has = t + u * WAVE + lane < cnt && clab[u] != FW_REMOVED;
           anyle = anyle | (has & le);
           prune[u] = prune[u] | (has & ge & lt);
         }
@@ -1297,10 +1306,11 @@ __global__ __launch_bounds__(NT_TILE) void k_group_process(Slot* slots) {
         const bool has = tb + lane < cnt;
         if (prune[u]) S.Lstate[clab[u]] = L_DEAD;
         const uint64_t hm = ballot(has);
-        const uint64_t am = ballot(has && !prune[u]);
-        pruned += __popcll(hm & ~am);
+        const uint64_t am = ballot(has && clab[u] != FW_REMOVED && !prune[u]);
+        pruned += __popcll(ballot(prune[u]));
+        nlive += __popcll(ballot(has && clab[u] != FW_REMOVED));
         if (moved || cursor != tb || am != hm) {
-          if (has && !prune[u]) {
+          if (has && clab[u] != FW_REMOVED && !prune[u]) {
             const int64_t w = doff + cursor + rank_below(am);
 #pragma unroll
             for (int kk = 0; kk < DM; ++kk)
@@ -1311,6 +1321,8 @@ __global__ __launch_bounds__(NT_TILE) void k_group_process(Slot* slots) {
         cursor += __popcll(am);
       }
     }
+    fpairs += (int64_t)ks * nlive;
+    fbytes += (int64_t)nlive * 4 * d;
     // ---- C. append the accepted candidates
     const uint64_t accm = surv & ~rejm;
     const bool acc = (accm >> lane) & 1ull;
@@ -1350,13 +1362,15 @@ __global__ __launch_bounds__(NT_TILE) void k_group_process(Slot* slots) {
 
 // ---------------------------------------------------------------- big groups
 // Pair tiles of the big groups, one wave per tile, both operands in lanes:
-//   A-tiles (candidate tile I x candidate tile J): a candidate of I is rejected
-//     if a candidate of J weakly dominates it (ties: the smaller arc id stays);
-//   B-tiles (frontier tile T x candidate tile J): a candidate is rejected if an
-//     entry of T weakly dominates it; an entry is pruned if a candidate strictly
-//     dominates it.  Any candidate may prune: the minimal candidates below a
-//     pruning one are accepted (the live frontier is an antichain), so the
-//     outcome equals pruning by accepted candidates only.
+//   A-tiles (candidate tile I x candidate tile J, 64 x 64): a candidate of I is
+//     rejected if a candidate of J weakly dominates it (ties: the smaller arc
+//     id stays);
+//   B-tiles (frontier tile T of 256 entries, 4 per lane, x candidate tile J
+//     of 64): a candidate is rejected if an entry of T weakly dominates it; an
+//     entry is pruned if a candidate strictly dominates it.  Any candidate may
+//     prune: the minimal candidates below a pruning one are accepted (the live
+//     frontier is an antichain), so the outcome equals pruning by accepted
+//     candidates only.
 // Rejections are idempotent stores; a prune sets PRUNED_BIT in the entry's
 // label-id slot with an atomic OR, and the first setter marks the label dead.
 template <int DM>
@@ -1416,32 +1430,49 @@ __global__ __launch_bounds__(NT_TILE) void k_group_pairs(Slot* slots) {
       }
       if (hi && rej) S.c_rej[fi] = 1;
     } else {
+      // frontier tile I: BT_U entries per lane
       const NodeRec nr = S.node[v];
-      const int e = I * WAVE + lane;
-      const bool has = e < nr.count;
-      int32_t sv[DM];
+      int32_t sv[BT_U][DM];
+      bool has[BT_U], prune[BT_U];
 #pragma unroll
-      for (int kk = 0; kk < DM; ++kk) sv[kk] = (has && kk < d) ? fw[nr.off + (int64_t)kk * nr.cap + e] : 0;
-      bool prune = false;
+      for (int u = 0; u < BT_U; ++u) {
+        const int e = I * BT_ENTRIES + u * WAVE + lane;
+        has[u] = e < nr.count && fw[nr.off + (int64_t)d * nr.cap + e] != FW_REMOVED;
+#pragma unroll
+        for (int kk = 0; kk < DM; ++kk)
+          sv[u][kk] = (has[u] && kk < d) ? fw[nr.off + (int64_t)kk * nr.cap + e] : 0;
+        prune[u] = false;
+      }
       uint64_t rejm = 0;
       for (int jj = 0; jj < nj; ++jj) {
-        bool le = has, ge = has, lt = false;
+        int32_t c[DM];
 #pragma unroll
-        for (int kk = 0; kk < DM; ++kk) {
-          const int c = bcast(cj[kk], jj);
-          le = le & (sv[kk] <= c);
-          ge = ge & (c <= sv[kk]);
-          lt = lt | (c < sv[kk]);
+        for (int kk = 0; kk < DM; ++kk) c[kk] = bcast(cj[kk], jj);
+        bool anyle = false;
+#pragma unroll
+        for (int u = 0; u < BT_U; ++u) {
+          bool le = has[u], ge = has[u], lt = false;
+#pragma unroll
+          for (int kk = 0; kk < DM; ++kk) {
+            le = le & (sv[u][kk] <= c[kk]);
+            ge = ge & (c[kk] <= sv[u][kk]);
+            lt = lt | (c[kk] < sv[u][kk]);
+          }
+          anyle = anyle | le;
+          prune[u] = prune[u] | (ge & lt);
         }
-        if (ballot(le)) rejm |= 1ull << jj;
-        prune = prune | (ge & lt);
+        if (ballot(anyle)) rejm |= 1ull << jj;
       }
       if ((rejm >> lane) & 1ull) S.c_rej[fj] = 1;
-      if (prune) {
-        const int old = atomicOr(&fw[nr.off + (int64_t)d * nr.cap + e], PRUNED_BIT);
-        if (old >= 0) {
-          S.Lstate[old] = L_DEAD;
-          pruned++;
+#pragma unroll
+      for (int u = 0; u < BT_U; ++u) {
+        if (prune[u]) {
+          const int e = I * BT_ENTRIES + u * WAVE + lane;
+          const int old = atomicOr(&fw[nr.off + (int64_t)d * nr.cap + e], PRUNED_BIT);
+          if (old >= 0) {
+            S.Lstate[old] = L_DEAD;
+            pruned++;
+          }
         }
       }
     }
@@ -1471,30 +1502,43 @@ __global__ __launch_bounds__(NT_TILE) void k_group_finish(Slot* slots) {
     const NodeRec nr = S.node[v];
     const int cnt = nr.count;
     gpairs += (int64_t)k * (k - 1);
-    fpairs += (int64_t)k * cnt;
-    fbytes += (int64_t)cnt * 4 * d;
     int64_t doff;
     int dcap;
     if (!frontier_dest(Sp, S, nr, cnt + k, d, &doff, &dcap)) break;
     const bool moved = doff != nr.off;
-    int cursor = 0;
-    for (int t = 0; t < cnt; t += WAVE) {
-      const int e = t + lane;
-      const bool has = e < cnt;
-      const int slab = has ? fw[nr.off + (int64_t)d * nr.cap + e] : 0;
-      const bool keep = has && slab >= 0;
-      int32_t sv[DM];
-      FOR_K(kk) sv[kk] = keep ? fw[nr.off + (int64_t)kk * nr.cap + e] : 0;
-      const uint64_t hm = ballot(has), am = ballot(keep);
-      if (moved || cursor != t || am != hm) {
-        if (keep) {
-          const int64_t w = doff + cursor + rank_below(am);
-          FOR_K(kk) fw[w + (int64_t)kk * dcap] = sv[kk];
-          fw[w + (int64_t)d * dcap] = slab;
-        }
+    int cursor = 0, nlive = 0;  // nlive: entries the pair tiles compared
+    // label ids BT_U per lane at a time; the vectors are read only where the
+    // block has to be rewritten (it moved, or entries before were dropped)
+    for (int t0 = 0; t0 < cnt; t0 += BT_ENTRIES) {
+      int slab[BT_U];
+#pragma unroll
+      for (int u = 0; u < BT_U; ++u) {
+        const int e = t0 + u * WAVE + lane;
+        slab[u] = e < cnt ? fw[nr.off + (int64_t)d * nr.cap + e] : 0;
       }
-      cursor += __popcll(am);
+#pragma unroll
+      for (int u = 0; u < BT_U; ++u) {
+        const int t = t0 + u * WAVE;
+        if (t >= cnt) break;
+        const int e = t + lane;
+        const bool has = e < cnt;
+        const bool keep = has && slab[u] >= 0;
+        nlive += __popcll(ballot(has && slab[u] != FW_REMOVED));
+        const uint64_t hm = ballot(has), am = ballot(keep);
+        if (moved || cursor != t || am != hm) {
+          if (keep) {
+            int32_t sv[DM];
+            FOR_K(kk) sv[kk] = fw[nr.off + (int64_t)kk * nr.cap + e];
+            const int64_t w = doff + cursor + rank_below(am);
+            FOR_K(kk) fw[w + (int64_t)kk * dcap] = sv[kk];
+            fw[w + (int64_t)d * dcap] = slab[u];
+          }
+        }
+        cursor += __popcll(am);
+      }
     }
+    fpairs += (int64_t)k * nlive;
+    fbytes += (int64_t)nlive * 4 * d;
     for (int ct = 0; ct < k; ct += WAVE) {
       const int j = ct + lane;
       const bool have = j < k;
@@ -1588,6 +1632,7 @@ __global__ __launch_bounds__(NT_SLOT) void k_accept_scan(Slot* slots) {
         const int rn = bn + rank_below(mn), rf = bf + rank_below(mf);
         S.c_rank[i] = rn + rf;
         S.c_rej[i] = a[u] == 1 ? rn : rf;
+        S.order[rn + rf] = i;  // accepted candidates by label id (grouping is done)
       }
       bn += __popcll(mn);
       bf += __popcll(mf);
@@ -1661,10 +1706,10 @@ __global__ void k_step_end(Slot* slots, int nslots) {
 
 // ---------------------------------------------------------------- launchers
 const char* const kStepKernelNames[kStepKernels] = {
-    "k_far_hist",    "k_far_move",       "k_open_hist",   "k_open_threshold", "k_open_scatter",  "k_batch_finalize", "k_goal_pairs", "k_goal_merge",
-    "k_popcheck",    "k_expand",         "k_pfilter",       "k_group_count",    "k_group_offsets",
-    "k_group_scatter", "k_group_process", "k_group_pairs",  "k_group_finish",   "k_accept_scan",
-    "k_insert",      "k_step_end"};
+    "k_far_hist",      "k_far_move",      "k_open_hist",     "k_open_threshold", "k_open_scatter",
+    "k_batch_finalize", "k_goal_pairs",   "k_goal_merge",    "k_popcheck",       "k_expand",
+    "k_group_count",   "k_group_offsets", "k_group_scatter", "k_group_process",  "k_group_pairs",
+    "k_group_finish",  "k_accept_scan",   "k_insert",        "k_pfilter",        "k_step_end"};
 
 template <int DM>
 static void launch_step_dm(const StepArgs& a, hipStream_t st, hipEvent_t* ev, uint32_t mask) {
@@ -1685,7 +1730,6 @@ static void launch_step_dm(const StepArgs& a, hipStream_t st, hipEvent_t* ev, ui
   mark(); hipLaunchKernelGGL(k_goal_merge<DM>, per, dim3(NT_SLOT), 0, st, a.slots);
   mark(); hipLaunchKernelGGL(k_popcheck<DM>, tiled, dim3(NT_TILE), 0, st, a.slots, a.G);
   mark(); hipLaunchKernelGGL(k_expand<DM>, tiled, dim3(NT_TILE), 0, st, a.slots, a.G);
-  mark(); hipLaunchKernelGGL(k_pfilter<DM>, tiled, dim3(NT_TILE), 0, st, a.slots, a.G);
   mark(); hipLaunchKernelGGL(k_group_count, tiled, dim3(NT_TILE), 0, st, a.slots);
   mark(); hipLaunchKernelGGL(k_group_offsets, per, dim3(NT_SLOT), 0, st, a.slots);
   mark(); hipLaunchKernelGGL(k_group_scatter, tiled, dim3(NT_TILE), 0, st, a.slots);
@@ -1694,6 +1738,7 @@ static void launch_step_dm(const StepArgs& a, hipStream_t st, hipEvent_t* ev, ui
   mark(); hipLaunchKernelGGL(k_group_finish<DM>, tiled, dim3(NT_TILE), 0, st, a.slots);
   mark(); hipLaunchKernelGGL(k_accept_scan, per, dim3(NT_SLOT), 0, st, a.slots);
   mark(); hipLaunchKernelGGL(k_insert<DM>, tiled, dim3(NT_TILE), 0, st, a.slots, a.G);
+  mark(); hipLaunchKernelGGL(k_pfilter<DM>, tiled, dim3(NT_TILE), 0, st, a.slots, a.G);
   mark(); hipLaunchKernelGGL(k_step_end, dim3((a.nslots + 63) / 64), dim3(64), 0, st, a.slots, a.nslots);
   mark();
 }
