@@ -395,6 +395,9 @@ def main():
                                for n, v in sorted(table.items(), key=lambda x: -x[1][0])},
         "kernel_table_steps": pre,
         "search_state": {"pops": s1["pops"], "labels": s1["inserted"], "front_so_far": s1["front"],
+                         "pops_per_s": (s1["pops"] - s0["pops"]) / wall,
+                         "labels_per_s": (s1["inserted"] - s0["inserted"]) / wall,
+                         "tie_entries_per_step": (s1["tie_entries"] - s0["tie_entries"]) / steps,
                          "pairs_timed": pairs,
                          "frontier_bytes_timed": s1["frontier_bytes"] - s0["frontier_bytes"]},
     }

@@ -468,7 +468,7 @@ __global__ __launch_bounds__(NT_SLOT) void k_batch_finalize(Slot* slots, GraphDe
   if (S.status != S_RUN) return;
   __shared__ int32_t lds[10240];
   __shared__ int tmp[NT_SLOT / WAVE];
-  __shared__ int sh_a, sh_b;
+  __shared__ int sh_a, sh_b, sh_c;
   const int d = S.d;
   int nb = S.batch_n, keep_n = S.keep_n;
   const uint64_t c0 = wall_clock64();
@@ -490,25 +490,38 @@ __global__ __launch_bounds__(NT_SLOT) void k_batch_finalize(Slot* slots, GraphDe
     constexpr int KC = 10240 - NB;
     const bool cache = n <= KC;
     while (und > TIECAP && need > 0 && need < und) {
+      // one level: histogram of the undecided entries' current key word over
+      // NB - 1 bins of width 2^shift spanning [min, max]; entries outside the
+      // bin holding the need-th smallest are decided
       ++levels;
-      if (threadIdx.x == 0) sh_a = INT32_MAX;
+      if (threadIdx.x == 0) {
+        sh_a = INT32_MAX;
+        sh_c = INT32_MIN;
+      }
       __syncthreads();
-      int mn = INT32_MAX;
+      int mn = INT32_MAX, mx = INT32_MIN;
       for (int i = threadIdx.x; i < n; i += NT_SLOT)
         if (TS[i] == 0) {
           const int x = key_word(S, i, word);
           if (cache) kc[i] = x;
           mn = min(mn, x);
+          mx = max(mx, x);
         }
       mn = wave_min(mn);
-      if (lane_id() == 0) atomicMin(&sh_a, mn);
+      mx = -wave_min(-mx);
+      if (lane_id() == 0) {
+        atomicMin(&sh_a, mn);
+        atomicMax(&sh_c, mx);
+      }
       for (int i = threadIdx.x; i < NB; i += NT_SLOT) hist[i] = 0;
       __syncthreads();
       const int m = sh_a;
+      int shift = 0;
+      while ((((int64_t)sh_c - m) >> shift) >= NB - 1) ++shift;
       for (int i = threadIdx.x; i < n; i += NT_SLOT)
         if (TS[i] == 0) {
-          const int64_t b = (int64_t)(cache ? kc[i] : key_word(S, i, word)) - m;
-          atomicAdd(&hist[b < NB - 1 ? (int)b : NB - 1], 1);
+          const int b = (int)(((int64_t)(cache ? kc[i] : key_word(S, i, word)) - m) >> shift);
+          atomicAdd(&hist[b], 1);
         }
       __syncthreads();
       constexpr int PER = NB / NT_SLOT;
@@ -540,14 +553,13 @@ __global__ __launch_bounds__(NT_SLOT) void k_batch_finalize(Slot* slots, GraphDe
       const int inb = hist[bstar] - below;
       for (int i = threadIdx.x; i < n; i += NT_SLOT)
         if (TS[i] == 0) {
-          const int64_t b64 = (int64_t)(cache ? kc[i] : key_word(S, i, word)) - m;
-          const int b = b64 < NB - 1 ? (int)b64 : NB - 1;
+          const int b = (int)(((int64_t)(cache ? kc[i] : key_word(S, i, word)) - m) >> shift);
           if (b < bstar) TS[i] = 1;
           else if (b > bstar) TS[i] = 2;
         }
       need -= below;
       und = inb;
-      if (bstar < NB - 1) ++word;  // the undecided now share this word's value
+      if (shift == 0) ++word;  // the undecided now share this word's value
       __syncthreads();
     }
     if (threadIdx.x == 0) {
@@ -682,14 +694,34 @@ __global__ __launch_bounds__(NT_SLOT) void k_batch_finalize(Slot* slots, GraphDe
 
 // ---------------------------------------------------------------- goal-front tests
 // A vector F is dropped when some goal-front entry p has p <= F in every
-// objective.  Front chunks are staged in LDS as int4 words; components k >= d
-// hold INT32_MIN and rows past the chunk hold INT32_MAX, so every test runs
-// over whole words with no bounds or objective-count checks, branch-free.
+// objective.  Front chunks are staged in LDS as int4 words: components k >= d
+// hold 0 (in the tested vectors too) and rows past the chunk hold INT32_MAX in
+// every component k < d, so every test runs over whole words with no bounds
+// or objective-count checks.  p <= F in every component exactly when the OR
+// of the differences F_k - p_k has a clear sign bit: costs lie in
+// [0, INT32_MAX), so no difference overflows.  A chunk dominates F when the
+// AND over its rows of those ORs has a clear sign bit (one subtract per
+// component, one OR and one AND per row; components at or beyond the
+// compile-time bound DM are skipped).
 template <int DM>
 struct FrontChunk {
   static constexpr int NW = (DM + 3) / 4;
   int4 w[PCH][NW];
 };
+
+__device__ __forceinline__ int comp(const int4& v, int c) {
+  return c == 0 ? v.x : (c == 1 ? v.y : (c == 2 ? v.z : v.w));
+}
+
+// OR over components k < DM of (q_k - r_k): sign bit clear <=> r <= q everywhere.
+template <int DM>
+__device__ __forceinline__ int or_diff(const int4 (&r)[FrontChunk<DM>::NW],
+                                       const int4 (&q)[FrontChunk<DM>::NW]) {
+  int o = 0;
+#pragma unroll
+  for (int k = 0; k < DM; ++k) o |= comp(q[k >> 2], k & 3) - comp(r[k >> 2], k & 3);
+  return o;
+}
 
 template <int DM>
 __device__ __forceinline__ void stage_chunk(FrontChunk<DM>& ch, const int32_t* Pg, int Pc, int p0,
@@ -699,7 +731,7 @@ __device__ __forceinline__ void stage_chunk(FrontChunk<DM>& ch, const int32_t* P
     int32_t v[NW * 4];
 #pragma unroll
     for (int k = 0; k < NW * 4; ++k)
-      v[k] = r < npt ? (k < d ? Pg[(size_t)k * Pc + p0 + r] : INT32_MIN) : INT32_MAX;
+      v[k] = k < d ? (r < npt ? Pg[(size_t)k * Pc + p0 + r] : INT32_MAX) : 0;
 #pragma unroll
     for (int w = 0; w < NW; ++w) ch.w[r][w] = make_int4(v[4 * w], v[4 * w + 1], v[4 * w + 2], v[4 * w + 3]);
   }
@@ -707,19 +739,10 @@ __device__ __forceinline__ void stage_chunk(FrontChunk<DM>& ch, const int32_t* P
 
 template <int DM>
 __device__ __forceinline__ bool chunk_dominates(const FrontChunk<DM>& ch, const int4 (&F)[FrontChunk<DM>::NW]) {
-  constexpr int NW = FrontChunk<DM>::NW;
-  int dom = 0;
-#pragma unroll 4
-  for (int q = 0; q < PCH; ++q) {
-    int le = 1;
-#pragma unroll
-    for (int w = 0; w < NW; ++w) {
-      const int4 p = ch.w[q][w];
-      le &= (p.x <= F[w].x) & (p.y <= F[w].y) & (p.z <= F[w].z) & (p.w <= F[w].w);
-    }
-    dom |= le;
-  }
-  return dom != 0;
+  int acc = -1;
+#pragma unroll 8
+  for (int q = 0; q < PCH; ++q) acc &= or_diff<DM>(ch.w[q], F);
+  return acc >= 0;
 }
 
 // ---------------------------------------------------------------- goal step
@@ -750,13 +773,11 @@ __device__ __forceinline__ void pack_query(const int32_t (&x)[FrontChunk<DM>::NW
 template <int DM>
 __device__ __forceinline__ void le_ne(const int4 (&r)[FrontChunk<DM>::NW], const int4 (&Q)[FrontChunk<DM>::NW],
                                       int& le, int& ne) {
-  le = 1;
-  ne = 0;
+  int x = 0;
 #pragma unroll
-  for (int w = 0; w < FrontChunk<DM>::NW; ++w) {
-    le &= (r[w].x <= Q[w].x) & (r[w].y <= Q[w].y) & (r[w].z <= Q[w].z) & (r[w].w <= Q[w].w);
-    ne |= (r[w].x != Q[w].x) | (r[w].y != Q[w].y) | (r[w].z != Q[w].z) | (r[w].w != Q[w].w);
-  }
+  for (int k = 0; k < DM; ++k) x |= comp(Q[k >> 2], k & 3) ^ comp(r[k >> 2], k & 3);
+  le = or_diff<DM>(r, Q) >= 0;
+  ne = x != 0;
 }
 
 template <int DM>
@@ -788,10 +809,10 @@ __global__ __launch_bounds__(NT_TILE) void k_goal_pairs(Slot* slots) {
     if (t < nt) {
       mylab = S.goal_lab[t0 + t];
 #pragma unroll
-      for (int k = 0; k < NW * 4; ++k) x[k] = k < d ? S.Lg[(size_t)k * pc + mylab] : INT32_MIN;
+      for (int k = 0; k < NW * 4; ++k) x[k] = k < d ? S.Lg[(size_t)k * pc + mylab] : 0;
     } else {
 #pragma unroll
-      for (int k = 0; k < NW * 4; ++k) x[k] = INT32_MAX;
+      for (int k = 0; k < NW * 4; ++k) x[k] = k < d ? INT32_MAX : 0;
     }
     int4 G[NW];
     pack_query<DM>(x, G);
@@ -831,7 +852,7 @@ __global__ __launch_bounds__(NT_TILE) void k_goal_pairs(Slot* slots) {
         olab[t] = lb;
         int32_t y[NW * 4];
 #pragma unroll
-        for (int k = 0; k < NW * 4; ++k) y[k] = k < d ? S.Lg[(size_t)k * pc + lb] : INT32_MIN;
+        for (int k = 0; k < NW * 4; ++k) y[k] = k < d ? S.Lg[(size_t)k * pc + lb] : 0;
 #pragma unroll
         for (int w = 0; w < NW; ++w)
           other.w[t][w] = make_int4(y[4 * w], y[4 * w + 1], y[4 * w + 2], y[4 * w + 3]);
@@ -922,6 +943,30 @@ __global__ __launch_bounds__(NT_SLOT) void k_goal_merge(Slot* slots) {
   }
 }
 
+// One tile of labels (one per thread, F packed as int4 words) against the front
+// chunks c0 .. c1-1, each staged in LDS in turn; stops early once every label
+// of the tile is dominated.  Returns whether this thread's label is dominated.
+// Work items are (label tile, run of chunks) pairs with runs sized so that the
+// items about fill the grid: a label's F is formed once per run.
+template <int DM>
+__device__ bool tile_vs_front(FrontChunk<DM>& ch, const int32_t* Pg, int Pc, int np, int d,
+                              int c0, int c1, bool have, const int4 (&F)[FrontChunk<DM>::NW]) {
+  bool dom = false;
+  for (int c = c0; c < c1; ++c) {
+    const int p0 = c * PCH;
+    __syncthreads();
+    stage_chunk<DM>(ch, Pg, Pc, p0, min(PCH, np - p0), d);
+    __syncthreads();
+    if (have && !dom) dom = chunk_dominates<DM>(ch, F);
+    if (__syncthreads_and(!have || dom)) break;
+  }
+  return dom;
+}
+
+__device__ __forceinline__ int chunks_per_item(int nlt, int npc) {
+  return max(1, (nlt * npc + (int)gridDim.x - 1) / (int)gridDim.x);
+}
+
 // The paper's PruneOPEN drops every open label whose F the goal front
 // dominates (Algorithm 1); here it is applied lazily to the
 // popped regular labels (weak dominance), after this step's goal labels were
@@ -935,7 +980,8 @@ __global__ __launch_bounds__(NT_TILE) void k_popcheck(Slot* slots, GraphDev G) {
   const int R = S.reg_n, np = S.P_n;
   if (R == 0 || np == 0) return;
   const int nlt = (R + NT_TILE - 1) / NT_TILE, npc = (np + PCH - 1) / PCH;
-  const int ntiles = nlt * npc;
+  const int cpi = chunks_per_item(nlt, npc), ngrp = (npc + cpi - 1) / cpi;
+  const int ntiles = nlt * ngrp;
   if ((int)blockIdx.x >= ntiles) return;
   constexpr int NW = FrontChunk<DM>::NW;
   __shared__ FrontChunk<DM> ch;
@@ -943,26 +989,27 @@ __global__ __launch_bounds__(NT_TILE) void k_popcheck(Slot* slots, GraphDev G) {
   const int32_t* Pg = pick(S.Pg, S.P_sel);
   int killed = 0;
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    const int lt = t / npc, pcn = t - lt * npc;
-    const int p0 = pcn * PCH, npt = min(PCH, np - p0);
-    __syncthreads();
-    stage_chunk<DM>(ch, Pg, Pc, p0, npt, d);
-    __syncthreads();
+    const int lt = t / ngrp, gi = t - lt * ngrp;
     const int i = lt * NT_TILE + threadIdx.x;
-    if (i < R) {
-      const int lab = S.reg[i];
+    const bool have = i < R && !S.reg_kill[i];
+    int lab = 0;
+    int32_t f[NW * 4];
+#pragma unroll
+    for (int k = 0; k < NW * 4; ++k) f[k] = 0;
+    if (have) {
+      lab = S.reg[i];
       const int v = S.Lnode[lab];
-      int32_t f[NW * 4];
 #pragma unroll
       for (int k = 0; k < NW * 4; ++k)
         f[k] = k < d ? S.Lg[(size_t)k * pc + lab] + S.h[(size_t)k * n + v] : 0;
-      int4 F[NW];
+    }
+    int4 F[NW];
 #pragma unroll
-      for (int w = 0; w < NW; ++w) F[w] = make_int4(f[4 * w], f[4 * w + 1], f[4 * w + 2], f[4 * w + 3]);
-      if (chunk_dominates<DM>(ch, F) && atomicExch(&S.reg_kill[i], 1) == 0) {
-        S.Lstate[lab] = L_DEAD;
-        ++killed;
-      }
+    for (int w = 0; w < NW; ++w) F[w] = make_int4(f[4 * w], f[4 * w + 1], f[4 * w + 2], f[4 * w + 3]);
+    const bool dom = tile_vs_front<DM>(ch, Pg, Pc, np, d, gi * cpi, min(npc, (gi + 1) * cpi), have, F);
+    if (have && dom && atomicExch(&S.reg_kill[i], 1) == 0) {
+      S.Lstate[lab] = L_DEAD;
+      ++killed;
     }
   }
   const int64_t k64 = wave_sum64(killed);
@@ -1039,33 +1086,34 @@ __global__ __launch_bounds__(NT_TILE) void k_pfilter(Slot* slots, GraphDev G) {
   if (blockIdx.x == 0 && threadIdx.x == 0)
     atomicAdd((unsigned long long*)&Sp->st[ST_PPAIRS], (unsigned long long)((int64_t)R * (np - S.P_dead)));
   const int nlt = (R + NT_TILE - 1) / NT_TILE, npc = (np + PCH - 1) / PCH;
-  const int ntiles = nlt * npc;
+  const int cpi = chunks_per_item(nlt, npc), ngrp = (npc + cpi - 1) / cpi;
+  const int ntiles = nlt * ngrp;
   if ((int)blockIdx.x >= ntiles) return;
   constexpr int NW = FrontChunk<DM>::NW;
   __shared__ FrontChunk<DM> ch;
   const int d = S.d, pc = S.pool_cap, Pc = S.P_cap, n = G.n;
   const int32_t* Pg = pick(S.Pg, S.P_sel);
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    const int lt = t / npc, pcn = t - lt * npc;
-    const int p0 = pcn * PCH, npt = min(PCH, np - p0);
-    __syncthreads();
-    stage_chunk<DM>(ch, Pg, Pc, p0, npt, d);
-    __syncthreads();
+    const int lt = t / ngrp, gi = t - lt * ngrp;
     const int i = lt * NT_TILE + threadIdx.x;
-    if (i < R) {
-      const int id = base + i;
+    const int id = base + i;
+    const bool have = i < R && S.Lstate[id] != L_DEAD;
+    int32_t x[NW * 4];
+#pragma unroll
+    for (int k = 0; k < NW * 4; ++k) x[k] = 0;
+    if (have) {
       const int v = S.Lnode[id];
-      int32_t x[NW * 4];
 #pragma unroll
       for (int k = 0; k < NW * 4; ++k)
         x[k] = k < d ? S.Lg[(size_t)k * pc + id] + S.h[(size_t)k * n + v] : 0;
-      int4 F[NW];
+    }
+    int4 F[NW];
 #pragma unroll
-      for (int w = 0; w < NW; ++w) F[w] = make_int4(x[4 * w], x[4 * w + 1], x[4 * w + 2], x[4 * w + 3]);
-      if (chunk_dominates<DM>(ch, F)) {
-        S.Lstate[id] = L_DEAD;
-        S.fw[S.c_fslot[S.order[i]]] = FW_REMOVED;  // leaves its node's frontier
-      }
+    for (int w = 0; w < NW; ++w) F[w] = make_int4(x[4 * w], x[4 * w + 1], x[4 * w + 2], x[4 * w + 3]);
+    const bool dom = tile_vs_front<DM>(ch, Pg, Pc, np, d, gi * cpi, min(npc, (gi + 1) * cpi), have, F);
+    if (have && dom) {
+      S.Lstate[id] = L_DEAD;
+      S.fw[S.c_fslot[S.order[i]]] = FW_REMOVED;  // leaves its node's frontier
     }
   }
 }
@@ -1201,6 +1249,28 @@ constexpr int U = 4;  // frontier entries per lane per pass
 
 __device__ __forceinline__ int bcast(int v, int lane) { return __builtin_amdgcn_readlane(v, lane); }
 
+// For candidate c and frontier entry e (components k >= d are 0 on both
+// sides; costs lie in [0, INT32_MAX), so no difference overflows):
+//   dmin = min_k (c_k - e_k), dmax = max_k (c_k - e_k);
+//   e <= c in every component            <=>  dmin >= 0  (e rejects c)
+//   c <= e everywhere and c != e         <=>  dmax <= 0 and dmin < 0
+//                                        <=>  sign bit of ((dmax - 1) & dmin)  (c prunes e)
+// Plain integer arithmetic (min3/max3, no per-component compares or masks).
+// An absent entry is given INT32_MAX in every component k < d: then dmin < 0,
+// so it rejects nothing, and its prune flag is masked out by its owner.
+template <int DM>
+__device__ __forceinline__ void diff_range(const int32_t (&c)[DM], const int32_t (&e)[DM], int& dmin,
+                                           int& dmax) {
+  dmin = c[0] - e[0];
+  dmax = dmin;
+#pragma unroll
+  for (int k = 1; k < DM; ++k) {
+    const int t = c[k] - e[k];
+    dmin = min(dmin, t);
+    dmax = max(dmax, t);
+  }
+}
+
 template <int DM>
 __device__ __forceinline__ void load_entries(const int32_t* fw, const NodeRec& nr, int d, int base,
                                              int32_t (&sv)[U][DM], int32_t (&lab)[U]) {
@@ -1275,30 +1345,33 @@ __global__ __launch_bounds__(NT_TILE) void k_group_process(Slot* slots) {
         clab[u] = slab[u];
       }
       if (t + U * WAVE < cnt) load_entries<DM>(fw, nr, d, t + U * WAVE, sv, slab);
-      bool prune[U];
+      bool present[U], prune[U];
+      int32_t ev[U][DM];  // compare values: absent entries get INT32_MAX (k < d)
+      int pacc[U];
 #pragma unroll
-      for (int u = 0; u < U; ++u) prune[u] = false;
+      for (int u = 0; u < U; ++u) {
+        present[u] = t + u * WAVE + lane < cnt && clab[u] != FW_REMOVED;
+#pragma unroll
+        for (int kk = 0; kk < DM; ++kk) ev[u][kk] = present[u] ? cv[u][kk] : (kk < d ? INT32_MAX : 0);
+        pacc[u] = 0;
+      }
       for (uint64_t m = surv & ~rejm; m; m &= m - 1) {
         const int jj = __ffsll((long long)m) - 1;
         int32_t c[DM];
 #pragma unroll
         for (int kk = 0; kk < DM; ++kk) c[kk] = bcast(ci[kk], jj);
-        bool anyle = false;
+        int allneg = -1;
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-          bool le = true, ge = true, lt = false;
-#pragma unroll
-          for (int kk = 0; kk < DM; ++kk) {
-            le = le & (cv[u][kk] <= c[kk]);
-            ge = ge & (c[kk] <= cv[u][kk]);
-            lt = lt | (c[kk] < cv[u][kk]);
-          }
-          const bool has = t + u * WAVE + lane < cnt && clab[u] != FW_REMOVED;
-          anyle = anyle | (has & le);
-          prune[u] = prune[u] | (has & ge & lt);
+          int dmin, dmax;
+          diff_range<DM>(c, ev[u], dmin, dmax);
+          allneg &= dmin;
+          pacc[u] |= (dmax - 1) & dmin;
         }
-        if (ballot(anyle)) rejm |= 1ull << jj;
+        if (ballot(allneg >= 0)) rejm |= 1ull << jj;
       }
+#pragma unroll
+      for (int u = 0; u < U; ++u) prune[u] = present[u] && pacc[u] < 0;
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int tb = t + u * WAVE;
@@ -1406,7 +1479,7 @@ __global__ __launch_bounds__(NT_TILE) void k_group_pairs(Slot* slots) {
     int32_t cj[DM];
 #pragma unroll
     for (int kk = 0; kk < DM; ++kk) cj[kk] = (hj && kk < d) ? S.c_g[(size_t)kk * cc + fj] : 0;
-    const int nj = min(WAVE, k - J * WAVE);
+    const int nj = __builtin_amdgcn_readfirstlane(min(WAVE, k - J * WAVE));  // wave-uniform
     if (is_a) {
       const int i = I * WAVE + lane;
       const bool hi = i < k;
@@ -1440,29 +1513,28 @@ __global__ __launch_bounds__(NT_TILE) void k_group_pairs(Slot* slots) {
         has[u] = e < nr.count && fw[nr.off + (int64_t)d * nr.cap + e] != FW_REMOVED;
 #pragma unroll
         for (int kk = 0; kk < DM; ++kk)
-          sv[u][kk] = (has[u] && kk < d) ? fw[nr.off + (int64_t)kk * nr.cap + e] : 0;
-        prune[u] = false;
+          sv[u][kk] = kk < d ? (has[u] ? fw[nr.off + (int64_t)kk * nr.cap + e] : INT32_MAX) : 0;
       }
       uint64_t rejm = 0;
+      int pacc[BT_U];
+#pragma unroll
+      for (int u = 0; u < BT_U; ++u) pacc[u] = 0;
       for (int jj = 0; jj < nj; ++jj) {
         int32_t c[DM];
 #pragma unroll
         for (int kk = 0; kk < DM; ++kk) c[kk] = bcast(cj[kk], jj);
-        bool anyle = false;
+        int allneg = -1;
 #pragma unroll
         for (int u = 0; u < BT_U; ++u) {
-          bool le = has[u], ge = has[u], lt = false;
-#pragma unroll
-          for (int kk = 0; kk < DM; ++kk) {
-            le = le & (sv[u][kk] <= c[kk]);
-            ge = ge & (c[kk] <= sv[u][kk]);
-            lt = lt | (c[kk] < sv[u][kk]);
-          }
-          anyle = anyle | le;
-          prune[u] = prune[u] | (ge & lt);
+          int dmin, dmax;
+          diff_range<DM>(c, sv[u], dmin, dmax);
+          allneg &= dmin;
+          pacc[u] |= (dmax - 1) & dmin;
         }
-        if (ballot(anyle)) rejm |= 1ull << jj;
+        if (ballot(allneg >= 0)) rejm |= 1ull << jj;
       }
+#pragma unroll
+      for (int u = 0; u < BT_U; ++u) prune[u] = has[u] && pacc[u] < 0;
       if ((rejm >> lane) & 1ull) S.c_rej[fj] = 1;
 #pragma unroll
       for (int u = 0; u < BT_U; ++u) {
