@@ -66,6 +66,18 @@ __device__ int block_exscan(int v, int* total, int* tmp /* >= NT/64 ints */) {
   return before + x - v;
 }
 
+// Wave-aggregated append to an LDS counter: lanes with p get consecutive
+// positions (in no particular order across waves); -1 for !p.
+__device__ __forceinline__ int lds_append(int* ctr, bool p) {
+  const uint64_t m = ballot(p);
+  if (m == 0) return -1;
+  const int leader = __ffsll((long long)m) - 1;
+  int base = 0;
+  if (lane_id() == leader) base = atomicAdd(ctr, __popcll(m));
+  base = __shfl(base, leader);
+  return p ? base + rank_below(m) : -1;
+}
+
 // Workgroup-aggregated append of NQ flags per thread: one atomic per counter
 // and workgroup; pos[q] is the thread's position for counter q (-1 if !p[q]).
 // Every thread of the workgroup calls it (it synchronises the workgroup).
@@ -383,6 +395,7 @@ __global__ __launch_bounds__(NT_TILE) void k_open_scatter(Slot* slots) {
     if (to_tie && p < S.tie_cap) {
       S.tie_f1[p] = f;
       S.tie_lab[p] = lab;
+      S.tie_st[p] = 0;
       const int v = S.Lnode[lab];
       for (int k = 1; k < S.d; ++k)
         S.tie_key[(size_t)(k - 1) * S.tie_cap + p] = S.Lg[(size_t)k * S.pool_cap + lab] +
@@ -480,9 +493,7 @@ __global__ __launch_bounds__(NT_SLOT) void k_batch_finalize(Slot* slots, GraphDe
     // are ordered in LDS.  (F, node) is unique among live labels, so this ends.
     const int n = min(S.tie_n, S.tie_cap);
     int need = S.r_tie;
-    int32_t* TS = S.tie_st;  // 0 undecided, 1 taken, 2 not taken
-    for (int i = threadIdx.x; i < n; i += NT_SLOT) TS[i] = 0;
-    __syncthreads();
+    int32_t* TS = S.tie_st;  // 0 undecided (set by the scatter), 1 taken, 2 not taken
     // an inner bin holds a single F1 value: refinement starts at F2
     int und = n, word = (S.t_star > 0 && S.t_star < NB - 1) ? 1 : 0, levels = 0;
     int32_t* hist = lds;        // NB ints
@@ -578,16 +589,15 @@ __global__ __launch_bounds__(NT_SLOT) void k_batch_finalize(Slot* slots, GraphDe
       constexpr int KW = (DM + 1 + 3) / 4;
       int4* K4 = reinterpret_cast<int4*>(lds);          // TIECAP x KW words
       int32_t* idx = lds + 4 * KW * TIECAP;              // positions into the tie arrays
-      int cnt = 0;
+      if (threadIdx.x == 0) sh_a = 0;
+      __syncthreads();
       for (int base = 0; base < n; base += NT_SLOT) {
         const int i = base + threadIdx.x;
-        const int u = (i < n && TS[i] == 0) ? 1 : 0;
-        int tt;
-        const int p = block_exscan<NT_SLOT>(u, &tt, tmp);
-        if (u && cnt + p < TIECAP) idx[cnt + p] = i;
-        cnt += tt;
+        const int p = lds_append(&sh_a, i < n && TS[i] == 0);
+        if (p >= 0 && p < TIECAP) idx[p] = i;
       }
       __syncthreads();
+      const int cnt = min(sh_a, TIECAP);
       if (threadIdx.x < cnt) {
         const int i = threadIdx.x;
         int32_t key[KW * 4];
@@ -627,26 +637,29 @@ __global__ __launch_bounds__(NT_SLOT) void k_batch_finalize(Slot* slots, GraphDe
     // taken -> batch, not taken -> OPEN (other buffer)
     int32_t* KF = pick(S.open_f1, S.open_sel ^ 1);
     int32_t* KL = pick(S.open_lab, S.open_sel ^ 1);
-    int taken = 0, kept = 0, kmin = INT32_MAX;
+    int kmin = INT32_MAX;
+    if (threadIdx.x == 0) {
+      sh_a = 0;
+      sh_b = 0;
+    }
+    __syncthreads();
     for (int base = 0; base < n; base += NT_SLOT) {
       const int i = base + threadIdx.x;
       const int st = i < n ? TS[i] : 0;
-      int t1, t2;
-      const int p1 = block_exscan<NT_SLOT>(st == 1 ? 1 : 0, &t1, tmp);
-      const int p2 = block_exscan<NT_SLOT>(st == 2 ? 1 : 0, &t2, tmp);
-      if (st == 1 && nb + taken + p1 < S.batch_cap) S.batch[nb + taken + p1] = S.tie_lab[i];
-      if (st == 2 && keep_n + kept + p2 < S.open_cap) {
-        KF[keep_n + kept + p2] = S.tie_f1[i];
-        KL[keep_n + kept + p2] = S.tie_lab[i];
+      const int p1 = lds_append(&sh_a, st == 1);
+      const int p2 = lds_append(&sh_b, st == 2);
+      if (p1 >= 0 && nb + p1 < S.batch_cap) S.batch[nb + p1] = S.tie_lab[i];
+      if (p2 >= 0 && keep_n + p2 < S.open_cap) {
+        KF[keep_n + p2] = S.tie_f1[i];
+        KL[keep_n + p2] = S.tie_lab[i];
         kmin = min(kmin, S.tie_f1[i]);
       }
-      taken += t1;
-      kept += t2;
     }
     kmin = wave_min(kmin);
     if (lane_id() == 0 && kmin != INT32_MAX) atomicMin(&Sp->lo_next, kmin);
-    nb += taken;
-    keep_n += kept;
+    __syncthreads();
+    nb += sh_a;
+    keep_n += sh_b;
     if (threadIdx.x == 0) {
       Sp->batch_n = nb;
       Sp->keep_n = keep_n;
