@@ -1594,15 +1594,16 @@ __global__ __launch_bounds__(NT_TILE) void k_group_finish(Slot* slots) {
     int cursor = 0, nlive = 0;  // nlive: entries the pair tiles compared
     // label ids BT_U per lane at a time; the vectors are read only where the
     // block has to be rewritten (it moved, or entries before were dropped)
-    for (int t0 = 0; t0 < cnt; t0 += BT_ENTRIES) {
-      int slab[BT_U];
+    constexpr int FU = 16;  // label ids per lane in flight
+    for (int t0 = 0; t0 < cnt; t0 += FU * WAVE) {
+      int slab[FU];
 #pragma unroll
-      for (int u = 0; u < BT_U; ++u) {
+      for (int u = 0; u < FU; ++u) {
         const int e = t0 + u * WAVE + lane;
         slab[u] = e < cnt ? fw[nr.off + (int64_t)d * nr.cap + e] : 0;
       }
 #pragma unroll
-      for (int u = 0; u < BT_U; ++u) {
+      for (int u = 0; u < FU; ++u) {
         const int t = t0 + u * WAVE;
         if (t >= cnt) break;
         const int e = t + lane;
@@ -1624,20 +1625,31 @@ __global__ __launch_bounds__(NT_TILE) void k_group_finish(Slot* slots) {
     }
     fpairs += (int64_t)k * nlive;
     fbytes += (int64_t)nlive * 4 * d;
-    for (int ct = 0; ct < k; ct += WAVE) {
-      const int j = ct + lane;
-      const bool have = j < k;
-      const int fj = have ? ord[j] : 0;
-      const bool acc = have && !S.c_rej[fj];
-      const uint64_t m = ballot(acc);
-      if (acc) {
-        const int64_t w = doff + cursor + rank_below(m);
-        FOR_K(kk) fw[w + (int64_t)kk * dcap] = S.c_g[(size_t)kk * cc + fj];
-        fw[w + (int64_t)d * dcap] = -1;
-        S.c_fslot[fj] = w + (int64_t)d * dcap;
-        S.c_acc[fj] = open_tier(S, S.c_g[fj] + S.h[v]);
+    const int hv = S.h[v];
+    constexpr int CU = 4;  // candidates per lane in flight
+    for (int c0 = 0; c0 < k; c0 += CU * WAVE) {
+      int fjs[CU];
+      bool accs[CU];
+#pragma unroll
+      for (int u = 0; u < CU; ++u) {
+        const int j = c0 + u * WAVE + lane;
+        fjs[u] = j < k ? ord[j] : -1;
       }
-      cursor += __popcll(m);
+#pragma unroll
+      for (int u = 0; u < CU; ++u) accs[u] = fjs[u] >= 0 && !S.c_rej[fjs[u]];
+#pragma unroll
+      for (int u = 0; u < CU; ++u) {
+        const uint64_t m = ballot(accs[u]);
+        if (accs[u]) {
+          const int fj = fjs[u];
+          const int64_t w = doff + cursor + rank_below(m);
+          FOR_K(kk) fw[w + (int64_t)kk * dcap] = S.c_g[(size_t)kk * cc + fj];
+          fw[w + (int64_t)d * dcap] = -1;
+          S.c_fslot[fj] = w + (int64_t)d * dcap;
+          S.c_acc[fj] = open_tier(S, S.c_g[fj] + hv);
+        }
+        cursor += __popcll(m);
+      }
     }
     if (lane == 0) {
       NodeRec out;
