@@ -263,11 +263,11 @@ static bool plan_layout(const mos_graph* g, int d, int B, int64_t budget, int64_
   L->tie_cap = TIECAP;
   const int64_t fixed = fixed_bytes(g->n, d, L->batch_cap, L->cand_cap, 0);
   if (budget <= fixed) return false;
-  // bytes per pooled label: pool (node, parent, arc, g, state) + OPEN 2x(F1,
+  // bytes per pooled label: pool (node, parent, arc, g, state, tested mark) + OPEN 2x(F1,
   // lab) + tie set (F1, lab, state, d key words) + frontier 3*(d+1) words + goal
   // front share
-  const double per = (12.0 + 4.0 * d + 1.0) + 32.0 + 12.0 + 4.0 * d + 12.0 * (d + 1) +
-                     (8.0 * (d + 1) + 8.0) / 8.0;
+  const double per = (16.0 + 4.0 * d + 1.0) + 32.0 + 12.0 + 4.0 * d + 12.0 * (d + 1) +
+                     (8.0 * (d + 2) + 8.0) / 8.0;
   int64_t pool = (int64_t)((double)(budget - fixed - 32 * 256) / per);
   pool = std::min<int64_t>(pool, (int64_t)1 << 30);
   if (label_limit > 0) pool = std::min<int64_t>(pool, label_limit);
@@ -281,7 +281,7 @@ static bool plan_layout(const mos_graph* g, int d, int B, int64_t budget, int64_
   b += 3 * al(4 * pool) + al(4 * (int64_t)d * pool) + al(pool);  // pool
   b += 8 * al(4 * pool);                                          // OPEN near + far tiers
   b += 3 * al(4 * pool) + al(4 * (int64_t)d * pool);             // tie set and its keys
-  b += 2 * (al(4 * (int64_t)d * L->P_cap) + al(4 * (int64_t)L->P_cap));
+  b += 2 * (al(4 * (int64_t)d * L->P_cap) + 2 * al(4 * (int64_t)L->P_cap)) + al(4 * pool);
   b += al(4 * L->fw_cap);
   L->bytes = al(b);
   return L->bytes <= budget;
@@ -325,6 +325,7 @@ static void carve(Slot& s, char* base, const Layout& L, int64_t n, int d) {
   s.Lpar = (int32_t*)take(4 * pc);
   s.Larc = (int32_t*)take(4 * pc);
   s.Lg = (int32_t*)take(4 * (int64_t)d * pc);
+  s.Lpseq = (int32_t*)take(4 * pc);
   s.Lstate = (uint8_t*)take(pc);
   for (int b = 0; b < 2; ++b) {
     s.open_f1[b] = (int32_t*)take(4 * (int64_t)L.open_cap);
@@ -339,6 +340,7 @@ static void carve(Slot& s, char* base, const Layout& L, int64_t n, int d) {
   for (int b = 0; b < 2; ++b) {
     s.Pg[b] = (int32_t*)take(4 * (int64_t)d * L.P_cap);
     s.Plab[b] = (int32_t*)take(4 * (int64_t)L.P_cap);
+    s.Pseq[b] = (int32_t*)take(4 * (int64_t)L.P_cap);
   }
   s.fw = (int32_t*)take(4 * L.fw_cap);
   if (p - base > L.bytes) throw MosError(MOS_E_DEVICE, "slot layout overrun");

@@ -125,6 +125,7 @@ __global__ void k_slot_seed(Slot* slots, int s, GraphDev G) {
   S->P_n = 0;
   S->P_sel = 0;
   S->P_dead = 0;
+  S->P_seq = 0;
   S->lo_next = INT32_MAX;
   if (!reach) {
     S->n_labels = 0;
@@ -136,6 +137,7 @@ __global__ void k_slot_seed(Slot* slots, int s, GraphDev G) {
   S->Lpar[0] = -1;
   S->Larc[0] = -1;
   S->Lstate[0] = L_OPEN;
+  S->Lpseq[0] = 0;
   for (int k = 0; k < d; ++k) S->Lg[(size_t)k * S->pool_cap] = 0;
   S->n_labels = 1;
   NodeRec r;

@@ -112,6 +112,8 @@ struct Slot {
   int32_t* Pg[2];      // d planes of P_cap each: goal front (unordered; a removed
                        //   entry holds INT32_MAX in every plane until compaction)
   int32_t* Plab[2];    //   label id of each goal-front entry
+  int32_t* Pseq[2];    //   append number of each entry (increasing along P)
+  int32_t* Lpseq;      // pool_cap: goal-front appends already tested against the label
   int32_t* batch;      // batch_cap: popped labels
   int32_t* reg;        // batch_cap: popped regular labels (ascending label id)
   int32_t* reg_off;    // batch_cap+1: exclusive prefix of their out-degrees
@@ -141,6 +143,7 @@ struct Slot {
   // ---------------- dynamic (device-updated)
   int32_t n_labels, open_n, open_sel, P_n;
   int32_t P_sel, lo, lo_next, P_dead;  // P_dead: removed entries among the first P_n
+  int32_t P_seq, pad4;                  // P_seq: goal-front entries appended so far
   int64_t fw_top;
   int32_t t_star, r_tie, tie_mode, big_work;  // big_work: set at admission
   int32_t batch_n, goal_n, reg_n, cand_n;

@@ -510,14 +510,26 @@ __global__ __launch_bounds__(NT_SLOT) void k_batch_finalize(Slot* slots, GraphDe
         sh_c = INT32_MIN;
       }
       __syncthreads();
+      // passes over the tie set: TU entries per thread with their loads issued
+      // together (state and key word are independent loads)
+      constexpr int TU = 4;
       int mn = INT32_MAX, mx = INT32_MIN;
-      for (int i = threadIdx.x; i < n; i += NT_SLOT)
-        if (TS[i] == 0) {
-          const int x = key_word(S, i, word);
-          if (cache) kc[i] = x;
-          mn = min(mn, x);
-          mx = max(mx, x);
+      for (int base = threadIdx.x; base < n; base += TU * NT_SLOT) {
+        int ts[TU], x[TU];
+#pragma unroll
+        for (int u = 0; u < TU; ++u) {
+          const int i = base + u * NT_SLOT;
+          ts[u] = i < n ? TS[i] : 3;
+          x[u] = i < n ? key_word(S, i, word) : 0;
         }
+#pragma unroll
+        for (int u = 0; u < TU; ++u)
+          if (ts[u] == 0) {
+            if (cache) kc[base + u * NT_SLOT] = x[u];
+            mn = min(mn, x[u]);
+            mx = max(mx, x[u]);
+          }
+      }
       mn = wave_min(mn);
       mx = -wave_min(-mx);
       if (lane_id() == 0) {
@@ -529,11 +541,18 @@ __global__ __launch_bounds__(NT_SLOT) void k_batch_finalize(Slot* slots, GraphDe
       const int m = sh_a;
       int shift = 0;
       while ((((int64_t)sh_c - m) >> shift) >= NB - 1) ++shift;
-      for (int i = threadIdx.x; i < n; i += NT_SLOT)
-        if (TS[i] == 0) {
-          const int b = (int)(((int64_t)(cache ? kc[i] : key_word(S, i, word)) - m) >> shift);
-          atomicAdd(&hist[b], 1);
+      for (int base = threadIdx.x; base < n; base += TU * NT_SLOT) {
+        int ts[TU], x[TU];
+#pragma unroll
+        for (int u = 0; u < TU; ++u) {
+          const int i = base + u * NT_SLOT;
+          ts[u] = i < n ? TS[i] : 3;
+          x[u] = i < n ? (cache ? kc[i] : key_word(S, i, word)) : 0;
         }
+#pragma unroll
+        for (int u = 0; u < TU; ++u)
+          if (ts[u] == 0) atomicAdd(&hist[(int)(((int64_t)x[u] - m) >> shift)], 1);
+      }
       __syncthreads();
       constexpr int PER = NB / NT_SLOT;
       int loc[PER], sum = 0;
@@ -562,12 +581,22 @@ __global__ __launch_bounds__(NT_SLOT) void k_batch_finalize(Slot* slots, GraphDe
       const int bstar = sh_b;
       const int below = bstar > 0 ? hist[bstar - 1] : 0;
       const int inb = hist[bstar] - below;
-      for (int i = threadIdx.x; i < n; i += NT_SLOT)
-        if (TS[i] == 0) {
-          const int b = (int)(((int64_t)(cache ? kc[i] : key_word(S, i, word)) - m) >> shift);
-          if (b < bstar) TS[i] = 1;
-          else if (b > bstar) TS[i] = 2;
+      for (int base = threadIdx.x; base < n; base += TU * NT_SLOT) {
+        int ts[TU], x[TU];
+#pragma unroll
+        for (int u = 0; u < TU; ++u) {
+          const int i = base + u * NT_SLOT;
+          ts[u] = i < n ? TS[i] : 3;
+          x[u] = i < n ? (cache ? kc[i] : key_word(S, i, word)) : 0;
         }
+#pragma unroll
+        for (int u = 0; u < TU; ++u)
+          if (ts[u] == 0) {
+            const int b = (int)(((int64_t)x[u] - m) >> shift);
+            if (b < bstar) TS[base + u * NT_SLOT] = 1;
+            else if (b > bstar) TS[base + u * NT_SLOT] = 2;
+          }
+      }
       need -= below;
       und = inb;
       if (shift == 0) ++word;  // the undecided now share this word's value
@@ -643,16 +672,26 @@ __global__ __launch_bounds__(NT_SLOT) void k_batch_finalize(Slot* slots, GraphDe
       sh_b = 0;
     }
     __syncthreads();
-    for (int base = 0; base < n; base += NT_SLOT) {
-      const int i = base + threadIdx.x;
-      const int st = i < n ? TS[i] : 0;
-      const int p1 = lds_append(&sh_a, st == 1);
-      const int p2 = lds_append(&sh_b, st == 2);
-      if (p1 >= 0 && nb + p1 < S.batch_cap) S.batch[nb + p1] = S.tie_lab[i];
-      if (p2 >= 0 && keep_n + p2 < S.open_cap) {
-        KF[keep_n + p2] = S.tie_f1[i];
-        KL[keep_n + p2] = S.tie_lab[i];
-        kmin = min(kmin, S.tie_f1[i]);
+    constexpr int DU = 4;  // tie entries per thread in flight
+    for (int base = 0; base < n; base += DU * NT_SLOT) {
+      int st[DU], lab[DU], f1[DU];
+#pragma unroll
+      for (int u = 0; u < DU; ++u) {
+        const int i = base + u * NT_SLOT + threadIdx.x;
+        st[u] = i < n ? TS[i] : 0;
+        lab[u] = i < n ? S.tie_lab[i] : 0;
+        f1[u] = i < n ? S.tie_f1[i] : 0;
+      }
+#pragma unroll
+      for (int u = 0; u < DU; ++u) {
+        const int p1 = lds_append(&sh_a, st[u] == 1);
+        const int p2 = lds_append(&sh_b, st[u] == 2);
+        if (p1 >= 0 && nb + p1 < S.batch_cap) S.batch[nb + p1] = lab[u];
+        if (p2 >= 0 && keep_n + p2 < S.open_cap) {
+          KF[keep_n + p2] = f1[u];
+          KL[keep_n + p2] = lab[u];
+          kmin = min(kmin, f1[u]);
+        }
       }
     }
     kmin = wave_min(kmin);
@@ -904,6 +943,7 @@ __global__ __launch_bounds__(NT_SLOT) void k_goal_merge(Slot* slots) {
   const int ng = S.goal_n, np = S.P_n;
   int32_t* Pg = pick(S.Pg, S.P_sel);
   int32_t* Pl = pick(S.Plab, S.P_sel);
+  int32_t* Ps = pick(S.Pseq, S.P_sel);
   if (np + ng > Pc) {
     if (threadIdx.x == 0) {
       Sp->status = S_OVERFLOW;
@@ -921,6 +961,7 @@ __global__ __launch_bounds__(NT_SLOT) void k_goal_merge(Slot* slots) {
       const int lab = S.goal_lab[i];
       FOR_K(k) Pg[(size_t)k * Pc + np + na + pos] = S.Lg[(size_t)k * pc + lab];
       Pl[np + na + pos] = lab;
+      Ps[np + na + pos] = S.P_seq + na + pos;
     }
     na += tot;
   }
@@ -930,6 +971,7 @@ __global__ __launch_bounds__(NT_SLOT) void k_goal_merge(Slot* slots) {
     __syncthreads();  // appended entries visible to the whole workgroup
     int32_t* Qg = pick(S.Pg, S.P_sel ^ 1);
     int32_t* Ql = pick(S.Plab, S.P_sel ^ 1);
+    int32_t* Qs = pick(S.Pseq, S.P_sel ^ 1);
     int carry = 0;
     for (int base = 0; base < n1; base += NT_SLOT) {
       const int i = base + threadIdx.x;
@@ -939,6 +981,7 @@ __global__ __launch_bounds__(NT_SLOT) void k_goal_merge(Slot* slots) {
       if (a) {
         FOR_K(k) Qg[(size_t)k * Pc + carry + pos] = Pg[(size_t)k * Pc + i];
         Ql[carry + pos] = Pl[i];
+        Qs[carry + pos] = Ps[i];
       }
       carry += tot;
     }
@@ -948,6 +991,7 @@ __global__ __launch_bounds__(NT_SLOT) void k_goal_merge(Slot* slots) {
   if (threadIdx.x == 0) {
     Sp->P_n = live;
     Sp->P_sel = sel;
+    Sp->P_seq = S.P_seq + na;
     if (live != n1) Sp->P_dead = 0;
     Sp->st[ST_PREAD] += (int64_t)np * ((ng + PCH - 1) / PCH);
     // goal labels the front already covers were not processed (lazy PruneOPEN)
@@ -983,8 +1027,10 @@ __device__ __forceinline__ int chunks_per_item(int nlt, int npc) {
 // The paper's PruneOPEN drops every open label whose F the goal front
 // dominates (Algorithm 1); here it is applied lazily to the
 // popped regular labels (weak dominance), after this step's goal labels were
-// merged into the front.  A dropped label is not expanded.  Work items are
-// (label tile, front chunk) pairs.
+// merged into the front.  A dropped label is not expanded.  A label was tested
+// against the whole front when it was inserted (k_pfilter), so only the
+// entries appended since then (a suffix of P, found by the append numbers)
+// can dominate it now.  Work items are (label tile, run of front chunks).
 template <int DM>
 __global__ __launch_bounds__(NT_TILE) void k_popcheck(Slot* slots, GraphDev G) {
   Slot* Sp = &slots[blockIdx.y];
@@ -998,8 +1044,10 @@ __global__ __launch_bounds__(NT_TILE) void k_popcheck(Slot* slots, GraphDev G) {
   if ((int)blockIdx.x >= ntiles) return;
   constexpr int NW = FrontChunk<DM>::NW;
   __shared__ FrontChunk<DM> ch;
+  __shared__ int sh_seq, sh_first;
   const int d = S.d, pc = S.pool_cap, Pc = S.P_cap, n = G.n;
   const int32_t* Pg = pick(S.Pg, S.P_sel);
+  const int32_t* Ps = pick(S.Pseq, S.P_sel);
   int killed = 0;
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const int lt = t / ngrp, gi = t - lt * ngrp;
@@ -1009,17 +1057,35 @@ __global__ __launch_bounds__(NT_TILE) void k_popcheck(Slot* slots, GraphDev G) {
     int32_t f[NW * 4];
 #pragma unroll
     for (int k = 0; k < NW * 4; ++k) f[k] = 0;
+    __syncthreads();  // the previous item is done with sh_first
+    if (threadIdx.x == 0) sh_seq = INT32_MAX;
+    __syncthreads();
+    int seq = INT32_MAX;
     if (have) {
       lab = S.reg[i];
+      seq = S.Lpseq[lab];
       const int v = S.Lnode[lab];
 #pragma unroll
       for (int k = 0; k < NW * 4; ++k)
         f[k] = k < d ? S.Lg[(size_t)k * pc + lab] + S.h[(size_t)k * n + v] : 0;
     }
+    seq = wave_min(seq);
+    if (lane_id() == 0) atomicMin(&sh_seq, seq);
+    __syncthreads();
+    if (threadIdx.x == 0) {  // first entry appended at or after the tile's earliest mark
+      int lo_i = 0, hi_i = np;
+      while (lo_i < hi_i) {
+        const int mid = (lo_i + hi_i) >> 1;
+        if (Ps[mid] < sh_seq) lo_i = mid + 1; else hi_i = mid;
+      }
+      sh_first = lo_i;
+    }
+    __syncthreads();
     int4 F[NW];
 #pragma unroll
     for (int w = 0; w < NW; ++w) F[w] = make_int4(f[4 * w], f[4 * w + 1], f[4 * w + 2], f[4 * w + 3]);
-    const bool dom = tile_vs_front<DM>(ch, Pg, Pc, np, d, gi * cpi, min(npc, (gi + 1) * cpi), have, F);
+    const int c0 = max(gi * cpi, sh_first / PCH), c1 = min(npc, (gi + 1) * cpi);
+    const bool dom = c0 < c1 && tile_vs_front<DM>(ch, Pg, Pc, np, d, c0, c1, have, F);
     if (have && dom && atomicExch(&S.reg_kill[i], 1) == 0) {
       S.Lstate[lab] = L_DEAD;
       ++killed;
@@ -1768,6 +1834,7 @@ __global__ __launch_bounds__(NT_TILE) void k_insert(Slot* slots, GraphDev G) {
     S.Lpar[id] = S.c_par[f];
     S.Larc[id] = S.c_arc[f];
     S.Lstate[id] = L_OPEN;
+    S.Lpseq[id] = S.P_seq;  // k_pfilter tests it against every entry appended so far
     FOR_K(k) S.Lg[(size_t)k * pc + id] = S.c_g[(size_t)k * cc + f];
     S.fw[S.c_fslot[f]] = id;
     const int f1 = S.c_g[f] + S.h[v];
