@@ -18,8 +18,20 @@ def mos():
 
 def _front(mos, g, s, t, d=None, **kw):
     G = mos.Graph.from_gen(g)
+    kw.setdefault("mem_budget", 4 << 30)  # a small arena: these instances are small
     r = mos.mos_solve(G, s, t, n_objectives=d or 0, **kw)
     return r
+
+
+def _fronts(mos, g, pairs, **kw):
+    """Several queries on one graph through one batched call (one engine)."""
+    G = mos.Graph.from_gen(g)
+    kw.setdefault("mem_budget", 4 << 30)
+    S = np.array([p[0] for p in pairs], dtype=np.int32)
+    T = np.array([p[1] for p in pairs], dtype=np.int32)
+    res = mos.mos_solve_batch(G, S, T, **kw)
+    assert all(st == mos.MOS_OK for st, _ in res)
+    return [r for _, r in res]
 
 
 @pytest.mark.parametrize("seed", [0, 1])
@@ -61,6 +73,38 @@ def test_tiny_random_graphs(mos, seed):
         assert ref.status == "ok"
         assert np.array_equal(r.costs.astype(np.int64), ref.costs), (seed, s, t)
         check_paths(g, s, t, r.costs, r.paths, d)
+
+
+@pytest.mark.parametrize("d", [5, 6, 7, 8])
+def test_many_objectives(mos, d):
+    """The kernels built for 6 and 8 objectives (two int4 words per vector):
+    tiny random multigraphs and a 6x6 grid with d objectives."""
+    for seed in range(4):
+        g = gen.random_small(9, 26, d, seed=100 + 10 * d + seed)
+        pairs = [(0, 8), (2, 7)]
+        for (s, t), r in zip(pairs, _fronts(mos, g, pairs, batch_width=3)):
+            ref = oracle.solve(g, s, t)
+            assert np.array_equal(r.costs.astype(np.int64), ref.costs), (d, seed, s, t)
+            check_paths(g, s, t, r.costs, r.paths, d)
+    g = gen.grid_uniform(6, 6, d, 1, 10, seed=d)
+    r = _front(mos, g, 0, g.n - 1, batch_width=64)
+    ref = oracle.solve(g, 0, g.n - 1)
+    assert np.array_equal(r.costs.astype(np.int64), ref.costs)
+    check_paths(g, 0, g.n - 1, r.costs, r.paths, d)
+
+
+@pytest.mark.parametrize("B", [1, 2, 5, 33])
+def test_random_multigraphs(mos, B):
+    """Random multigraphs with zero-cost arcs, self-loops and parallel arcs,
+    d in 1..4, several start/goal pairs each, at small batch widths."""
+    for seed in range(15):
+        d = 1 + seed % 4
+        g = gen.random_small(11, 34, d, seed=500 + seed)
+        pairs = [(0, 10), (4, 4), (7, 2), (1, 9)]
+        for (s, t), r in zip(pairs, _fronts(mos, g, pairs, batch_width=B)):
+            ref = oracle.solve(g, s, t)
+            assert np.array_equal(r.costs.astype(np.int64), ref.costs), (B, seed, s, t)
+            check_paths(g, s, t, r.costs, r.paths, d)
 
 
 @pytest.mark.parametrize("seed", [0, 1, 2])
