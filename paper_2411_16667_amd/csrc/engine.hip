@@ -748,6 +748,10 @@ class Engine {
     a.G = g_->view();
     a.nslots = S_;
     a.gx = gx_;
+    {
+      const int64_t cand = (int64_t)std::min(2 * B_, BATCH_MAX) * std::max(1, g_->maxdeg);
+      a.gc = (int)std::max<int64_t>(1, std::min<int64_t>(gx_, (cand + 255) / 256));
+    }
     a.dm = DM_;
     return a;
   }

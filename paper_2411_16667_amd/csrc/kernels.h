@@ -13,6 +13,7 @@ struct StepArgs {
   GraphDev G;
   int nslots;
   int gx;  // workgroups per slot of the tiled kernels
+  int gc;  // workgroups per slot of the per-candidate kernels (enough for one candidate per thread)
   int dm;  // compile-time bound on the objectives of every slot (2,3,4,5,6,8)
 };
 

@@ -1878,14 +1878,16 @@ const char* const kStepKernelNames[kStepKernels] = {
 template <int DM>
 static void launch_step_dm(const StepArgs& a, hipStream_t st, hipEvent_t* ev, uint32_t mask) {
   const dim3 tiled(a.gx, a.nslots), per(a.nslots);
+  const dim3 cand(a.gc, a.nslots);                    // per-candidate loops
+  const dim3 refill(std::min(a.gx, 256), a.nslots);   // far-tier kernels: idle on most steps
   int i = 0;
   auto mark = [&]() {
     const bool need = i == kStepKernels || ((mask >> i) & 1u) || (i > 0 && ((mask >> (i - 1)) & 1u));
     if (ev && need) hipEventRecord(ev[i], st);
     ++i;
   };
-  mark(); hipLaunchKernelGGL(k_far_hist, tiled, dim3(NT_TILE), 0, st, a.slots, a.hist);
-  mark(); hipLaunchKernelGGL(k_far_move, tiled, dim3(NT_TILE), 0, st, a.slots);
+  mark(); hipLaunchKernelGGL(k_far_hist, refill, dim3(NT_TILE), 0, st, a.slots, a.hist);
+  mark(); hipLaunchKernelGGL(k_far_move, refill, dim3(NT_TILE), 0, st, a.slots);
   mark(); hipLaunchKernelGGL(k_open_hist, tiled, dim3(NT_TILE), 0, st, a.slots, a.hist);
   mark(); hipLaunchKernelGGL(k_open_threshold, per, dim3(NT_SLOT), 0, st, a.slots, a.hist);
   mark(); hipLaunchKernelGGL(k_open_scatter, tiled, dim3(NT_TILE), 0, st, a.slots);
@@ -1893,15 +1895,15 @@ static void launch_step_dm(const StepArgs& a, hipStream_t st, hipEvent_t* ev, ui
   mark(); hipLaunchKernelGGL(k_goal_pairs<DM>, tiled, dim3(NT_TILE), 0, st, a.slots);
   mark(); hipLaunchKernelGGL(k_goal_merge<DM>, per, dim3(NT_SLOT), 0, st, a.slots);
   mark(); hipLaunchKernelGGL(k_popcheck<DM>, tiled, dim3(NT_TILE), 0, st, a.slots, a.G);
-  mark(); hipLaunchKernelGGL(k_expand<DM>, tiled, dim3(NT_TILE), 0, st, a.slots, a.G);
-  mark(); hipLaunchKernelGGL(k_group_count, tiled, dim3(NT_TILE), 0, st, a.slots);
+  mark(); hipLaunchKernelGGL(k_expand<DM>, cand, dim3(NT_TILE), 0, st, a.slots, a.G);
+  mark(); hipLaunchKernelGGL(k_group_count, cand, dim3(NT_TILE), 0, st, a.slots);
   mark(); hipLaunchKernelGGL(k_group_offsets, per, dim3(NT_SLOT), 0, st, a.slots);
-  mark(); hipLaunchKernelGGL(k_group_scatter, tiled, dim3(NT_TILE), 0, st, a.slots);
+  mark(); hipLaunchKernelGGL(k_group_scatter, cand, dim3(NT_TILE), 0, st, a.slots);
   mark(); hipLaunchKernelGGL(k_group_process<DM>, tiled, dim3(NT_TILE), 0, st, a.slots);
   mark(); hipLaunchKernelGGL(k_group_pairs<DM>, tiled, dim3(NT_TILE), 0, st, a.slots);
   mark(); hipLaunchKernelGGL(k_group_finish<DM>, tiled, dim3(NT_TILE), 0, st, a.slots);
   mark(); hipLaunchKernelGGL(k_accept_scan, per, dim3(NT_SLOT), 0, st, a.slots);
-  mark(); hipLaunchKernelGGL(k_insert<DM>, tiled, dim3(NT_TILE), 0, st, a.slots, a.G);
+  mark(); hipLaunchKernelGGL(k_insert<DM>, cand, dim3(NT_TILE), 0, st, a.slots, a.G);
   mark(); hipLaunchKernelGGL(k_pfilter<DM>, tiled, dim3(NT_TILE), 0, st, a.slots, a.G);
   mark(); hipLaunchKernelGGL(k_step_end, dim3((a.nslots + 63) / 64), dim3(64), 0, st, a.slots, a.nslots);
   mark();
