@@ -5,7 +5,11 @@ paper comes from this script, which calls only ``oracle`` (sequential NAMOA*)
 and the seeded input generators ``gen``.
 
 Usage:  python tests/golden/make_golden.py NAME [--time-limit S]
-NAME is one of: c1_s<seed>, ship<size>, c2, c3, c4_<first>_<count>
+NAME is one of: c1_s<seed>, c1_all, ship<size>, c2, c3, c4_<first>_<count>, c4mid
+  c1_all   the 32x32 grid query for seeds 0..31 (c1/s<seed>.txt.gz)
+  c4mid    20 queries on the 256x256 ship grid with Manhattan distance in
+           [60, 120] (query seed 99); the ones the oracle finishes within the
+           time limit (default 10 s) are written to c4mid/q<i>.txt.gz
 """
 from __future__ import annotations
 
@@ -74,6 +78,29 @@ def main():
         g, s, t = gen.config1(seed)
         h, c = solve_one(name, g, s, t, 3, a.time_limit)
         write_front(os.path.join(HERE, f"{name}.txt"), h, c)
+    elif name == "c1_all":
+        os.makedirs(os.path.join(HERE, "c1"), exist_ok=True)
+        for seed in range(32):
+            g, s, t = gen.config1(seed)
+            h, c = solve_one(f"c1_s{seed}", g, s, t, 3, a.time_limit)
+            write_front(os.path.join(HERE, "c1", f"s{seed:02d}.txt.gz"), h, c)
+            print(seed, h["front"], h["search_seconds"], flush=True)
+    elif name == "c4mid":
+        os.makedirs(os.path.join(HERE, "c4mid"), exist_ok=True)
+        g = gen.ship_grid(256, 256, 3, 0)
+        S, T = gen.ship_queries(256, 256, 20, seed=99, dmin=60, dmax=120)
+        limit = a.time_limit or 10.0
+        for q in range(20):
+            r = oracle.solve(g, int(S[q]), int(T[q]), 3, flags=FLAGS, time_limit=limit)
+            if r.status != "ok":
+                print(q, r.status, flush=True)
+                continue
+            h = {"workload": f"c4mid_q{q}", "graph": g.name, "graph_sha256_16": g.digest(),
+                 "start": int(S[q]), "goal": int(T[q]), "d": 3, "oracle_flags": FLAGS,
+                 "front": r.stats["front"], "pops": r.stats["pops"],
+                 "search_seconds": round(r.stats["search_seconds"], 3)}
+            write_front(os.path.join(HERE, "c4mid", f"q{q:02d}.txt.gz"), h, r.costs)
+            print(q, h["front"], h["search_seconds"], flush=True)
     elif name.startswith("ship"):
         size = int(name[4:])
         g, s, t = gen.config2(0, size=size)

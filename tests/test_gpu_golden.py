@@ -1,0 +1,61 @@
+"""GPU fronts against stored oracle fronts (written by tests/golden/make_golden.py,
+which calls only the oracle): the 32x32 grid query for all 32 seeds, and the
+mid-range ship-grid queries the oracle finishes within its time limit."""
+import glob
+import importlib.util
+import os
+
+import numpy as np
+import pytest
+
+import gen
+from helpers import check_paths
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _read_front():
+    spec = importlib.util.spec_from_file_location("make_golden", os.path.join(HERE, "make_golden.py"))
+    m = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(m)
+    return m.read_front
+
+
+@pytest.fixture(scope="module")
+def mos():
+    import paper_2411_16667_amd as m
+
+    return m
+
+
+def test_c1_all_seeds(mos):
+    read_front = _read_front()
+    files = sorted(glob.glob(os.path.join(HERE, "c1", "s*.txt.gz")))
+    assert len(files) == 32
+    for f in files:
+        h, costs = read_front(f)
+        seed = int(os.path.basename(f)[1:3])
+        g, s, t = gen.config1(seed)
+        assert h["graph_sha256_16"] == g.digest() and int(h["start"]) == s and int(h["goal"]) == t
+        r = mos.mos_solve(mos.Graph.from_gen(g), s, t, batch_width=512, mem_budget=2 << 30)
+        assert np.array_equal(r.costs.astype(np.int64), costs), seed
+        check_paths(g, s, t, r.costs, r.paths, 3)
+
+
+def test_ship_grid_mid_range(mos):
+    read_front = _read_front()
+    files = sorted(glob.glob(os.path.join(HERE, "c4mid", "q*.txt.gz")))
+    assert len(files) >= 8
+    g = gen.ship_grid(256, 256, 3, 0)
+    fronts = [read_front(f) for f in files]
+    assert all(h["graph_sha256_16"] == g.digest() for h, _ in fronts)
+    S = np.array([int(h["start"]) for h, _ in fronts], dtype=np.int32)
+    T = np.array([int(h["goal"]) for h, _ in fronts], dtype=np.int32)
+    res = mos.mos_solve_batch(mos.Graph.from_gen(g), S, T, batch_width=1024, max_slots=8,
+                              mem_budget=16 << 30)
+    for (h, costs), (st, r), s, t in zip(fronts, res, S, T):
+        assert st == mos.MOS_OK, h["workload"]
+        assert np.array_equal(r.costs.astype(np.int64), costs), h["workload"]
+        check_paths(g, int(s), int(t), r.costs, r.paths, 3)
