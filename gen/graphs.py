@@ -395,3 +395,137 @@ def overflow_bound_ok(g: Graph) -> bool:
     """2 * sum_e c_k(e) + max_e c_k(e) < INT32_MAX for every objective k."""
     c = g.cost.astype(np.int64)
     return bool(np.all(2 * c.sum(0) + c.max(0, initial=0) < INT32_MAX))
+
+
+# --------------------------------------------------------------------------
+# Time-expanded ship routes with up to 12 objectives (Tables 1-2 shapes)
+# --------------------------------------------------------------------------
+
+# Spatial corridors (cells along the route x cells across) sized so that, with
+# 10 time windows per cell and one goal sink, the node counts are close to the
+# five routes of Table 2 (201 to 1,610 nodes).
+ROUTE_SHAPES = {1: (16, 3), 2: (40, 4), 3: (23, 2), 4: (10, 2), 5: (26, 3)}
+
+
+def wave_fields(length: int, width: int, windows: int, rng, n_bumps: int = 6):
+    """Three time-varying fields over the corridor, each in [0, 1]: wave height,
+    wave period and wave direction (as a fraction of a full turn).
+
+    Each field is a sum of Gaussian bumps drifting with constant velocity.
+    Draw order per field: centres (n_bumps, 2) as [along, across] with along
+    U[0, length) and across U[0, width); velocities (n_bumps, 2) U[-1, 1] cells
+    per window; widths U[1, 0.5 * length + 1]; amplitudes U[0.5, 1.5].  The
+    field is min-max normalised over all (cell, window) points.
+    Returns float64[3, windows, length * width] (cell id = along * width + across)."""
+    a, c = np.meshgrid(np.arange(length, dtype=np.float64),
+                       np.arange(width, dtype=np.float64), indexing="ij")
+    a, c = a.ravel(), c.ravel()
+    out = np.empty((3, windows, length * width))
+    for f in range(3):
+        mu = rng.uniform(0.0, 1.0, size=(n_bumps, 2)) * np.array([length, width])
+        vel = rng.uniform(-1.0, 1.0, size=(n_bumps, 2))
+        sig = rng.uniform(1.0, 0.5 * length + 1.0, size=n_bumps)
+        amp = rng.uniform(0.5, 1.5, size=n_bumps)
+        for t in range(windows):
+            v = np.zeros(length * width)
+            for b in range(n_bumps):
+                ca, cc = mu[b] + t * vel[b]
+                v += amp[b] * np.exp(-((a - ca) ** 2 + (c - cc) ** 2) / (2.0 * sig[b] ** 2))
+            out[f, t] = v
+        lo, hi = out[f].min(), out[f].max()
+        out[f] = (out[f] - lo) / (hi - lo) if hi > lo else 0.0
+    return out
+
+
+def time_expanded_route(length: int, width: int, d: int = 12, seed: int = 0,
+                        windows: int = 10) -> tuple[Graph, int, int]:
+    """Directed spatio-temporal ship-routing graph with d <= 12 objectives.
+
+    The spatial part is a corridor of length x width cells from an origin cell
+    (along 0, middle column) to a destination cell (along length-1, middle
+    column); every cell is expanded into `windows` time windows (Section 6.1
+    expands each node into 10).  Node (cell, window) has id cell * windows +
+    window; the last id is a goal sink.  From (u, t) there is an arc to (v, t)
+    (fast passage) and, if t + 1 < windows, to (v, t + 1) (slow passage), for
+    every cell v that is an 8-neighbour of u not behind it along the corridor
+    (same or next along index).  Every (destination, t) has a zero-cost arc to
+    the sink.  The start is (origin, window 0), the goal the sink.
+
+    Objectives follow the order of Table 1 (the first d are kept): distance,
+    fuel, roll, pitch, vertical acceleration, horizontal acceleration,
+    vertical bending moment, vertical shear force, wave height, wave period,
+    relative wave bearing, random.  With len in {1, sqrt 2}, H, P, W the wave
+    height, period and direction fields averaged over the arc's two cells at
+    the departure window, r = |cos(2 pi W - bearing)| the relative bearing,
+    s = 2 for a fast and 1 for a slow passage:
+      distance  rint(100 len)
+      fuel      rint(100 len s (1 + H r))
+      roll      rint(100 len (0.2 + H (1 - r) + 0.3 P))
+      pitch     rint(100 len (0.2 + H r + 0.3 (1 - P)))
+      vert acc  rint(100 len (0.1 + s H (0.5 + 0.5 r)))
+      horz acc  rint(100 len (0.1 + s H (1 - 0.5 r)))
+      VBM       rint(100 len (0.1 + H (1 - P) + 0.2 s))
+      VSF       rint(100 len (0.1 + H P + 0.1 s r))
+      wave hgt  rint(100 len H)
+      wave per  rint(100 len P)
+      rel bear  rint(100 len r)
+      random    U{0..100} per arc (drawn in arc order)
+    Draw order: the three fields (``wave_fields``), then the random objective.
+    Returns (graph, start, goal)."""
+    if not 1 <= d <= 12:
+        raise ValueError("d must lie in [1, 12]")
+    rng = np.random.default_rng(seed)
+    H, P, W = wave_fields(length, width, windows, rng)
+    ncell = length * width
+    src_c, dst_c, dlen, bear = [], [], [], []
+    for i in range(length):
+        for j in range(width):
+            for di in (0, 1):
+                for dj in (-1, 0, 1):
+                    if di == 0 and dj == 0:
+                        continue
+                    i2, j2 = i + di, j + dj
+                    if i2 >= length or not 0 <= j2 < width:
+                        continue
+                    src_c.append(i * width + j)
+                    dst_c.append(i2 * width + j2)
+                    dlen.append(np.hypot(di, dj))
+                    bear.append(np.arctan2(dj, di))
+    src_c, dst_c = np.array(src_c), np.array(dst_c)
+    dlen, bear = np.array(dlen), np.array(bear)
+    src, dst, cols = [], [], []
+    for t in range(windows):
+        h = 0.5 * (H[t, src_c] + H[t, dst_c])
+        p = 0.5 * (P[t, src_c] + P[t, dst_c])
+        r = np.abs(np.cos(2.0 * np.pi * 0.5 * (W[t, src_c] + W[t, dst_c]) - bear))
+        for t2, s in ((t, 2.0), (t + 1, 1.0)):
+            if t2 >= windows:
+                continue
+            L = 100.0 * dlen
+            c = np.stack([
+                L, L * s * (1 + h * r), L * (0.2 + h * (1 - r) + 0.3 * p),
+                L * (0.2 + h * r + 0.3 * (1 - p)), L * (0.1 + s * h * (0.5 + 0.5 * r)),
+                L * (0.1 + s * h * (1 - 0.5 * r)), L * (0.1 + h * (1 - p) + 0.2 * s),
+                L * (0.1 + h * p + 0.1 * s * r), L * h, L * p, L * r,
+                np.zeros_like(L)], axis=1)
+            src.append(src_c * windows + t)
+            dst.append(dst_c * windows + t2)
+            cols.append(c)
+    sink = ncell * windows
+    dest_cell = (length - 1) * width + width // 2
+    src.append(dest_cell * windows + np.arange(windows))
+    dst.append(np.full(windows, sink))
+    cols.append(np.zeros((windows, 12)))
+    src, dst = np.concatenate(src), np.concatenate(dst)
+    cost = np.rint(np.concatenate(cols))
+    cost[: -windows, 11] = rng.integers(0, 101, size=src.size - windows)
+    start = (width // 2) * windows
+    g = from_arcs(sink + 1, src, dst, cost[:, :d].astype(np.int64),
+                  name=f"route{length}x{width}x{windows}_d{d}_s{seed}")
+    return g, int(start), int(sink)
+
+
+def tmplar_route(route: int, d: int = 12, seed: int = 0):
+    """A time-expanded route shaped like route `route` (1..5) of Table 2."""
+    length, width = ROUTE_SHAPES[route]
+    return time_expanded_route(length, width, d, seed)

@@ -40,7 +40,7 @@ extern "C" {
 #endif
 
 #define MOS_ABI_VERSION 1
-#define MOS_MAX_OBJECTIVES 8 /* largest D accepted by mos_graph_create */
+#define MOS_MAX_OBJECTIVES 12 /* largest D accepted by mos_graph_create */
 
 typedef struct mos_graph mos_graph;
 typedef struct mos_result mos_result;

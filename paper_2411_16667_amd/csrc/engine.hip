@@ -1026,7 +1026,7 @@ mos_status mos_graph_create(int32_t n, int64_t m, int32_t D, const int64_t* row_
   if (!out) return set_err(MOS_E_INVALID_ARG, "out is NULL");
   if (n < 1 || m < 0 || m >= ((int64_t)1 << 31) - 1)
     return set_err(MOS_E_INVALID_ARG, "n_nodes must be >= 1 and n_arcs in [0, 2^31-1)");
-  if (D < 1 || D > MOS_MAX_OBJECTIVES) return set_err(MOS_E_INVALID_ARG, "D must lie in [1, 8]");
+  if (D < 1 || D > MOS_MAX_OBJECTIVES) return set_err(MOS_E_INVALID_ARG, "D must lie in [1, 12]");
   if (!row_ptr || (m > 0 && (!col || !cost))) return set_err(MOS_E_INVALID_ARG, "NULL array");
   if (row_ptr[0] != 0 || row_ptr[n] != m) return set_err(MOS_E_INVALID_ARG, "row_ptr ends");
   int32_t maxdeg = 0;

@@ -13,7 +13,7 @@
 
 namespace mos {
 
-constexpr int MAXD = 8;           // objectives supported by the kernels
+constexpr int MAXD = 12;          // objectives supported by the kernels
 constexpr int NB = 4096;          // OPEN histogram bins: exact F1 values lo..lo+NB-2, then overflow
 constexpr int TIECAP = 256;       // tie sets up to this size are ranked in LDS; larger ones
                                   // are first narrowed by exact radix refinement

@@ -1915,7 +1915,8 @@ int dm_for(int d) {
   if (d <= 4) return 4;
   if (d <= 5) return 5;
   if (d <= 6) return 6;
-  return 8;
+  if (d <= 8) return 8;
+  return 12;
 }
 
 void launch_step(const StepArgs& a, hipStream_t st, hipEvent_t* ev, uint32_t mask) {
@@ -1925,7 +1926,8 @@ void launch_step(const StepArgs& a, hipStream_t st, hipEvent_t* ev, uint32_t mas
     case 4: launch_step_dm<4>(a, st, ev, mask); break;
     case 5: launch_step_dm<5>(a, st, ev, mask); break;
     case 6: launch_step_dm<6>(a, st, ev, mask); break;
-    default: launch_step_dm<8>(a, st, ev, mask); break;
+    case 8: launch_step_dm<8>(a, st, ev, mask); break;
+    default: launch_step_dm<12>(a, st, ev, mask); break;
   }
 }
 

@@ -59,7 +59,7 @@ def test_validation_precedes_device(mos):
     rp = g.row_ptr.copy(); rp[-1] -= 1
     assert _create(mos, g.n, rp, g.col, g.cost, 3)[0] == mos.MOS_E_INVALID_ARG
     # D out of range
-    assert _create(mos, g.n, g.row_ptr, g.col, np.zeros((g.n_arcs, 9)), 9)[0] == mos.MOS_E_INVALID_ARG
+    assert _create(mos, g.n, g.row_ptr, g.col, np.zeros((g.n_arcs, 13)), 13)[0] == mos.MOS_E_INVALID_ARG
     # NULL out-parameter
     assert mos.raw.mos_graph_create(1, 0, 1, np.zeros(2, np.int64).ctypes.data_as(
         ctypes.POINTER(ctypes.c_int64)), None, None, None) == mos.MOS_E_INVALID_ARG

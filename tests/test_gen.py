@@ -63,3 +63,44 @@ def test_local_queries_stay_within_radius():
     assert set(np.unique(D)) <= {3, 4, 5}
     S2, T2, D2 = gen.local_queries(g, comp, 200, seed=3, radius=0.05)
     assert np.array_equal(S, S2) and np.array_equal(T, T2) and np.array_equal(D, D2)
+
+
+def test_time_expanded_route_structure():
+    L, W, T = 6, 3, 4
+    g, s, t = gen.time_expanded_route(L, W, 12, seed=3, windows=T)
+    assert g.n == L * W * T + 1 and t == g.n - 1 and s == (W // 2) * T
+    src = g.arc_sources()
+    sink_arcs = g.col == t
+    # arcs into the sink: one per window of the destination cell, zero cost
+    dest = (L - 1) * W + W // 2
+    assert np.array_equal(np.sort(src[sink_arcs]), dest * T + np.arange(T))
+    assert not g.cost[sink_arcs].any()
+    # other arcs: same or next window, same or next along index, at most one across step
+    a, b = src[~sink_arcs], g.col[~sink_arcs]
+    (ca, ta), (cb, tb) = np.divmod(a, T), np.divmod(b, T)
+    assert np.all((tb == ta) | (tb == ta + 1))
+    ia, ja = np.divmod(ca, W)
+    ib, jb = np.divmod(cb, W)
+    assert np.all((ib - ia >= 0) & (ib - ia <= 1) & (np.abs(jb - ja) <= 1) & (ca != cb))
+    c = g.cost[~sink_arcs]
+    assert np.all(c[:, 0] > 0) and np.all(c >= 0) and c[:, 11].max() <= 100
+    # a fast passage (same window) has the slow one's distance and about twice its fuel
+    fast = {(x, y, w): k for k, (x, y, w, w2) in enumerate(zip(ca, cb, ta, tb)) if w2 == w}
+    n_pairs = 0
+    for k, (x, y, w, w2) in enumerate(zip(ca, cb, ta, tb)):
+        if w2 == w + 1:
+            f = fast[(x, y, w)]
+            assert c[f, 0] == c[k, 0] and abs(int(c[f, 1]) - 2 * int(c[k, 1])) <= 1
+            n_pairs += 1
+    assert n_pairs == np.count_nonzero(tb == ta + 1) > 0
+    assert gen.overflow_bound_ok(g)
+    # the first d objectives of the d=12 graph are the d-objective graph
+    g4, _, _ = gen.time_expanded_route(L, W, 4, seed=3, windows=T)
+    assert np.array_equal(g4.cost, g.cost[:, :4]) and np.array_equal(g4.col, g.col)
+
+
+def test_tmplar_route_node_counts():
+    # node counts of Table 2's five routes: 471, 1610, 461, 201, 778
+    for r, n in [(1, 471), (2, 1610), (3, 461), (4, 201), (5, 778)]:
+        g, s, t = gen.tmplar_route(r, 3, 0)
+        assert abs(g.n - n) <= 0.03 * n

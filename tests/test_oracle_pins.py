@@ -256,3 +256,28 @@ def test_heuristic_is_reverse_dijkstra():
     g2 = gen.from_arcs(3, [0, 1], [1, 2], np.ones((2, 1), dtype=np.int64))
     h2 = oracle.heuristic(g2, 0)
     assert h2[0, 0] == 0 and h2[0, 1] == oracle.INF and h2[0, 2] == oracle.INF
+
+
+@pytest.mark.parametrize("shape,d,seed", [((3, 2, 3), 12, 1), ((2, 3, 3), 11, 2), ((4, 2, 2), 10, 3),
+                                          ((3, 3, 2), 9, 4), ((5, 2, 2), 12, 5), ((3, 2, 3), 7, 6)])
+def test_brute_force_time_expanded(shape, d, seed):
+    """Up to 12 objectives on tiny time-expanded routes (directed, zero-cost
+    sink arcs, sideways cycles inside a window)."""
+    length, width, windows = shape
+    g, s, t = gen.time_expanded_route(length, width, d, seed=seed, windows=windows)
+    ref = brute_front(g, s, t, d)
+    for mode in MODES:
+        r = oracle.solve(g, s, t, d, flags=mode)
+        assert r.status == "ok"
+        assert np.array_equal(r.costs, ref), mode
+        check_paths(g, s, t, r.costs, r.paths, d)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_brute_force_random_high_d(seed):
+    d = 9 + seed % 4
+    g = gen.random_small(7, 18, d, seed=100 + seed, cmax=9)
+    for s, t in [(0, 6), (3, 1)]:
+        ref = brute_front(g, s, t, d)
+        r = oracle.solve(g, s, t, d)
+        assert np.array_equal(r.costs, ref), (seed, s, t)
