@@ -19,7 +19,9 @@ against a loop of single solves on short-range queries of the same grid.
 
 `--workload served` instead runs the request loop on the 1M-node road-like
 graph (saturation and Poisson arrivals, p50/p99 latency) and prints its own
-JSON line.
+JSON line; `--workload routes` solves the five time-expanded ship routes
+shaped like the paper's Table 2 at that table's largest objective counts (up
+to 12), whole queries, and prints its own JSON line.
 """
 from __future__ import annotations
 
@@ -57,9 +59,15 @@ def parse():
                     help="Manhattan distance range of those queries")
     ap.add_argument("--query-width", type=int, default=256,
                     help="batch width B of every query in that comparison")
-    ap.add_argument("--workload", choices=("steps", "served"), default="steps",
+    ap.add_argument("--workload", choices=("steps", "served", "routes"), default="steps",
                     help="steps: label steps of the ship-routing query (the headline line); "
-                         "served: the request loop on the 1M-node road-like graph")
+                         "served: the request loop on the 1M-node road-like graph; "
+                         "routes: whole queries on the time-expanded routes at up to 12 "
+                         "objectives")
+    ap.add_argument("--route-width", type=int, default=4096,
+                    help="routes workload: batch width B")
+    ap.add_argument("--route-repeats", type=int, default=3,
+                    help="routes workload: timed solves per route (the median is reported)")
     ap.add_argument("--served-queries", type=int, default=600,
                     help="queries per arrival-rate point of the served workload")
     ap.add_argument("--radius", type=float, default=0.02,
@@ -290,6 +298,90 @@ def served_bench(a):
     print(json.dumps(out))
 
 
+def routes_bench(a):
+    """Whole queries on the five time-expanded routes (Table 2 shapes), each at
+    Table 2's largest objective count for that route: one untimed solve, then
+    the median of --route-repeats timed solves (wall clock around mos_solve:
+    heuristic, search, harvest and paths).  The CPU baseline is the oracle on
+    the smallest route (whole query) and on a bounded sample of route 1."""
+    import gzip
+
+    import numpy as np
+
+    import gen
+    import paper_2411_16667_amd as mos
+
+    rows, tot_pairs, tot_s = [], 0, 0.0
+    for r in sorted(gen.ROUTE_SHAPES):
+        d = gen.ROUTE_MAX_OBJECTIVES[r]
+        g, s, t = gen.tmplar_route(r, 12, 0)
+        G = mos.Graph.from_gen(g)
+        kw = dict(n_objectives=d, batch_width=a.route_width)
+        res = mos.mos_solve(G, s, t, **kw)
+        walls = []
+        for _ in range(a.route_repeats):
+            t0 = time.perf_counter()
+            res = mos.mos_solve(G, s, t, **kw)
+            walls.append(time.perf_counter() - t0)
+        wall = float(np.median(walls))
+        st = res.stats
+        pairs = st["p_pairs"] + st["group_pairs"] + st["frontier_pairs"]
+        row = {"route": r, "nodes": g.n, "arcs": g.n_arcs, "d": d, "front": len(res.costs),
+               "seconds": wall, "search_ms": st["search_ms"], "heuristic_ms": st["heuristic_ms"],
+               "pops": st["pops"], "steps": st["steps"], "pairs": pairs, "checks_per_s": pairs / wall}
+        # the stored oracle front of this route, when there is one (tests/golden/routes)
+        ref = os.path.join(ROOT, "tests", "golden", "routes", f"r{r}.txt.gz")
+        if os.path.exists(ref):
+            hdr, rows_ref = {}, []
+            with gzip.open(ref, "rt") as f:
+                for line in f:
+                    if line.startswith("#"):
+                        k, _, v = line[1:].partition(":")
+                        hdr[k.strip()] = v.strip()
+                    elif line.strip():
+                        rows_ref.append([int(x) for x in line.split()])
+            row["same_front_as_stored_oracle"] = bool(
+                hdr.get("graph_sha256_16") == g.digest()
+                and np.array_equal(res.costs.astype(np.int64), np.array(rows_ref, np.int64).reshape(-1, d)))
+            row["oracle_pops"] = int(hdr["pops"])
+            row["oracle_seconds_when_stored"] = float(hdr["search_seconds"])
+        rows.append(row)
+        tot_pairs += pairs
+        tot_s += wall
+        print(f"routes: {row}", file=sys.stderr, flush=True)
+    out = {"metric": "dominance checks/s, whole queries, exact Pareto front, 1 GPU",
+           "value": tot_pairs / tot_s, "unit": "checks/s", "n_gpus": 1,
+           "higher_is_better": True, "dtype": "int32", "data": "synthetic",
+           "config": {"workload": "five time-expanded ship routes shaped like Table 2 "
+                                  "(10 time windows per cell), each at Table 2's largest "
+                                  "objective count (12, 4, 12, 12, 6)",
+                      "batch_width": a.route_width, "repeats": a.route_repeats},
+           "seconds_all_routes": tot_s, "routes": rows}
+    if a.cpu_seconds > 0:
+        import oracle
+
+        flags = oracle.WEAK_P | oracle.LAZY_PRUNEOPEN
+        base = []
+        for r, limit in ((4, a.cpu_seconds), (1, a.cpu_seconds)):
+            d = gen.ROUTE_MAX_OBJECTIVES[r]
+            g, s, t = gen.tmplar_route(r, 12, 0)
+            o = oracle.solve(g, s, t, d, flags=flags, time_limit=limit)
+            so = o.stats
+            pairs = so["frontier_pairs"] + so["p_pairs"]
+            base.append((r, o.status, so["search_seconds"], so["pops"], pairs))
+        pairs = sum(b[4] for b in base)
+        secs = max(sum(b[2] for b in base), 1e-9)
+        out["cpu_baseline"] = {
+            "value": pairs / secs, "unit": "checks/s", "cores": 1, "kind": "oracle",
+            "sample": "; ".join(f"route {r}: {'whole query' if stt == 'ok' else 'first'} "
+                                f"{sec:.1f} s, {pops} labels, {pr} pair checks"
+                                for r, stt, sec, pops, pr in base)}
+        r4 = next(b for b in base if b[0] == 4)
+        if r4[1] == "ok":
+            out["route4_speedup_vs_oracle"] = r4[2] / next(x for x in rows if x["route"] == 4)["seconds"]
+    print(json.dumps(out))
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -303,6 +395,9 @@ def main():
 
     if a.workload == "served":
         served_bench(a)
+        return
+    if a.workload == "routes":
+        routes_bench(a)
         return
     if a.copy_calibration > 0:
         import torch

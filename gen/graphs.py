@@ -405,6 +405,8 @@ def overflow_bound_ok(g: Graph) -> bool:
 # 10 time windows per cell and one goal sink, the node counts are close to the
 # five routes of Table 2 (201 to 1,610 nodes).
 ROUTE_SHAPES = {1: (16, 3), 2: (40, 4), 3: (23, 2), 4: (10, 2), 5: (26, 3)}
+# The largest objective count Table 2 reports for each route.
+ROUTE_MAX_OBJECTIVES = {1: 12, 2: 4, 3: 12, 4: 12, 5: 6}
 
 
 def wave_fields(length: int, width: int, windows: int, rng, n_bumps: int = 6):

@@ -1658,9 +1658,13 @@ __global__ __launch_bounds__(NT_TILE) void k_group_finish(Slot* slots) {
     if (!frontier_dest(Sp, S, nr, cnt + k, d, &doff, &dcap)) break;
     const bool moved = doff != nr.off;
     int cursor = 0, nlive = 0;  // nlive: entries the pair tiles compared
-    // label ids BT_U per lane at a time; the vectors are read only where the
-    // block has to be rewritten (it moved, or entries before were dropped)
-    constexpr int FU = 16;  // label ids per lane in flight
+    // label ids FU x 64 at a time; the vectors are read only where the block
+    // has to be rewritten (it moved, or entries before were dropped).  Every
+    // entry's destination lies at or before its own position, so within one
+    // block of ids all rewritten vectors of RU sub-chunks are loaded before
+    // any of them is stored (one memory round trip instead of RU).
+    constexpr int FU = 16;                                   // label ids per lane in flight
+    constexpr int RU = DM <= 3 ? 16 : (DM <= 6 ? 8 : 4);     // rewritten sub-chunks in flight
     for (int t0 = 0; t0 < cnt; t0 += FU * WAVE) {
       int slab[FU];
 #pragma unroll
@@ -1668,25 +1672,42 @@ __global__ __launch_bounds__(NT_TILE) void k_group_finish(Slot* slots) {
         const int e = t0 + u * WAVE + lane;
         slab[u] = e < cnt ? fw[nr.off + (int64_t)d * nr.cap + e] : 0;
       }
+      uint64_t am[FU];
+      int cur[FU];
+      uint32_t rw = 0;  // sub-chunks to rewrite (wave-uniform)
 #pragma unroll
       for (int u = 0; u < FU; ++u) {
         const int t = t0 + u * WAVE;
-        if (t >= cnt) break;
         const int e = t + lane;
         const bool has = e < cnt;
-        const bool keep = has && slab[u] >= 0;
         nlive += __popcll(ballot(has && slab[u] != FW_REMOVED));
-        const uint64_t hm = ballot(has), am = ballot(keep);
-        if (moved || cursor != t || am != hm) {
-          if (keep) {
-            int32_t sv[DM];
-            FOR_K(kk) sv[kk] = fw[nr.off + (int64_t)kk * nr.cap + e];
-            const int64_t w = doff + cursor + rank_below(am);
-            FOR_K(kk) fw[w + (int64_t)kk * dcap] = sv[kk];
-            fw[w + (int64_t)d * dcap] = slab[u];
+        const uint64_t hm = ballot(has);
+        am[u] = ballot(has && slab[u] >= 0);
+        cur[u] = cursor;
+        if (hm && (moved || cursor != t || am[u] != hm)) rw |= 1u << u;
+        cursor += __popcll(am[u]);
+      }
+      if (!rw) continue;
+#pragma unroll
+      for (int u0 = 0; u0 < FU; u0 += RU) {
+        int32_t sv[RU][DM];
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+          const int uu = u0 + u;
+          if (((rw >> uu) & 1) && ((am[uu] >> lane) & 1)) {
+            const int e = t0 + uu * WAVE + lane;
+            FOR_K(kk) sv[u][kk] = fw[nr.off + (int64_t)kk * nr.cap + e];
           }
         }
-        cursor += __popcll(am);
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+          const int uu = u0 + u;
+          if (((rw >> uu) & 1) && ((am[uu] >> lane) & 1)) {
+            const int64_t w = doff + cur[uu] + rank_below(am[uu]);
+            FOR_K(kk) fw[w + (int64_t)kk * dcap] = sv[u][kk];
+            fw[w + (int64_t)d * dcap] = slab[uu];
+          }
+        }
       }
     }
     fpairs += (int64_t)k * nlive;

@@ -5,11 +5,13 @@ paper comes from this script, which calls only ``oracle`` (sequential NAMOA*)
 and the seeded input generators ``gen``.
 
 Usage:  python tests/golden/make_golden.py NAME [--time-limit S]
-NAME is one of: c1_s<seed>, c1_all, ship<size>, c2, c3, c4_<first>_<count>, c4mid
+NAME is one of: c1_s<seed>, c1_all, ship<size>, c2, c3, c4_<first>_<count>, c4mid, route<r>
   c1_all   the 32x32 grid query for seeds 0..31 (c1/s<seed>.txt.gz)
   c4mid    20 queries on the 256x256 ship grid with Manhattan distance in
            [60, 120] (query seed 99); the ones the oracle finishes within the
            time limit (default 10 s) are written to c4mid/q<i>.txt.gz
+  route<r> the time-expanded route r (1..5) shaped like Table 2's route r, at
+           that route's largest objective count in Table 2 (routes/r<r>.txt.gz)
 """
 from __future__ import annotations
 
@@ -121,6 +123,14 @@ def main():
             h, c = solve_one(f"c4_q{q}", g, int(S[q]), int(T[q]), 3, a.time_limit)
             write_front(os.path.join(HERE, "c4", f"q{q:03d}.txt"), h, c)
             print(q, h["front"], h["search_seconds"], flush=True)
+    elif name.startswith("route"):
+        r = int(name[5:])
+        d = gen.ROUTE_MAX_OBJECTIVES[r]
+        g, s, t = gen.tmplar_route(r, 12, 0)
+        h, c = solve_one(f"route{r}_d{d}", g, s, t, d, a.time_limit)
+        os.makedirs(os.path.join(HERE, "routes"), exist_ok=True)
+        write_front(os.path.join(HERE, "routes", f"r{r}.txt.gz"), h, c)
+        print(r, d, h["front"], h["pops"], h["search_seconds"], flush=True)
     else:
         raise SystemExit(f"unknown workload {name}")
 
