@@ -59,3 +59,21 @@ def test_ship_grid_mid_range(mos):
         assert st == mos.MOS_OK, h["workload"]
         assert np.array_equal(r.costs.astype(np.int64), costs), h["workload"]
         check_paths(g, int(s), int(t), r.costs, r.paths, 3)
+
+
+def test_time_expanded_routes(mos):
+    """Routes shaped like Table 2 at that table's largest objective counts."""
+    read_front = _read_front()
+    files = sorted(glob.glob(os.path.join(HERE, "routes", "r*.txt.gz")))
+    assert len(files) >= 3
+    for f in files:
+        h, costs = read_front(f)
+        r = int(os.path.basename(f)[1])
+        d = gen.ROUTE_MAX_OBJECTIVES[r]
+        g, s, t = gen.tmplar_route(r, 12, 0)
+        assert h["graph_sha256_16"] == g.digest()
+        assert int(h["start"]) == s and int(h["goal"]) == t and int(h["d"]) == d
+        res = mos.mos_solve(mos.Graph.from_gen(g), s, t, n_objectives=d, batch_width=4096,
+                            mem_budget=16 << 30)
+        assert np.array_equal(res.costs.astype(np.int64), costs), r
+        check_paths(g, s, t, res.costs, res.paths, d)
