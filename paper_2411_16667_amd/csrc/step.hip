@@ -30,6 +30,7 @@ namespace mos {
 constexpr int NT_SLOT = 1024;  // threads of the one-workgroup-per-slot kernels
 constexpr int NT_TILE = 256;   // threads of the tiled kernels
 constexpr int GP_WAVES = NT_TILE / WAVE;
+constexpr int HOLECAP = 1024;  // holes a large group's in-place compaction lists in LDS
 constexpr int PCH = 256;       // goal-front entries per LDS chunk (one per tiled thread)
 constexpr int BT_U = 4;        // frontier entries per lane in a pair tile of a large group
 constexpr int BT_ENTRIES = BT_U * WAVE;
@@ -1633,8 +1634,9 @@ __global__ __launch_bounds__(NT_TILE) void k_group_pairs(Slot* slots) {
     atomicAdd((unsigned long long*)&Sp->st[ST_PRUNED], (unsigned long long)pruned);
 }
 
-// Finish a big group (one wave): compact the frontier without its pruned
-// entries, append the accepted candidates, reset the node's group scratch.
+// Finish a big group (one wave): compact the frontier without its pruned and
+// removed entries, append the accepted candidates, reset the node's group
+// scratch.
 template <int DM>
 __global__ __launch_bounds__(NT_TILE) void k_group_finish(Slot* slots) {
   Slot* Sp = &slots[blockIdx.y];
@@ -1645,6 +1647,7 @@ __global__ __launch_bounds__(NT_TILE) void k_group_finish(Slot* slots) {
   const int d = S.d, cc = S.cand_cap;
   int32_t* fw = S.fw;
   int64_t gpairs = 0, fpairs = 0, fbytes = 0;
+  __shared__ int32_t hole_list[GP_WAVES][HOLECAP];  // per wave: hole positions of its group
   for (int bi = blockIdx.x * GP_WAVES + wave; bi < nbig; bi += gridDim.x * GP_WAVES) {
     const int gid = S.big_list[bi];
     const int v = S.grp_node[gid];
@@ -1658,54 +1661,111 @@ __global__ __launch_bounds__(NT_TILE) void k_group_finish(Slot* slots) {
     if (!frontier_dest(Sp, S, nr, cnt + k, d, &doff, &dcap)) break;
     const bool moved = doff != nr.off;
     int cursor = 0, nlive = 0;  // nlive: entries the pair tiles compared
-    // label ids FU x 64 at a time; the vectors are read only where the block
-    // has to be rewritten (it moved, or entries before were dropped).  Every
-    // entry's destination lies at or before its own position, so within one
-    // block of ids all rewritten vectors of RU sub-chunks are loaded before
-    // any of them is stored (one memory round trip instead of RU).
-    constexpr int FU = 16;                                   // label ids per lane in flight
-    constexpr int RU = DM <= 3 ? 16 : (DM <= 6 ? 8 : 4);     // rewritten sub-chunks in flight
-    for (int t0 = 0; t0 < cnt; t0 += FU * WAVE) {
-      int slab[FU];
+    constexpr int FU = 16;      // label ids per lane in flight
+    // A frontier is a set, so a block that stays in place is compacted by
+    // moving the kept entries behind the new end K = cnt - holes into the
+    // holes before K (pass 1 lists the holes in LDS, pass 2 walks the tail
+    // [K, cnt), which is only `holes` entries long).  A block that moves, or
+    // one with more holes than the list holds, is rewritten in order.
+    bool ordered = moved, counted = false;
+    if (!moved) {
+      int32_t* hl = hole_list[wave];
+      int nh = 0;
+      constexpr int HU = 16;  // label ids per lane in flight in the hole scan
+      for (int t0 = 0; t0 < cnt; t0 += HU * WAVE) {
+        int slab[HU];
 #pragma unroll
-      for (int u = 0; u < FU; ++u) {
-        const int e = t0 + u * WAVE + lane;
-        slab[u] = e < cnt ? fw[nr.off + (int64_t)d * nr.cap + e] : 0;
-      }
-      uint64_t am[FU];
-      int cur[FU];
-      uint32_t rw = 0;  // sub-chunks to rewrite (wave-uniform)
-#pragma unroll
-      for (int u = 0; u < FU; ++u) {
-        const int t = t0 + u * WAVE;
-        const int e = t + lane;
-        const bool has = e < cnt;
-        nlive += __popcll(ballot(has && slab[u] != FW_REMOVED));
-        const uint64_t hm = ballot(has);
-        am[u] = ballot(has && slab[u] >= 0);
-        cur[u] = cursor;
-        if (hm && (moved || cursor != t || am[u] != hm)) rw |= 1u << u;
-        cursor += __popcll(am[u]);
-      }
-      if (!rw) continue;
-#pragma unroll
-      for (int u0 = 0; u0 < FU; u0 += RU) {
-        int32_t sv[RU][DM];
-#pragma unroll
-        for (int u = 0; u < RU; ++u) {
-          const int uu = u0 + u;
-          if (((rw >> uu) & 1) && ((am[uu] >> lane) & 1)) {
-            const int e = t0 + uu * WAVE + lane;
-            FOR_K(kk) sv[u][kk] = fw[nr.off + (int64_t)kk * nr.cap + e];
-          }
+        for (int u = 0; u < HU; ++u) {
+          const int e = t0 + u * WAVE + lane;
+          slab[u] = e < cnt ? fw[nr.off + (int64_t)d * nr.cap + e] : 0;
         }
 #pragma unroll
-        for (int u = 0; u < RU; ++u) {
-          const int uu = u0 + u;
-          if (((rw >> uu) & 1) && ((am[uu] >> lane) & 1)) {
-            const int64_t w = doff + cur[uu] + rank_below(am[uu]);
-            FOR_K(kk) fw[w + (int64_t)kk * dcap] = sv[u][kk];
-            fw[w + (int64_t)d * dcap] = slab[uu];
+        for (int u = 0; u < HU; ++u) {
+          const int e = t0 + u * WAVE + lane;
+          const bool has = e < cnt;
+          nlive += __popcll(ballot(has && slab[u] != FW_REMOVED));
+          const bool hole = has && slab[u] < 0;
+          const uint64_t m = ballot(hole);
+          if (hole) {
+            const int r = nh + rank_below(m);
+            if (r < HOLECAP) hl[r] = e;
+          }
+          nh += __popcll(m);
+        }
+      }
+      counted = true;
+      if (nh > HOLECAP) {
+        ordered = true;
+      } else {
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");  // the list is read across lanes
+        const int K = cnt - nh;
+        int r = 0;
+        for (int t = K; t < cnt; t += WAVE) {
+          const int e = t + lane;
+          const int id = e < cnt ? fw[nr.off + (int64_t)d * nr.cap + e] : -1;
+          const bool keep = id >= 0;
+          const uint64_t m = ballot(keep);
+          if (keep) {
+            const int dst = hl[r + rank_below(m)];  // a hole before K
+            int32_t sv[DM];
+            FOR_K(kk) sv[kk] = fw[nr.off + (int64_t)kk * nr.cap + e];
+            FOR_K(kk) fw[nr.off + (int64_t)kk * nr.cap + dst] = sv[kk];
+            fw[nr.off + (int64_t)d * nr.cap + dst] = id;
+          }
+          r += __popcll(m);
+        }
+        cursor = K;
+      }
+    }
+    if (ordered) {
+      // label ids FU x 64 at a time; the vectors are read only where the block
+      // has to be rewritten (it moved, or entries before were dropped).  Every
+      // entry's destination lies at or before its own position, so within one
+      // block of ids all rewritten vectors of RU sub-chunks are loaded before
+      // any of them is stored (one memory round trip instead of RU).
+      constexpr int RU = DM <= 3 ? 16 : (DM <= 6 ? 8 : 4);  // rewritten sub-chunks in flight
+      for (int t0 = 0; t0 < cnt; t0 += FU * WAVE) {
+        int slab[FU];
+#pragma unroll
+        for (int u = 0; u < FU; ++u) {
+          const int e = t0 + u * WAVE + lane;
+          slab[u] = e < cnt ? fw[nr.off + (int64_t)d * nr.cap + e] : 0;
+        }
+        uint64_t am[FU];
+        int cur[FU];
+        uint32_t rw = 0;  // sub-chunks to rewrite (wave-uniform)
+#pragma unroll
+        for (int u = 0; u < FU; ++u) {
+          const int t = t0 + u * WAVE;
+          const int e = t + lane;
+          const bool has = e < cnt;
+          if (!counted) nlive += __popcll(ballot(has && slab[u] != FW_REMOVED));
+          const uint64_t hm = ballot(has);
+          am[u] = ballot(has && slab[u] >= 0);
+          cur[u] = cursor;
+          if (hm && (moved || cursor != t || am[u] != hm)) rw |= 1u << u;
+          cursor += __popcll(am[u]);
+        }
+        if (!rw) continue;
+#pragma unroll
+        for (int u0 = 0; u0 < FU; u0 += RU) {
+          int32_t sv[RU][DM];
+#pragma unroll
+          for (int u = 0; u < RU; ++u) {
+            const int uu = u0 + u;
+            if (((rw >> uu) & 1) && ((am[uu] >> lane) & 1)) {
+              const int e = t0 + uu * WAVE + lane;
+              FOR_K(kk) sv[u][kk] = fw[nr.off + (int64_t)kk * nr.cap + e];
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < RU; ++u) {
+            const int uu = u0 + u;
+            if (((rw >> uu) & 1) && ((am[uu] >> lane) & 1)) {
+              const int64_t w = doff + cur[uu] + rank_below(am[uu]);
+              FOR_K(kk) fw[w + (int64_t)kk * dcap] = sv[u][kk];
+              fw[w + (int64_t)d * dcap] = slab[uu];
+            }
           }
         }
       }
