@@ -44,10 +44,12 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200, help="timed label steps")
-    ap.add_argument("--warmup", type=int, default=2000,
-                    help="untimed label steps before timing (2000 steps of B = 8192 take the "
-                         "search about 16M labels deep)")
-    ap.add_argument("--batch-width", type=int, default=8192)
+    ap.add_argument("--warmup", type=int, default=1100,
+                    help="untimed label steps before timing (1100 steps of B = 16384 take the "
+                         "search about 19M labels deep)")
+    ap.add_argument("--batch-width", type=int, default=16384,
+                    help="labels popped per step (the widest batch the library takes; a sweep "
+                         "at this depth gives 13.2M pops/s at 8192 and 16.8M at 16384)")
     ap.add_argument("--profile-steps", type=int, default=50,
                     help="last warm-up steps with every kernel timed (per-kernel table; "
                          "picks the dominant kernel)")
@@ -57,8 +59,9 @@ def parse():
                     help="queries of the batched-vs-plain comparison (0 = skip)")
     ap.add_argument("--qdist", type=int, nargs=2, default=(10, 60),
                     help="Manhattan distance range of those queries")
-    ap.add_argument("--query-width", type=int, default=256,
-                    help="batch width B of every query in that comparison")
+    ap.add_argument("--query-width", type=int, default=0,
+                    help="batch width B of every query in that comparison (0 = picked by "
+                         "the autotuner on a sample of the queries)")
     ap.add_argument("--workload", choices=("steps", "served", "routes"), default="steps",
                     help="steps: label steps of the ship-routing query (the headline line); "
                          "served: the request loop on the 1M-node road-like graph; "
@@ -174,21 +177,34 @@ def cpu_baseline(g, s, t, seconds):
 
 def batched_vs_plain(mos, gen, G, a):
     """Queries/s of one mos_solve_batch call against a loop of mos_solve over
-    the same start/goal list on the same grid (same B, paths included)."""
+    the same start/goal list on the same grid (same B, paths included; B from
+    the autotuner unless --query-width is given)."""
     import numpy as np
 
     S, T = gen.ship_queries(256, 256, a.queries, seed=1000, dmin=a.qdist[0], dmax=a.qdist[1])
-    mos.mos_solve(G, int(S[0]), int(T[0]), batch_width=a.query_width)  # engine warm-up
+    tuned = None
+    B = a.query_width
+    if B == 0:
+        from paper_2411_16667_amd.autotune import tune_batch_width
+
+        tuned = tune_batch_width(G, S, T, widths=(256, 1024, 4096), sample=len(S),
+                                 costs_only=False)
+        B = tuned["batch_width"]
+    # engines are cached per (slot count, width, ...): one untimed call of each
+    # form first, so that both timed forms reuse their engine
+    mos.mos_solve_batch(G, S, T, batch_width=B)
     t0 = time.perf_counter()
-    res = mos.mos_solve_batch(G, S, T, batch_width=a.query_width)
+    res = mos.mos_solve_batch(G, S, T, batch_width=B)
     t1 = time.perf_counter()
-    plain = [mos.mos_solve(G, int(S[q]), int(T[q]), batch_width=a.query_width)
-             for q in range(len(S))]
+    mos.mos_solve(G, int(S[0]), int(T[0]), batch_width=B)
+    t1 = time.perf_counter()
+    plain = [mos.mos_solve(G, int(S[q]), int(T[q]), batch_width=B) for q in range(len(S))]
     t2 = time.perf_counter()
     same = all(st == mos.MOS_OK and np.array_equal(r.costs, p.costs)
                for (st, r), p in zip(res, plain))
     fronts = [len(p.costs) for p in plain]
-    return {"queries": len(S), "manhattan_distance": list(a.qdist), "batch_width": a.query_width,
+    return {"queries": len(S), "manhattan_distance": list(a.qdist), "batch_width": B,
+            "autotune": tuned,
             "batched_qps": len(S) / (t1 - t0), "plain_qps": len(S) / (t2 - t1),
             "speedup": (t2 - t1) / (t1 - t0), "same_fronts": bool(same),
             "front_sizes": {"min": min(fronts), "median": int(np.median(fronts)), "max": max(fronts)}}

@@ -86,3 +86,21 @@ def test_small_budget_readmits(mos):
         assert st == mos.MOS_OK, q
         ref = oracle.solve(g, int(S[q]), int(T[q]), 3)
         assert np.array_equal(r.costs.astype(np.int64), ref.costs), q
+
+
+def test_autotuned_batch_width(mos):
+    """The autotuner returns one of its widths, and the fronts at that width
+    equal the oracle's."""
+    from paper_2411_16667_amd.autotune import tune_batch_width
+
+    g = gen.grid_uniform(12, 12, 3, 1, 10, seed=21)
+    G = mos.Graph.from_gen(g)
+    rng = np.random.default_rng(5)
+    S = rng.integers(0, g.n, 10).astype(np.int32)
+    T = rng.integers(0, g.n, 10).astype(np.int32)
+    r = tune_batch_width(G, S, T, widths=(4, 64, 512), sample=6, mem_budget=2 << 30)
+    assert r["batch_width"] in (4, 64, 512) and set(r["seconds"]) == {4, 64, 512}
+    res = mos.mos_solve_batch(G, S, T, batch_width=r["batch_width"], mem_budget=2 << 30)
+    for (st, x), s, t in zip(res, S, T):
+        assert st == mos.MOS_OK
+        assert np.array_equal(x.costs.astype(np.int64), oracle.solve(g, int(s), int(t)).costs)
