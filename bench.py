@@ -107,7 +107,8 @@ def kernel_bytes(name, c, d, steps):
         "k_group_process": fb1,
         "k_group_pairs": fb - fb1,
         "k_group_finish": fb - fb1,
-        "k_accept_scan": 4 * cands + 8 * acc,
+        "k_accept_count": 4 * cands,
+        "k_accept_scan": 4 * cands + 12 * acc,
         "k_insert": (12 * d + 24) * acc,
         "k_step_end": 0,
     }.get(name, 0)

@@ -15,6 +15,7 @@ namespace mos {
 
 constexpr int MAXD = 12;          // objectives supported by the kernels
 constexpr int NB = 4096;          // OPEN histogram bins: exact F1 values lo..lo+NB-2, then overflow
+constexpr int ACC_TILE = 2048;    // candidates per tile of the accepted-candidate numbering
 constexpr int TIECAP = 256;       // tie sets up to this size are ranked in LDS; larger ones
                                   // are first narrowed by exact radix refinement
 constexpr int MINCAP = 8;         // smallest frontier block, in entries
@@ -132,6 +133,7 @@ struct Slot {
   int32_t* c_rej;      //   rejected inside its group or by the frontier
   int32_t* c_acc;      //   accepted (inserted)
   int64_t* c_fslot;    //   word offset of the frontier label-id slot it was given
+  int32_t* acc_tile;   // 2 per ACC_TILE candidates: near and far accepted in the tile
   int32_t* order;      // cand_cap: candidates grouped by node
   int32_t* grp_node;   // cand_cap: node of each group
   int32_t* grp_off;    // cand_cap: first position of each group in `order`
@@ -196,6 +198,11 @@ __device__ __forceinline__ int agg_append(int32_t* ctr, bool p) {
 
 __device__ __forceinline__ int wave_min(int v) {
   for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+  return v;
+}
+
+__device__ __forceinline__ int wave_sum(int v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
   return v;
 }
 

@@ -15,7 +15,8 @@
 //            split into pair tiles): Duplicate, NotDominated and Prune against
 //            the node's labels (G_OP and G_CL together) plus dominance among the
 //            candidates of the same step
-//   insert   k_accept_scan, k_insert, k_step_end: new labels into OPEN and G_OP
+//   insert   k_accept_count, k_accept_scan, k_insert, k_step_end: new labels
+//            into OPEN and G_OP
 //   filter   k_pfilter: NotDominated(F', P) for the labels inserted this step
 //
 // All arithmetic is exact int32.  Tiled kernels run on a (gx, slots) grid and
@@ -35,6 +36,7 @@ constexpr int PCH = 256;       // goal-front entries per LDS chunk (one per tile
 constexpr int BT_U = 4;        // frontier entries per lane in a pair tile of a large group
 constexpr int BT_ENTRIES = BT_U * WAVE;
 static_assert(PCH == NT_TILE, "goal tiles map one label to one thread");
+static_assert(ACC_TILE % NT_TILE == 0, "an accept tile is whole chunks of one workgroup");
 
 #define FOR_K(k) _Pragma("unroll") for (int k = 0; k < DM; ++k) if (k < d)
 
@@ -1818,78 +1820,150 @@ __global__ __launch_bounds__(NT_TILE) void k_group_finish(Slot* slots) {
 // ---------------------------------------------------------------- insert
 // Ranks of the accepted candidates in flat order: c_rank = rank among all
 // accepted (label id offset), c_rej = rank within the OPEN tier it joins
-// (c_acc: 0 rejected, 1 near, 2 far).  Wave w owns a contiguous segment; one
-// counting pass, one exchange of per-wave totals, one writing pass.
-__global__ __launch_bounds__(NT_SLOT) void k_accept_scan(Slot* slots) {
-  Slot* Sp = &slots[blockIdx.x];
+// (c_acc: 0 rejected, 1 near, 2 far).  Two grid-wide passes over tiles of
+// ACC_TILE candidates: k_accept_count stores each tile's near and far counts;
+// k_accept_scan starts each tile after the counts of the tiles before it and
+// numbers the tile's accepted candidates in index order.
+__global__ __launch_bounds__(NT_TILE) void k_accept_count(Slot* slots) {
+  Slot* Sp = &slots[blockIdx.y];
   const Slot S = *Sp;
   if (S.status != S_RUN) return;
-  constexpr int NW = NT_SLOT / WAVE;
-  __shared__ int wn[NW], wf[NW];
-  const int M = S.cand_n;
-  const int w = threadIdx.x / WAVE, lane = lane_id();
-  const int seg = ((M + NW - 1) / NW + WAVE - 1) / WAVE * WAVE;
-  const int lo = min(M, w * seg), hi = min(M, lo + seg);
-  // counting pass: AU independent loads per lane in flight
-  constexpr int AU = 8;
-  int cn = 0, cf = 0;
-  for (int b = lo; b < hi; b += AU * WAVE) {
-    int a[AU];
+  constexpr int U = ACC_TILE / NT_TILE;
+  __shared__ int wn[GP_WAVES], wf[GP_WAVES];
+  const int M = S.cand_n, nt = (M + ACC_TILE - 1) / ACC_TILE;
+  const int wave = threadIdx.x / WAVE, lane = lane_id();
+  for (int t = blockIdx.x; t < nt; t += gridDim.x) {
+    int a[U];
 #pragma unroll
-    for (int u = 0; u < AU; ++u) {
-      const int i = b + u * WAVE + lane;
-      a[u] = i < hi ? S.c_acc[i] : 0;
+    for (int u = 0; u < U; ++u) {
+      const int i = t * ACC_TILE + u * NT_TILE + threadIdx.x;
+      a[u] = i < M ? S.c_acc[i] : 0;
     }
+    int cn = 0, cf = 0;
 #pragma unroll
-    for (int u = 0; u < AU; ++u) {
+    for (int u = 0; u < U; ++u) {
       cn += __popcll(ballot(a[u] == 1));
       cf += __popcll(ballot(a[u] == 2));
     }
-  }
-  if (lane == 0) {
-    wn[w] = cn;
-    wf[w] = cf;
-  }
-  __syncthreads();
-  int bn = 0, bf = 0, tn = 0, tf = 0;
-#pragma unroll
-  for (int x = 0; x < NW; ++x) {
-    if (x < w) {
-      bn += wn[x];
-      bf += wf[x];
+    if (lane == 0) {
+      wn[wave] = cn;
+      wf[wave] = cf;
     }
-    tn += wn[x];
-    tf += wf[x];
-  }
-  for (int b = lo; b < hi; b += AU * WAVE) {
-    int a[AU];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int n = 0, f = 0;
 #pragma unroll
-    for (int u = 0; u < AU; ++u) {
-      const int i = b + u * WAVE + lane;
-      a[u] = i < hi ? S.c_acc[i] : 0;
+      for (int w = 0; w < GP_WAVES; ++w) {
+        n += wn[w];
+        f += wf[w];
+      }
+      S.acc_tile[2 * t] = n;
+      S.acc_tile[2 * t + 1] = f;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(NT_TILE) void k_accept_scan(Slot* slots) {
+  Slot* Sp = &slots[blockIdx.y];
+  const Slot S = *Sp;
+  if (S.status != S_RUN) return;
+  constexpr int U = ACC_TILE / NT_TILE;
+  __shared__ int red[4][GP_WAVES];
+  __shared__ int cwn[U][GP_WAVES], cwf[U][GP_WAVES];
+  const int M = S.cand_n, nt = (M + ACC_TILE - 1) / ACC_TILE;
+  const int wave = threadIdx.x / WAVE, lane = lane_id();
+  if (blockIdx.x == 0) {  // totals and the capacity check
+    int tn = 0, tf = 0;
+    for (int x = threadIdx.x; x < nt; x += NT_TILE) {
+      tn += S.acc_tile[2 * x];
+      tf += S.acc_tile[2 * x + 1];
+    }
+    tn = wave_sum(tn);
+    tf = wave_sum(tf);
+    if (lane == 0) {
+      red[2][wave] = tn;
+      red[3][wave] = tf;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      tn = tf = 0;
+#pragma unroll
+      for (int w = 0; w < GP_WAVES; ++w) {
+        tn += red[2][w];
+        tf += red[3][w];
+      }
+      Sp->accept_n = tn + tf;
+      Sp->accept_near = tn;
+      Sp->accept_far = tf;
+      if (S.n_labels + tn + tf > S.pool_cap || S.keep_n + tn > S.open_cap ||
+          S.far_n + tf > S.open_cap) {
+        Sp->status = S_OVERFLOW;
+        Sp->err_line = __LINE__;
+      }
+    }
+    __syncthreads();
+  }
+  for (int t = blockIdx.x; t < nt; t += gridDim.x) {
+    int a[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = t * ACC_TILE + u * NT_TILE + threadIdx.x;
+      a[u] = i < M ? S.c_acc[i] : 0;
+    }
+    int bn = 0, bf = 0;  // accepted in the tiles before this one
+    for (int x = threadIdx.x; x < t; x += NT_TILE) {
+      bn += S.acc_tile[2 * x];
+      bf += S.acc_tile[2 * x + 1];
+    }
+    bn = wave_sum(bn);
+    bf = wave_sum(bf);
+    uint64_t mn[U], mf[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      mn[u] = ballot(a[u] == 1);
+      mf[u] = ballot(a[u] == 2);
+    }
+    if (lane == 0) {
+      red[0][wave] = bn;
+      red[1][wave] = bf;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        cwn[u][wave] = __popcll(mn[u]);
+        cwf[u][wave] = __popcll(mf[u]);
+      }
+    }
+    __syncthreads();
+    // chunk u of the tile is candidates t*ACC_TILE + u*NT_TILE + [0, NT_TILE),
+    // wave w holds 64 of them: its base is every chunk before u plus the
+    // waves before w in chunk u
+    int on = 0, of = 0;
+#pragma unroll
+    for (int w = 0; w < GP_WAVES; ++w) {
+      on += red[0][w];
+      of += red[1][w];
     }
 #pragma unroll
-    for (int u = 0; u < AU; ++u) {
-      const int i = b + u * WAVE + lane;
-      const uint64_t mn = ballot(a[u] == 1), mf = ballot(a[u] == 2);
+    for (int u = 0; u < U; ++u) {
+      int pn = on, pf = of;
+#pragma unroll
+      for (int w = 0; w < GP_WAVES; ++w) {
+        if (w < wave) {
+          pn += cwn[u][w];
+          pf += cwf[u][w];
+        }
+        on += cwn[u][w];
+        of += cwf[u][w];
+      }
       if (a[u]) {
-        const int rn = bn + rank_below(mn), rf = bf + rank_below(mf);
+        const int i = t * ACC_TILE + u * NT_TILE + threadIdx.x;
+        const int rn = pn + rank_below(mn[u]), rf = pf + rank_below(mf[u]);
         S.c_rank[i] = rn + rf;
         S.c_rej[i] = a[u] == 1 ? rn : rf;
         S.order[rn + rf] = i;  // accepted candidates by label id (grouping is done)
       }
-      bn += __popcll(mn);
-      bf += __popcll(mf);
     }
-  }
-  if (threadIdx.x == 0) {
-    Sp->accept_n = tn + tf;
-    Sp->accept_near = tn;
-    Sp->accept_far = tf;
-    if (S.n_labels + tn + tf > S.pool_cap || S.keep_n + tn > S.open_cap || S.far_n + tf > S.open_cap) {
-      Sp->status = S_OVERFLOW;
-      Sp->err_line = __LINE__;
-    }
+    __syncthreads();
   }
 }
 
@@ -1954,7 +2028,8 @@ const char* const kStepKernelNames[kStepKernels] = {
     "k_far_hist",      "k_far_move",      "k_open_hist",     "k_open_threshold", "k_open_scatter",
     "k_batch_finalize", "k_goal_pairs",   "k_goal_merge",    "k_popcheck",       "k_expand",
     "k_group_count",   "k_group_offsets", "k_group_scatter", "k_group_process",  "k_group_pairs",
-    "k_group_finish",  "k_accept_scan",   "k_insert",        "k_pfilter",        "k_step_end"};
+    "k_group_finish",  "k_accept_count",  "k_accept_scan",   "k_insert",         "k_pfilter",
+    "k_step_end"};
 
 template <int DM>
 static void launch_step_dm(const StepArgs& a, hipStream_t st, hipEvent_t* ev, uint32_t mask) {
@@ -1983,7 +2058,8 @@ static void launch_step_dm(const StepArgs& a, hipStream_t st, hipEvent_t* ev, ui
   mark(); hipLaunchKernelGGL(k_group_process<DM>, tiled, dim3(NT_TILE), 0, st, a.slots);
   mark(); hipLaunchKernelGGL(k_group_pairs<DM>, tiled, dim3(NT_TILE), 0, st, a.slots);
   mark(); hipLaunchKernelGGL(k_group_finish<DM>, tiled, dim3(NT_TILE), 0, st, a.slots);
-  mark(); hipLaunchKernelGGL(k_accept_scan, per, dim3(NT_SLOT), 0, st, a.slots);
+  mark(); hipLaunchKernelGGL(k_accept_count, cand, dim3(NT_TILE), 0, st, a.slots);
+  mark(); hipLaunchKernelGGL(k_accept_scan, cand, dim3(NT_TILE), 0, st, a.slots);
   mark(); hipLaunchKernelGGL(k_insert<DM>, cand, dim3(NT_TILE), 0, st, a.slots, a.G);
   mark(); hipLaunchKernelGGL(k_pfilter<DM>, tiled, dim3(NT_TILE), 0, st, a.slots, a.G);
   mark(); hipLaunchKernelGGL(k_step_end, dim3((a.nslots + 63) / 64), dim3(64), 0, st, a.slots, a.nslots);
