@@ -244,6 +244,12 @@ struct Layout {
 
 static inline int64_t al(int64_t x) { return (x + 255) & ~int64_t(255); }
 
+// per-tile counts of the batch split: SPLIT_WORDS ints per SPLIT_TILE items
+// (direct pops and tie entries)
+static inline int64_t split_tile_bytes(int64_t batch_cap, int64_t tie_cap) {
+  return 4 * (int64_t)SPLIT_WORDS * ((batch_cap + tie_cap) / SPLIT_TILE + 2);
+}
+
 static int64_t fixed_bytes(int64_t n, int d, int batch_cap, int cand_cap, int tie_cap) {
   int64_t b = 0;
   b += al(4 * d * n) + al(16 * n) + 2 * al(4 * n);                   // h, node, grp
@@ -265,11 +271,11 @@ static bool plan_layout(const mos_graph* g, int d, int B, int64_t budget, int64_
   const int64_t fixed = fixed_bytes(g->n, d, L->batch_cap, L->cand_cap, 0);
   if (budget <= fixed) return false;
   // bytes per pooled label: pool (node, parent, arc, g, state, tested mark) + OPEN 2x(F1,
-  // lab) + tie set (F1, lab, state, d key words) + frontier 3*(d+1) words + goal
-  // front share
-  const double per = (16.0 + 4.0 * d + 1.0) + 32.0 + 12.0 + 4.0 * d + 12.0 * (d + 1) +
-                     (8.0 * (d + 2) + 8.0) / 8.0;
-  int64_t pool = (int64_t)((double)(budget - fixed - 32 * 256) / per);
+  // lab) + tie set (F1, lab, state, d key words, split tile share) + frontier 3*(d+1)
+  // words + goal front share
+  const double per = (16.0 + 4.0 * d + 1.0) + 32.0 + 12.0 + 4.0 * d +
+                     4.0 * SPLIT_WORDS / SPLIT_TILE + 12.0 * (d + 1) + (8.0 * (d + 2) + 8.0) / 8.0;
+  int64_t pool = (int64_t)((double)(budget - fixed - 48 * 256) / per);
   pool = std::min<int64_t>(pool, (int64_t)1 << 30);
   if (label_limit > 0) pool = std::min<int64_t>(pool, label_limit);
   if (pool < 16) return false;
@@ -282,6 +288,7 @@ static bool plan_layout(const mos_graph* g, int d, int B, int64_t budget, int64_
   b += 3 * al(4 * pool) + al(4 * (int64_t)d * pool) + al(pool);  // pool
   b += 8 * al(4 * pool);                                          // OPEN near + far tiers
   b += 3 * al(4 * pool) + al(4 * (int64_t)d * pool);             // tie set and its keys
+  b += al(split_tile_bytes(L->batch_cap, (int32_t)pool));         // batch split tiles
   b += 2 * (al(4 * (int64_t)d * L->P_cap) + 2 * al(4 * (int64_t)L->P_cap)) + al(4 * pool);
   b += al(4 * L->fw_cap);
   L->bytes = al(b);
@@ -339,6 +346,7 @@ static void carve(Slot& s, char* base, const Layout& L, int64_t n, int d) {
   s.tie_lab = (int32_t*)take(4 * (int64_t)L.tie_cap);
   s.tie_st = (int32_t*)take(4 * (int64_t)L.tie_cap);
   s.tie_key = (int32_t*)take(4 * (int64_t)d * L.tie_cap);
+  s.split_tile = (int32_t*)take(split_tile_bytes(L.batch_cap, L.tie_cap));
   for (int b = 0; b < 2; ++b) {
     s.Pg[b] = (int32_t*)take(4 * (int64_t)d * L.P_cap);
     s.Plab[b] = (int32_t*)take(4 * (int64_t)L.P_cap);

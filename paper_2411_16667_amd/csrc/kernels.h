@@ -24,7 +24,7 @@ int dm_for(int d);
 // kStepKernels kernels.  With ev != nullptr, the kernels i whose bit is set in
 // `mask` are bracketed by events: ev[i] is recorded before kernel i and
 // ev[i + 1] after it; ev[kStepKernels] is always recorded after the last one.
-constexpr int kStepKernels = 21;
+constexpr int kStepKernels = 23;
 extern const char* const kStepKernelNames[kStepKernels];
 void launch_step(const StepArgs& a, hipStream_t st, hipEvent_t* ev = nullptr,
                  uint32_t mask = 0xffffffffu);

@@ -16,6 +16,8 @@ namespace mos {
 constexpr int MAXD = 12;          // objectives supported by the kernels
 constexpr int NB = 4096;          // OPEN histogram bins: exact F1 values lo..lo+NB-2, then overflow
 constexpr int ACC_TILE = 2048;    // candidates per tile of the accepted-candidate numbering
+constexpr int SPLIT_TILE = 2048;  // items (popped labels, tie entries) per tile of the batch split
+constexpr int SPLIT_WORDS = 5;    // per split tile: goal, regular, out-degree sum, back to OPEN, min F1
 constexpr int TIECAP = 256;       // tie sets up to this size are ranked in LDS; larger ones
                                   // are first narrowed by exact radix refinement
 constexpr int MINCAP = 8;         // smallest frontier block, in entries
@@ -124,6 +126,7 @@ struct Slot {
   int32_t* tie_lab;    // tie_cap
   int32_t* tie_st;     // tie_cap: refinement state of each tie entry
   int32_t* tie_key;    // d planes of tie_cap: F_2..F_d and the node of each tie entry
+  int32_t* split_tile; // SPLIT_WORDS per SPLIT_TILE items of the batch split
   int32_t* c_node;     // cand_cap: candidate target node
   int32_t* c_par;      //   parent label
   int32_t* c_arc;      //   arc
@@ -156,6 +159,7 @@ struct Slot {
   int32_t refill, r_T, r_all, r_moved;  // refill of near from far, decided per step
   int32_t r_keep, lo_refill, blocks_a, blocks_b;
   int32_t spill_T, spill_on, accept_near, accept_far;
+  int32_t pop_nb, pop_keep;      // set by k_batch_finalize: direct pops, near-tier length
 
   int64_t st[NSTAT];
 };

@@ -37,6 +37,7 @@ constexpr int BT_U = 4;        // frontier entries per lane in a pair tile of a 
 constexpr int BT_ENTRIES = BT_U * WAVE;
 static_assert(PCH == NT_TILE, "goal tiles map one label to one thread");
 static_assert(ACC_TILE % NT_TILE == 0, "an accept tile is whole chunks of one workgroup");
+static_assert(SPLIT_TILE % NT_TILE == 0, "a split tile is whole chunks of one workgroup");
 
 #define FOR_K(k) _Pragma("unroll") for (int k = 0; k < DM; ++k) if (k < d)
 
@@ -427,56 +428,9 @@ __device__ __forceinline__ int key_word(const Slot& S, int i, int w) {
   return w == 0 ? S.tie_f1[i] : S.tie_key[(size_t)(w - 1) * S.tie_cap + i];
 }
 
-// Goal/regular split of the nb popped labels (thread t owns batch positions
-// t*E .. t*E+E-1): goal labels to goal_lab (their goal-step flags cleared),
-// regular labels to reg with the exclusive prefix of their out-degrees.
-template <int E>
-__device__ void split_batch(const Slot& S, const GraphDev& G, int nb, int* tmp, int* goal_total,
-                            int* reg_total, int* deg_total) {
-  const int goal = S.goal;
-  int cg = 0, cr = 0, cdeg = 0;
-  int labs[E], kind[E], degs[E];
-#pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const int i = threadIdx.x * E + e;
-    labs[e] = 0;
-    kind[e] = 0;
-    degs[e] = 0;
-    if (i < nb) {
-      const int lab = S.batch[i];
-      const int v = S.Lnode[lab];
-      labs[e] = lab;
-      if (v == goal) {
-        kind[e] = 1;
-        ++cg;
-      } else {
-        kind[e] = 2;
-        degs[e] = G.row_ptr[v + 1] - G.row_ptr[v];
-        ++cr;
-        cdeg += degs[e];
-      }
-    }
-  }
-  int pg = block_exscan<NT_SLOT>(cg, goal_total, tmp);
-  int pr = block_exscan<NT_SLOT>(cr, reg_total, tmp);
-  int pd = block_exscan<NT_SLOT>(cdeg, deg_total, tmp);
-#pragma unroll
-  for (int e = 0; e < E; ++e) {
-    if (kind[e] == 1) {
-      if (pg < S.cand_cap) S.c_rej[pg] = 0;  // goal-step flag of this goal label
-      S.goal_lab[pg++] = labs[e];
-    } else if (kind[e] == 2) {
-      S.reg[pr] = labs[e];
-      S.reg_off[pr] = pd;
-      S.reg_kill[pr] = 0;
-      ++pr;
-      pd += degs[e];
-    }
-  }
-}
 
-// Finish the pop: exact selection inside the tie bin, goal/regular split,
-// out-degree prefix of the regular labels.
+// Exact selection inside the tie bin (one workgroup per slot); the batch is
+// assembled and split by k_split_count and k_split_scan.
 template <int DM>
 __global__ __launch_bounds__(NT_SLOT) void k_batch_finalize(Slot* slots, GraphDev G) {
   Slot* Sp = &slots[blockIdx.x];
@@ -666,84 +620,244 @@ __global__ __launch_bounds__(NT_SLOT) void k_batch_finalize(Slot* slots, GraphDe
       }
       __syncthreads();
     }
-    // taken -> batch, not taken -> OPEN (other buffer)
-    int32_t* KF = pick(S.open_f1, S.open_sel ^ 1);
-    int32_t* KL = pick(S.open_lab, S.open_sel ^ 1);
-    int kmin = INT32_MAX;
-    if (threadIdx.x == 0) {
-      sh_a = 0;
-      sh_b = 0;
-    }
-    __syncthreads();
-    constexpr int DU = 4;  // tie entries per thread in flight
-    for (int base = 0; base < n; base += DU * NT_SLOT) {
-      int st[DU], lab[DU], f1[DU];
-#pragma unroll
-      for (int u = 0; u < DU; ++u) {
-        const int i = base + u * NT_SLOT + threadIdx.x;
-        st[u] = i < n ? TS[i] : 0;
-        lab[u] = i < n ? S.tie_lab[i] : 0;
-        f1[u] = i < n ? S.tie_f1[i] : 0;
-      }
-#pragma unroll
-      for (int u = 0; u < DU; ++u) {
-        const int p1 = lds_append(&sh_a, st[u] == 1);
-        const int p2 = lds_append(&sh_b, st[u] == 2);
-        if (p1 >= 0 && nb + p1 < S.batch_cap) S.batch[nb + p1] = lab[u];
-        if (p2 >= 0 && keep_n + p2 < S.open_cap) {
-          KF[keep_n + p2] = f1[u];
-          KL[keep_n + p2] = lab[u];
-          kmin = min(kmin, f1[u]);
-        }
-      }
-    }
-    kmin = wave_min(kmin);
-    if (lane_id() == 0 && kmin != INT32_MAX) atomicMin(&Sp->lo_next, kmin);
-    __syncthreads();
-    nb += sh_a;
-    keep_n += sh_b;
-    if (threadIdx.x == 0) {
-      Sp->batch_n = nb;
-      Sp->keep_n = keep_n;
-    }
-    __syncthreads();
   }
-  const uint64_t c1 = wall_clock64();
-  if (nb > S.batch_cap || nb > BATCH_MAX || keep_n > S.open_cap) {
+  // taken tie entries join the batch and the others go back to OPEN in the
+  // batch split (k_split_count, k_split_scan), which also splits the batch
+  if (nb > S.batch_cap || nb > BATCH_MAX) {
     if (threadIdx.x == 0) {
       Sp->status = S_OVERFLOW;
       Sp->err_line = __LINE__;
     }
     return;
   }
-  // ---- split into goal and regular labels.  The order of the batch is
-  // immaterial: no decision of the step depends on label ids or positions
-  // (ties between equal candidates go to the smaller arc id, which is unique
-  // among them).
-  int goal_total, reg_total, deg_carry;
-  if (nb <= NT_SLOT) split_batch<1>(S, G, nb, tmp, &goal_total, &reg_total, &deg_carry);
-  else if (nb <= 2 * NT_SLOT) split_batch<2>(S, G, nb, tmp, &goal_total, &reg_total, &deg_carry);
-  else if (nb <= 4 * NT_SLOT) split_batch<4>(S, G, nb, tmp, &goal_total, &reg_total, &deg_carry);
-  else if (nb <= 8 * NT_SLOT) split_batch<8>(S, G, nb, tmp, &goal_total, &reg_total, &deg_carry);
-  else split_batch<16>(S, G, nb, tmp, &goal_total, &reg_total, &deg_carry);
   if (threadIdx.x == 0) {
-    const uint64_t c3 = wall_clock64();
-    Sp->st[ST_T0 + 0] += c1 - c0;
-    Sp->st[ST_T0 + 2] += c3 - c1;
-    S.reg_off[reg_total] = deg_carry;
-    Sp->goal_n = goal_total;
-    Sp->reg_n = reg_total;
-    Sp->cand_n = deg_carry;
+    Sp->st[ST_T0 + 0] += wall_clock64() - c0;
+    Sp->pop_nb = nb;
+    Sp->pop_keep = S.keep_n;
     Sp->ngroups = 0;
     Sp->accept_n = 0;
-    Sp->st[ST_POPS] += nb;
-    Sp->st[ST_GOAL_POPS] += goal_total;
-    if (deg_carry > S.cand_cap || goal_total > S.cand_cap) {
-      Sp->status = S_OVERFLOW;
-      Sp->err_line = __LINE__;
-    } else if (nb == 0 && Sp->far_n == 0) {
-      Sp->status = S_DONE;  // no live label left in OPEN
+  }
+}
+
+// Second half of the pop, over SPLIT_TILE-item tiles of the directly popped
+// labels (batch[0, pop_nb)) followed by the tie entries: a taken tie entry
+// joins the batch, a tie entry not taken goes back to the near tier of OPEN,
+// and every batch label is split into goal labels (goal_lab, their goal-step
+// flags cleared) and regular labels (reg, with the exclusive prefix of their
+// out-degrees in reg_off).  k_split_count stores each tile's counts;
+// k_split_scan starts each tile after the tiles before it and writes its items
+// in order.  Item i of a tile is loaded by thread i % NT_TILE (U per thread).
+enum { SPLIT_NONE = 0, SPLIT_GOAL = 1, SPLIT_REG = 2, SPLIT_BACK = 3 };
+
+template <int U>
+__device__ __forceinline__ void split_items(const Slot& S, const GraphDev& G, int t, int nb0,
+                                            int items, int (&lab)[U], int (&kind)[U],
+                                            int (&deg)[U], int (&f1)[U]) {
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int i = t * SPLIT_TILE + u * NT_TILE + threadIdx.x;
+    lab[u] = -1;
+    kind[u] = SPLIT_NONE;
+    deg[u] = 0;
+    f1[u] = 0;
+    if (i < nb0) {
+      lab[u] = S.batch[i];
+      kind[u] = SPLIT_REG;  // goal or regular: decided by the node below
+    } else if (i < items) {
+      const int j = i - nb0, st = S.tie_st[j];
+      if (st == 1) {
+        lab[u] = S.tie_lab[j];
+        kind[u] = SPLIT_REG;
+      } else if (st == 2) {
+        lab[u] = S.tie_lab[j];
+        f1[u] = S.tie_f1[j];
+        kind[u] = SPLIT_BACK;
+      }
     }
+  }
+  int v[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) v[u] = kind[u] == SPLIT_REG ? S.Lnode[lab[u]] : 0;
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    if (kind[u] != SPLIT_REG) continue;
+    if (v[u] == S.goal) kind[u] = SPLIT_GOAL;
+    else deg[u] = (int)(G.row_ptr[v[u] + 1] - G.row_ptr[v[u]]);
+  }
+}
+
+__device__ __forceinline__ int split_items_total(const Slot& S) {
+  return S.pop_nb + (S.tie_mode ? min(S.tie_n, S.tie_cap) : 0);
+}
+
+__global__ __launch_bounds__(NT_TILE) void k_split_count(Slot* slots, GraphDev G) {
+  Slot* Sp = &slots[blockIdx.y];
+  const Slot S = *Sp;
+  if (S.status != S_RUN) return;
+  constexpr int U = SPLIT_TILE / NT_TILE;
+  __shared__ int red[SPLIT_WORDS][GP_WAVES];
+  const int wave = threadIdx.x / WAVE, lane = lane_id();
+  const int nb0 = S.pop_nb, items = split_items_total(S);
+  const int nt = (items + SPLIT_TILE - 1) / SPLIT_TILE;
+  for (int t = blockIdx.x; t < nt; t += gridDim.x) {
+    int lab[U], kind[U], deg[U], f1[U];
+    split_items<U>(S, G, t, nb0, items, lab, kind, deg, f1);
+    int c[SPLIT_WORDS] = {0, 0, 0, 0, INT32_MAX};
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      c[0] += kind[u] == SPLIT_GOAL;
+      c[1] += kind[u] == SPLIT_REG;
+      c[2] += deg[u];
+      c[3] += kind[u] == SPLIT_BACK;
+      if (kind[u] == SPLIT_BACK) c[4] = min(c[4], f1[u]);
+    }
+#pragma unroll
+    for (int w = 0; w < 4; ++w) c[w] = wave_sum(c[w]);
+    c[4] = wave_min(c[4]);
+    if (lane == 0)
+#pragma unroll
+      for (int w = 0; w < SPLIT_WORDS; ++w) red[w][wave] = c[w];
+    __syncthreads();
+    if (threadIdx.x < SPLIT_WORDS) {
+      const int w = threadIdx.x;
+      int a = w == 4 ? INT32_MAX : 0;
+#pragma unroll
+      for (int x = 0; x < GP_WAVES; ++x) a = w == 4 ? min(a, red[w][x]) : a + red[w][x];
+      S.split_tile[(size_t)SPLIT_WORDS * t + w] = a;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(NT_TILE) void k_split_scan(Slot* slots, GraphDev G) {
+  Slot* Sp = &slots[blockIdx.y];
+  const Slot S = *Sp;
+  if (S.status != S_RUN) return;
+  constexpr int U = SPLIT_TILE / NT_TILE;
+  __shared__ int red[SPLIT_WORDS][GP_WAVES];
+  __shared__ int cw[4][U][GP_WAVES];  // per (kind, chunk, wave): goal, regular, degree sum, back
+  const int wave = threadIdx.x / WAVE, lane = lane_id();
+  const int nb0 = S.pop_nb, keep0 = S.pop_keep, items = split_items_total(S);
+  const int nt = (items + SPLIT_TILE - 1) / SPLIT_TILE;
+  const int32_t* TT = S.split_tile;
+  if (blockIdx.x == 0) {  // totals (no other workgroup reads the fields written here)
+    int c[SPLIT_WORDS] = {0, 0, 0, 0, INT32_MAX};
+    for (int x = threadIdx.x; x < nt; x += NT_TILE) {
+#pragma unroll
+      for (int w = 0; w < 4; ++w) c[w] += TT[(size_t)SPLIT_WORDS * x + w];
+      c[4] = min(c[4], TT[(size_t)SPLIT_WORDS * x + 4]);
+    }
+#pragma unroll
+    for (int w = 0; w < 4; ++w) c[w] = wave_sum(c[w]);
+    c[4] = wave_min(c[4]);
+    if (lane == 0)
+#pragma unroll
+      for (int w = 0; w < SPLIT_WORDS; ++w) red[w][wave] = c[w];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int a[SPLIT_WORDS] = {0, 0, 0, 0, INT32_MAX};
+#pragma unroll
+      for (int x = 0; x < GP_WAVES; ++x) {
+#pragma unroll
+        for (int w = 0; w < 4; ++w) a[w] += red[w][x];
+        a[4] = min(a[4], red[4][x]);
+      }
+      const int nb = a[0] + a[1], keep_n = keep0 + a[3];
+      Sp->goal_n = a[0];
+      Sp->reg_n = a[1];
+      Sp->cand_n = a[2];
+      Sp->batch_n = nb;
+      Sp->keep_n = keep_n;
+      if (a[1] <= S.batch_cap) S.reg_off[a[1]] = a[2];
+      if (a[4] != INT32_MAX) atomicMin(&Sp->lo_next, a[4]);
+      Sp->st[ST_POPS] += nb;
+      Sp->st[ST_GOAL_POPS] += a[0];
+      if (nb > S.batch_cap || a[2] > S.cand_cap || a[0] > S.cand_cap || keep_n > S.open_cap) {
+        Sp->status = S_OVERFLOW;
+        Sp->err_line = __LINE__;
+      } else if (nb == 0 && S.far_n == 0) {
+        Sp->status = S_DONE;  // no live label left in OPEN
+      }
+    }
+    __syncthreads();
+  }
+  int32_t* KF = pick(S.open_f1, S.open_sel ^ 1);
+  int32_t* KL = pick(S.open_lab, S.open_sel ^ 1);
+  for (int t = blockIdx.x; t < nt; t += gridDim.x) {
+    int lab[U], kind[U], deg[U], f1[U];
+    split_items<U>(S, G, t, nb0, items, lab, kind, deg, f1);
+    int b[4] = {0, 0, 0, 0};  // the tiles before this one
+    for (int x = threadIdx.x; x < t; x += NT_TILE)
+#pragma unroll
+      for (int w = 0; w < 4; ++w) b[w] += TT[(size_t)SPLIT_WORDS * x + w];
+#pragma unroll
+    for (int w = 0; w < 4; ++w) b[w] = wave_sum(b[w]);
+    uint64_t mg[U], mr[U], mk[U];
+    int incl[U];  // inclusive prefix of the out-degrees over the wave, per chunk
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      mg[u] = ballot(kind[u] == SPLIT_GOAL);
+      mr[u] = ballot(kind[u] == SPLIT_REG);
+      mk[u] = ballot(kind[u] == SPLIT_BACK);
+      int x = deg[u];
+#pragma unroll
+      for (int o = 1; o < WAVE; o <<= 1) {
+        const int y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+      }
+      incl[u] = x;
+    }
+    if (lane == WAVE - 1) {
+#pragma unroll
+      for (int w = 0; w < 4; ++w) red[w][wave] = b[w];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        cw[0][u][wave] = __popcll(mg[u]);
+        cw[1][u][wave] = __popcll(mr[u]);
+        cw[2][u][wave] = incl[u];
+        cw[3][u][wave] = __popcll(mk[u]);
+      }
+    }
+    __syncthreads();
+    int o[4];
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      o[w] = 0;
+#pragma unroll
+      for (int x = 0; x < GP_WAVES; ++x) o[w] += red[w][x];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      int p[4];
+#pragma unroll
+      for (int w = 0; w < 4; ++w) {
+        p[w] = o[w];
+#pragma unroll
+        for (int x = 0; x < GP_WAVES; ++x) {
+          if (x < wave) p[w] += cw[w][u][x];
+          o[w] += cw[w][u][x];
+        }
+      }
+      if (kind[u] == SPLIT_GOAL) {
+        const int pg = p[0] + rank_below(mg[u]);
+        if (pg < S.batch_cap) S.goal_lab[pg] = lab[u];
+        if (pg < S.cand_cap) S.c_rej[pg] = 0;  // goal-step flag of this goal label
+      } else if (kind[u] == SPLIT_REG) {
+        const int pr = p[1] + rank_below(mr[u]);
+        if (pr < S.batch_cap) {
+          S.reg[pr] = lab[u];
+          S.reg_off[pr] = p[2] + incl[u] - deg[u];
+          S.reg_kill[pr] = 0;
+        }
+      } else if (kind[u] == SPLIT_BACK) {
+        const int pk = keep0 + p[3] + rank_below(mk[u]);
+        if (pk < S.open_cap) {
+          KF[pk] = f1[u];
+          KL[pk] = lab[u];
+        }
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -2026,7 +2140,7 @@ __global__ void k_step_end(Slot* slots, int nslots) {
 // ---------------------------------------------------------------- launchers
 const char* const kStepKernelNames[kStepKernels] = {
     "k_far_hist",      "k_far_move",      "k_open_hist",     "k_open_threshold", "k_open_scatter",
-    "k_batch_finalize", "k_goal_pairs",   "k_goal_merge",    "k_popcheck",       "k_expand",
+    "k_batch_finalize", "k_split_count",  "k_split_scan",    "k_goal_pairs",   "k_goal_merge",    "k_popcheck",       "k_expand",
     "k_group_count",   "k_group_offsets", "k_group_scatter", "k_group_process",  "k_group_pairs",
     "k_group_finish",  "k_accept_count",  "k_accept_scan",   "k_insert",         "k_pfilter",
     "k_step_end"};
@@ -2048,6 +2162,8 @@ static void launch_step_dm(const StepArgs& a, hipStream_t st, hipEvent_t* ev, ui
   mark(); hipLaunchKernelGGL(k_open_threshold, per, dim3(NT_SLOT), 0, st, a.slots, a.hist);
   mark(); hipLaunchKernelGGL(k_open_scatter, tiled, dim3(NT_TILE), 0, st, a.slots);
   mark(); hipLaunchKernelGGL(k_batch_finalize<DM>, per, dim3(NT_SLOT), 0, st, a.slots, a.G);
+  mark(); hipLaunchKernelGGL(k_split_count, tiled, dim3(NT_TILE), 0, st, a.slots, a.G);
+  mark(); hipLaunchKernelGGL(k_split_scan, tiled, dim3(NT_TILE), 0, st, a.slots, a.G);
   mark(); hipLaunchKernelGGL(k_goal_pairs<DM>, tiled, dim3(NT_TILE), 0, st, a.slots);
   mark(); hipLaunchKernelGGL(k_goal_merge<DM>, per, dim3(NT_SLOT), 0, st, a.slots);
   mark(); hipLaunchKernelGGL(k_popcheck<DM>, tiled, dim3(NT_TILE), 0, st, a.slots, a.G);
