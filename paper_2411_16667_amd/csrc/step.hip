@@ -1137,6 +1137,32 @@ __device__ bool tile_vs_front(FrontChunk<DM>& ch, const int32_t* Pg, int Pc, int
   return dom;
 }
 
+// Two vectors per thread against the staged chunks (each row read from LDS
+// serves both); `dom*` accumulate across calls.
+template <int DM>
+__device__ void tile_vs_front2(FrontChunk<DM>& ch, const int32_t* Pg, int Pc, int np, int d,
+                               int c0, int c1, bool have0, bool have1,
+                               const int4 (&F0)[FrontChunk<DM>::NW],
+                               const int4 (&F1)[FrontChunk<DM>::NW], bool& dom0, bool& dom1) {
+  for (int c = c0; c < c1; ++c) {
+    const int p0 = c * PCH;
+    __syncthreads();
+    stage_chunk<DM>(ch, Pg, Pc, p0, min(PCH, np - p0), d);
+    __syncthreads();
+    if ((have0 && !dom0) || (have1 && !dom1)) {
+      int a0 = -1, a1 = -1;
+#pragma unroll 8
+      for (int q = 0; q < PCH; ++q) {
+        a0 &= or_diff<DM>(ch.w[q], F0);
+        a1 &= or_diff<DM>(ch.w[q], F1);
+      }
+      dom0 = dom0 || a0 >= 0;
+      dom1 = dom1 || a1 >= 0;
+    }
+    if (__syncthreads_and((!have0 || dom0) && (!have1 || dom1))) break;
+  }
+}
+
 __device__ __forceinline__ int chunks_per_item(int nlt, int npc) {
   return max(1, (nlt * npc + (int)gridDim.x - 1) / (int)gridDim.x);
 }
@@ -1271,7 +1297,8 @@ __global__ __launch_bounds__(NT_TILE) void k_expand(Slot* slots, GraphDev G) {
 // it rejected or pruned has a g no better than its own, so the goal front
 // dominates that label's F as well.  Weak dominance: a completion of F = p
 // cannot improve on p.  Work items are (label tile, front chunk) pairs so that
-// a large front spreads over the whole chip.
+// a large front spreads over the whole chip; a label tile holds two labels per
+// thread, so each front row read from LDS serves two tests.
 template <int DM>
 __global__ __launch_bounds__(NT_TILE) void k_pfilter(Slot* slots, GraphDev G) {
   Slot* Sp = &slots[blockIdx.y];
@@ -1281,7 +1308,8 @@ __global__ __launch_bounds__(NT_TILE) void k_pfilter(Slot* slots, GraphDev G) {
   if (R == 0 || np == 0) return;
   if (blockIdx.x == 0 && threadIdx.x == 0)
     atomicAdd((unsigned long long*)&Sp->st[ST_PPAIRS], (unsigned long long)((int64_t)R * (np - S.P_dead)));
-  const int nlt = (R + NT_TILE - 1) / NT_TILE, npc = (np + PCH - 1) / PCH;
+  constexpr int LT = 2 * NT_TILE;  // labels per tile: two per thread
+  const int nlt = (R + LT - 1) / LT, npc = (np + PCH - 1) / PCH;
   const int cpi = chunks_per_item(nlt, npc), ngrp = (npc + cpi - 1) / cpi;
   const int ntiles = nlt * ngrp;
   if ((int)blockIdx.x >= ntiles) return;
@@ -1291,26 +1319,34 @@ __global__ __launch_bounds__(NT_TILE) void k_pfilter(Slot* slots, GraphDev G) {
   const int32_t* Pg = pick(S.Pg, S.P_sel);
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const int lt = t / ngrp, gi = t - lt * ngrp;
-    const int i = lt * NT_TILE + threadIdx.x;
-    const int id = base + i;
-    const bool have = i < R && S.Lstate[id] != L_DEAD;
-    int32_t x[NW * 4];
+    int ii[2];
+    bool have[2], dom[2] = {false, false};
+    int4 F[2][NW];
 #pragma unroll
-    for (int k = 0; k < NW * 4; ++k) x[k] = 0;
-    if (have) {
-      const int v = S.Lnode[id];
+    for (int h = 0; h < 2; ++h) {
+      ii[h] = lt * LT + h * NT_TILE + threadIdx.x;
+      const int id = base + ii[h];
+      have[h] = ii[h] < R && S.Lstate[id] != L_DEAD;
+      int32_t x[NW * 4];
 #pragma unroll
-      for (int k = 0; k < NW * 4; ++k)
-        x[k] = k < d ? S.Lg[(size_t)k * pc + id] + S.h[(size_t)k * n + v] : 0;
+      for (int k = 0; k < NW * 4; ++k) x[k] = 0;
+      if (have[h]) {
+        const int v = S.Lnode[id];
+#pragma unroll
+        for (int k = 0; k < NW * 4; ++k)
+          x[k] = k < d ? S.Lg[(size_t)k * pc + id] + S.h[(size_t)k * n + v] : 0;
+      }
+#pragma unroll
+      for (int w = 0; w < NW; ++w) F[h][w] = make_int4(x[4 * w], x[4 * w + 1], x[4 * w + 2], x[4 * w + 3]);
     }
-    int4 F[NW];
+    tile_vs_front2<DM>(ch, Pg, Pc, np, d, gi * cpi, min(npc, (gi + 1) * cpi), have[0], have[1],
+                       F[0], F[1], dom[0], dom[1]);
 #pragma unroll
-    for (int w = 0; w < NW; ++w) F[w] = make_int4(x[4 * w], x[4 * w + 1], x[4 * w + 2], x[4 * w + 3]);
-    const bool dom = tile_vs_front<DM>(ch, Pg, Pc, np, d, gi * cpi, min(npc, (gi + 1) * cpi), have, F);
-    if (have && dom) {
-      S.Lstate[id] = L_DEAD;
-      S.fw[S.c_fslot[S.order[i]]] = FW_REMOVED;  // leaves its node's frontier
-    }
+    for (int h = 0; h < 2; ++h)
+      if (have[h] && dom[h]) {
+        S.Lstate[base + ii[h]] = L_DEAD;
+        S.fw[S.c_fslot[S.order[ii[h]]]] = FW_REMOVED;  // leaves its node's frontier
+      }
   }
 }
 
