@@ -1117,28 +1117,12 @@ __global__ __launch_bounds__(NT_SLOT) void k_goal_merge(Slot* slots) {
   }
 }
 
-// One tile of labels (one per thread, F packed as int4 words) against the front
-// chunks c0 .. c1-1, each staged in LDS in turn; stops early once every label
-// of the tile is dominated.  Returns whether this thread's label is dominated.
-// Work items are (label tile, run of chunks) pairs with runs sized so that the
-// items about fill the grid: a label's F is formed once per run.
-template <int DM>
-__device__ bool tile_vs_front(FrontChunk<DM>& ch, const int32_t* Pg, int Pc, int np, int d,
-                              int c0, int c1, bool have, const int4 (&F)[FrontChunk<DM>::NW]) {
-  bool dom = false;
-  for (int c = c0; c < c1; ++c) {
-    const int p0 = c * PCH;
-    __syncthreads();
-    stage_chunk<DM>(ch, Pg, Pc, p0, min(PCH, np - p0), d);
-    __syncthreads();
-    if (have && !dom) dom = chunk_dominates<DM>(ch, F);
-    if (__syncthreads_and(!have || dom)) break;
-  }
-  return dom;
-}
-
-// Two vectors per thread against the staged chunks (each row read from LDS
-// serves both); `dom*` accumulate across calls.
+// A tile of labels, two per thread (F packed as int4 words), against the front
+// chunks c0 .. c1-1, each staged in LDS in turn (each row read from LDS serves
+// both of a thread's tests); stops early once every label of the tile is
+// dominated, and sets dom0 / dom1 for this thread's labels.  Work items are
+// (label tile, run of chunks) pairs with runs sized so that the items about
+// fill the grid: a label's F is formed once per run.
 template <int DM>
 __device__ void tile_vs_front2(FrontChunk<DM>& ch, const int32_t* Pg, int Pc, int np, int d,
                                int c0, int c1, bool have0, bool have1,
@@ -1181,7 +1165,8 @@ __global__ __launch_bounds__(NT_TILE) void k_popcheck(Slot* slots, GraphDev G) {
   if (S.status != S_RUN) return;
   const int R = S.reg_n, np = S.P_n;
   if (R == 0 || np == 0) return;
-  const int nlt = (R + NT_TILE - 1) / NT_TILE, npc = (np + PCH - 1) / PCH;
+  constexpr int LT = 2 * NT_TILE;  // labels per tile: two per thread
+  const int nlt = (R + LT - 1) / LT, npc = (np + PCH - 1) / PCH;
   const int cpi = chunks_per_item(nlt, npc), ngrp = (npc + cpi - 1) / cpi;
   const int ntiles = nlt * ngrp;
   if ((int)blockIdx.x >= ntiles) return;
@@ -1194,23 +1179,30 @@ __global__ __launch_bounds__(NT_TILE) void k_popcheck(Slot* slots, GraphDev G) {
   int killed = 0;
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const int lt = t / ngrp, gi = t - lt * ngrp;
-    const int i = lt * NT_TILE + threadIdx.x;
-    const bool have = i < R && !S.reg_kill[i];
-    int lab = 0;
-    int32_t f[NW * 4];
-#pragma unroll
-    for (int k = 0; k < NW * 4; ++k) f[k] = 0;
+    int ii[2], lab[2] = {0, 0};
+    bool have[2], dom[2] = {false, false};
+    int4 F[2][NW];
     __syncthreads();  // the previous item is done with sh_first
     if (threadIdx.x == 0) sh_seq = INT32_MAX;
     __syncthreads();
     int seq = INT32_MAX;
-    if (have) {
-      lab = S.reg[i];
-      seq = S.Lpseq[lab];
-      const int v = S.Lnode[lab];
 #pragma unroll
-      for (int k = 0; k < NW * 4; ++k)
-        f[k] = k < d ? S.Lg[(size_t)k * pc + lab] + S.h[(size_t)k * n + v] : 0;
+    for (int h = 0; h < 2; ++h) {
+      ii[h] = lt * LT + h * NT_TILE + threadIdx.x;
+      have[h] = ii[h] < R && !S.reg_kill[ii[h]];
+      int32_t f[NW * 4];
+#pragma unroll
+      for (int k = 0; k < NW * 4; ++k) f[k] = 0;
+      if (have[h]) {
+        lab[h] = S.reg[ii[h]];
+        seq = min(seq, S.Lpseq[lab[h]]);
+        const int v = S.Lnode[lab[h]];
+#pragma unroll
+        for (int k = 0; k < NW * 4; ++k)
+          f[k] = k < d ? S.Lg[(size_t)k * pc + lab[h]] + S.h[(size_t)k * n + v] : 0;
+      }
+#pragma unroll
+      for (int w = 0; w < NW; ++w) F[h][w] = make_int4(f[4 * w], f[4 * w + 1], f[4 * w + 2], f[4 * w + 3]);
     }
     seq = wave_min(seq);
     if (lane_id() == 0) atomicMin(&sh_seq, seq);
@@ -1224,15 +1216,15 @@ __global__ __launch_bounds__(NT_TILE) void k_popcheck(Slot* slots, GraphDev G) {
       sh_first = lo_i;
     }
     __syncthreads();
-    int4 F[NW];
-#pragma unroll
-    for (int w = 0; w < NW; ++w) F[w] = make_int4(f[4 * w], f[4 * w + 1], f[4 * w + 2], f[4 * w + 3]);
     const int c0 = max(gi * cpi, sh_first / PCH), c1 = min(npc, (gi + 1) * cpi);
-    const bool dom = c0 < c1 && tile_vs_front<DM>(ch, Pg, Pc, np, d, c0, c1, have, F);
-    if (have && dom && atomicExch(&S.reg_kill[i], 1) == 0) {
-      S.Lstate[lab] = L_DEAD;
-      ++killed;
-    }
+    if (c0 < c1)
+      tile_vs_front2<DM>(ch, Pg, Pc, np, d, c0, c1, have[0], have[1], F[0], F[1], dom[0], dom[1]);
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+      if (have[h] && dom[h] && atomicExch(&S.reg_kill[ii[h]], 1) == 0) {
+        S.Lstate[lab[h]] = L_DEAD;
+        ++killed;
+      }
   }
   const int64_t k64 = wave_sum64(killed);
   if (lane_id() == 0 && k64) {
