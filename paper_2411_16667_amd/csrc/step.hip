@@ -275,11 +275,22 @@ __global__ __launch_bounds__(NT_TILE) void k_open_hist(Slot* slots, int32_t* his
   const int32_t* F1 = pick(S.open_f1, S.open_sel);
   const int32_t* LB = pick(S.open_lab, S.open_sel);
   const int lo = S.lo;
-  for (int i = blockIdx.x * NT_TILE + threadIdx.x; i < n; i += gridDim.x * NT_TILE) {
-    if (S.Lstate[LB[i]] == L_OPEN) {
-      const int b = min(max(F1[i] - lo, 0), NB - 1);
-      atomicAdd(&h[b], 1);
+  constexpr int HU = 4;  // entries per thread in flight
+  const int stride = gridDim.x * NT_TILE;
+  for (int i0 = blockIdx.x * NT_TILE + threadIdx.x; i0 < n; i0 += HU * stride) {
+    int lab[HU], f[HU];
+#pragma unroll
+    for (int u = 0; u < HU; ++u) {
+      const int i = i0 + u * stride;
+      lab[u] = i < n ? LB[i] : -1;
+      f[u] = i < n ? F1[i] : 0;
     }
+    bool live[HU];
+#pragma unroll
+    for (int u = 0; u < HU; ++u) live[u] = lab[u] >= 0 && S.Lstate[lab[u]] == L_OPEN;
+#pragma unroll
+    for (int u = 0; u < HU; ++u)
+      if (live[u]) atomicAdd(&h[min(max(f[u] - lo, 0), NB - 1)], 1);
   }
   __syncthreads();
   int32_t* gh = hist + (size_t)blockIdx.y * NB;
@@ -1349,14 +1360,24 @@ __global__ __launch_bounds__(NT_TILE) void k_group_count(Slot* slots) {
   if (S.status != S_RUN) return;
   const int M = S.cand_n;
   for (int f = blockIdx.x * NT_TILE + threadIdx.x; f < M; f += gridDim.x * NT_TILE) {
-    if (!S.c_keep[f]) continue;
-    const int v = S.c_node[f];
-    const int r = atomicAdd(&S.grp_cnt[v], 1);
-    S.c_rank[f] = r;
-    if (r == 0) {
-      const int gid = atomicAdd(&Sp->ngroups, 1);
-      S.grp_node[gid] = v;
-      S.grp_id[v] = gid;
+    int v = 0, r = -1;
+    if (S.c_keep[f]) {
+      v = S.c_node[f];
+      r = atomicAdd(&S.grp_cnt[v], 1);
+      S.c_rank[f] = r;
+    }
+    // a node's first candidate opens its group: one group-count atomic per wave
+    const uint64_t m = ballot(r == 0);
+    if (m) {
+      const int leader = __ffsll((long long)m) - 1;
+      int gb = 0;
+      if (lane_id() == leader) gb = atomicAdd(&Sp->ngroups, __popcll(m));
+      gb = __shfl(gb, leader);
+      if (r == 0) {
+        const int gid = gb + rank_below(m);
+        S.grp_node[gid] = v;
+        S.grp_id[v] = gid;
+      }
     }
   }
 }
@@ -2178,6 +2199,9 @@ static void launch_step_dm(const StepArgs& a, hipStream_t st, hipEvent_t* ev, ui
   const dim3 tiled(a.gx, a.nslots), per(a.nslots);
   const dim3 cand(a.gc, a.nslots);                    // per-candidate loops
   const dim3 refill(std::min(a.gx, 256), a.nslots);   // far-tier kernels: idle on most steps
+  // OPEN scans: several entries per thread, so that the per-workgroup appends
+  // (one atomic per counter and workgroup) stay few
+  const dim3 scan(std::min(a.gx, 256), a.nslots);
   int i = 0;
   auto mark = [&]() {
     const bool need = i == kStepKernels || ((mask >> i) & 1u) || (i > 0 && ((mask >> (i - 1)) & 1u));
@@ -2186,9 +2210,9 @@ static void launch_step_dm(const StepArgs& a, hipStream_t st, hipEvent_t* ev, ui
   };
   mark(); hipLaunchKernelGGL(k_far_hist, refill, dim3(NT_TILE), 0, st, a.slots, a.hist);
   mark(); hipLaunchKernelGGL(k_far_move, refill, dim3(NT_TILE), 0, st, a.slots);
-  mark(); hipLaunchKernelGGL(k_open_hist, tiled, dim3(NT_TILE), 0, st, a.slots, a.hist);
+  mark(); hipLaunchKernelGGL(k_open_hist, scan, dim3(NT_TILE), 0, st, a.slots, a.hist);
   mark(); hipLaunchKernelGGL(k_open_threshold, per, dim3(NT_SLOT), 0, st, a.slots, a.hist);
-  mark(); hipLaunchKernelGGL(k_open_scatter, tiled, dim3(NT_TILE), 0, st, a.slots);
+  mark(); hipLaunchKernelGGL(k_open_scatter, scan, dim3(NT_TILE), 0, st, a.slots);
   mark(); hipLaunchKernelGGL(k_batch_finalize<DM>, per, dim3(NT_SLOT), 0, st, a.slots, a.G);
   mark(); hipLaunchKernelGGL(k_split_count, tiled, dim3(NT_TILE), 0, st, a.slots, a.G);
   mark(); hipLaunchKernelGGL(k_split_scan, tiled, dim3(NT_TILE), 0, st, a.slots, a.G);
