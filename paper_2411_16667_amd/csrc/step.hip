@@ -1701,6 +1701,7 @@ __global__ __launch_bounds__(NT_TILE) void k_group_pairs(Slot* slots) {
   const int d = S.d, cc = S.cand_cap;
   int32_t* fw = S.fw;
   int64_t pruned = 0;
+  __shared__ int4 cstage[GP_WAVES][WAVE][FrontChunk<DM>::NW];  // per wave: its candidate tile
   for (int tt = blockIdx.x * GP_WAVES + wave; tt < total; tt += gridDim.x * GP_WAVES) {
     int lo_i = 0, hi_i = nbig - 1;  // big group owning tile tt
     while (lo_i < hi_i) {
@@ -1764,10 +1765,26 @@ __global__ __launch_bounds__(NT_TILE) void k_group_pairs(Slot* slots) {
       int pacc[BT_U];
 #pragma unroll
       for (int u = 0; u < BT_U; ++u) pacc[u] = 0;
+      // the wave's candidates go through LDS: one broadcast read per candidate
+      // on the LDS pipe instead of DM lane reads on the vector ALU
+      constexpr int NW = FrontChunk<DM>::NW;
+      {
+        int32_t x[NW * 4];
+#pragma unroll
+        for (int k = 0; k < NW * 4; ++k) x[k] = k < DM ? cj[k] : 0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w)
+          cstage[wave][lane][w] = make_int4(x[4 * w], x[4 * w + 1], x[4 * w + 2], x[4 * w + 3]);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");  // read across lanes below
+#pragma unroll 4
       for (int jj = 0; jj < nj; ++jj) {
+        int4 cw[NW];
+#pragma unroll
+        for (int w = 0; w < NW; ++w) cw[w] = cstage[wave][jj][w];
         int32_t c[DM];
 #pragma unroll
-        for (int kk = 0; kk < DM; ++kk) c[kk] = bcast(cj[kk], jj);
+        for (int kk = 0; kk < DM; ++kk) c[kk] = comp(cw[kk >> 2], kk & 3);
         int allneg = -1;
 #pragma unroll
         for (int u = 0; u < BT_U; ++u) {
