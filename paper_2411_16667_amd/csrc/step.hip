@@ -1492,7 +1492,6 @@ __device__ __forceinline__ bool frontier_dest(Slot* Sp, const Slot& S, const Nod
 // Rejections live in a wave-uniform 64-bit mask; all compares are branch-free.
 constexpr int U = 4;  // frontier entries per lane per pass
 
-__device__ __forceinline__ int bcast(int v, int lane) { return __builtin_amdgcn_readlane(v, lane); }
 
 // For candidate c and frontier entry e (components k >= d are 0 on both
 // sides; costs lie in [0, INT32_MAX), so no difference overflows):
@@ -1540,6 +1539,8 @@ __global__ __launch_bounds__(NT_TILE) void k_group_process(Slot* slots) {
   const int d = S.d, cc = S.cand_cap;
   int32_t* fw = S.fw;
   int64_t gpairs = 0, fpairs = 0, fbytes = 0, pruned = 0;
+  __shared__ int4 cstage[GP_WAVES][WAVE][FrontChunk<DM>::NW];  // per wave: its group's candidates
+  __shared__ int astage[GP_WAVES][WAVE];                          // and their arcs
   for (int si = blockIdx.x * GP_WAVES + wave; si < nsmall; si += gridDim.x * GP_WAVES) {
     const int gid = S.small_list[si];
     const int v = S.grp_node[gid];
@@ -1556,19 +1557,35 @@ __global__ __launch_bounds__(NT_TILE) void k_group_process(Slot* slots) {
     // first frontier pass in flight while the candidates are resolved
     int32_t sv[U][DM], slab[U];
     load_entries<DM>(fw, nr, d, 0, sv, slab);
+    // the group's candidates go through LDS: one broadcast read per candidate
+    // on the LDS pipe instead of DM lane reads on the vector ALU
+    constexpr int NW = FrontChunk<DM>::NW;
+    {
+      int32_t x[NW * 4];
+#pragma unroll
+      for (int q = 0; q < NW * 4; ++q) x[q] = q < DM ? ci[q] : 0;
+#pragma unroll
+      for (int w = 0; w < NW; ++w)
+        cstage[wave][lane][w] = make_int4(x[4 * w], x[4 * w + 1], x[4 * w + 2], x[4 * w + 3]);
+      astage[wave][lane] = ai;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");  // read across lanes below
     // ---- A. intra-group resolution
     bool rej = false;
     if (k > 1) {
       gpairs += (int64_t)k * (k - 1);
       for (int jj = 0; jj < k; ++jj) {
+        int4 cw[NW];
+#pragma unroll
+        for (int w = 0; w < NW; ++w) cw[w] = cstage[wave][jj][w];
         bool le = true, eq = true;
 #pragma unroll
         for (int kk = 0; kk < DM; ++kk) {
-          const int b = bcast(ci[kk], jj);
+          const int b = comp(cw[kk >> 2], kk & 3);
           le = le & (b <= ci[kk]);
           eq = eq & (b == ci[kk]);
         }
-        const int aj = bcast(ai, jj);
+        const int aj = astage[wave][jj];
         rej = rej | (jj != lane && le && (!eq || aj < ai));
       }
     }
@@ -1602,9 +1619,12 @@ __global__ __launch_bounds__(NT_TILE) void k_group_process(Slot* slots) {
       }
       for (uint64_t m = surv & ~rejm; m; m &= m - 1) {
         const int jj = __ffsll((long long)m) - 1;
+        int4 cw[NW];
+#pragma unroll
+        for (int w = 0; w < NW; ++w) cw[w] = cstage[wave][jj][w];
         int32_t c[DM];
 #pragma unroll
-        for (int kk = 0; kk < DM; ++kk) c[kk] = bcast(ci[kk], jj);
+        for (int kk = 0; kk < DM; ++kk) c[kk] = comp(cw[kk >> 2], kk & 3);
         int allneg = -1;
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -1702,6 +1722,7 @@ __global__ __launch_bounds__(NT_TILE) void k_group_pairs(Slot* slots) {
   int32_t* fw = S.fw;
   int64_t pruned = 0;
   __shared__ int4 cstage[GP_WAVES][WAVE][FrontChunk<DM>::NW];  // per wave: its candidate tile
+  __shared__ int2 fstage[GP_WAVES][WAVE];                         // and their ids and arcs
   for (int tt = blockIdx.x * GP_WAVES + wave; tt < total; tt += gridDim.x * GP_WAVES) {
     int lo_i = 0, hi_i = nbig - 1;  // big group owning tile tt
     while (lo_i < hi_i) {
@@ -1726,6 +1747,19 @@ __global__ __launch_bounds__(NT_TILE) void k_group_pairs(Slot* slots) {
 #pragma unroll
     for (int kk = 0; kk < DM; ++kk) cj[kk] = (hj && kk < d) ? S.c_g[(size_t)kk * cc + fj] : 0;
     const int nj = __builtin_amdgcn_readfirstlane(min(WAVE, k - J * WAVE));  // wave-uniform
+    // the wave's candidates go through LDS: one broadcast read per candidate
+    // on the LDS pipe instead of DM lane reads on the vector ALU
+    constexpr int NW = FrontChunk<DM>::NW;
+    {
+      int32_t x[NW * 4];
+#pragma unroll
+      for (int q = 0; q < NW * 4; ++q) x[q] = q < DM ? cj[q] : 0;
+#pragma unroll
+      for (int w = 0; w < NW; ++w)
+        cstage[wave][lane][w] = make_int4(x[4 * w], x[4 * w + 1], x[4 * w + 2], x[4 * w + 3]);
+      fstage[wave][lane] = make_int2(fj, aj);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");  // read across lanes below
     if (is_a) {
       const int i = I * WAVE + lane;
       const bool hi = i < k;
@@ -1736,16 +1770,18 @@ __global__ __launch_bounds__(NT_TILE) void k_group_pairs(Slot* slots) {
       for (int kk = 0; kk < DM; ++kk) ci[kk] = (hi && kk < d) ? S.c_g[(size_t)kk * cc + fi] : 0;
       bool rej = false;
       for (int jj = 0; jj < nj; ++jj) {
+        int4 cw[NW];
+#pragma unroll
+        for (int w = 0; w < NW; ++w) cw[w] = cstage[wave][jj][w];
         bool le = true, eq = true;
 #pragma unroll
         for (int kk = 0; kk < DM; ++kk) {
-          const int b = bcast(cj[kk], jj);
+          const int b = comp(cw[kk >> 2], kk & 3);
           le = le & (b <= ci[kk]);
           eq = eq & (b == ci[kk]);
         }
-        const int fb = bcast(fj, jj);
-        const int ab = bcast(aj, jj);
-        rej = rej | (fb != fi && le && (!eq || ab < ai));
+        const int2 fa = fstage[wave][jj];
+        rej = rej | (fa.x != fi && le && (!eq || fa.y < ai));
       }
       if (hi && rej) S.c_rej[fi] = 1;
     } else {
@@ -1765,18 +1801,6 @@ __global__ __launch_bounds__(NT_TILE) void k_group_pairs(Slot* slots) {
       int pacc[BT_U];
 #pragma unroll
       for (int u = 0; u < BT_U; ++u) pacc[u] = 0;
-      // the wave's candidates go through LDS: one broadcast read per candidate
-      // on the LDS pipe instead of DM lane reads on the vector ALU
-      constexpr int NW = FrontChunk<DM>::NW;
-      {
-        int32_t x[NW * 4];
-#pragma unroll
-        for (int k = 0; k < NW * 4; ++k) x[k] = k < DM ? cj[k] : 0;
-#pragma unroll
-        for (int w = 0; w < NW; ++w)
-          cstage[wave][lane][w] = make_int4(x[4 * w], x[4 * w + 1], x[4 * w + 2], x[4 * w + 3]);
-      }
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");  // read across lanes below
 #pragma unroll 4
       for (int jj = 0; jj < nj; ++jj) {
         int4 cw[NW];
