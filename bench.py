@@ -44,12 +44,12 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200, help="timed label steps")
-    ap.add_argument("--warmup", type=int, default=1100,
-                    help="untimed label steps before timing (1100 steps of B = 16384 take the "
-                         "search about 19M labels deep)")
-    ap.add_argument("--batch-width", type=int, default=16384,
-                    help="labels popped per step (the widest batch the library takes; a sweep "
-                         "at this depth gives 13.2M pops/s at 8192 and 16.8M at 16384)")
+    ap.add_argument("--warmup", type=int, default=480,
+                    help="untimed label steps before timing (480 steps of B = 32768 and the "
+                         "timed steps take the search about 20M labels deep)")
+    ap.add_argument("--batch-width", type=int, default=32768,
+                    help="labels popped per step (the widest batch the library takes; at this "
+                         "depth 16384 gives 21.8M pops/s and 32768 about 25M)")
     ap.add_argument("--profile-steps", type=int, default=50,
                     help="last warm-up steps with every kernel timed (per-kernel table; "
                          "picks the dominant kernel)")

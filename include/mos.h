@@ -66,7 +66,7 @@ typedef struct {
   uint32_t struct_size;
   int32_t n_objectives; /* 0 = all D; else use the first n objectives (the
                            paper's Table 1 rule: "the first n are used") */
-  int32_t batch_width;  /* B, labels popped per step (paper: NUM_POP), 1..16384; 0 = default */
+  int32_t batch_width;  /* B, labels popped per step (paper: NUM_POP), 1..32768; 0 = default */
   int32_t max_slots;    /* mos_solve_batch: queries resident at once; 0 = auto */
   int64_t label_limit;  /* per query; 0 = bounded only by mem_budget */
   int64_t mem_budget;   /* bytes of device memory for search state; 0 = auto */

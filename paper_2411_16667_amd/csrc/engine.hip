@@ -979,7 +979,7 @@ static mos_status read_opts(const mos_options* o, Opts* out) {
                                                : (o->heuristic_radius < 0 ? 0 : o->heuristic_radius);
   }
   if (r.B < 1 || r.B > BATCH_MAX)
-    return set_err(MOS_E_INVALID_ARG, "batch_width must lie in [1, 16384]");
+    return set_err(MOS_E_INVALID_ARG, "batch_width must lie in [1, 32768]");
   if (r.max_slots < 0 || r.label_limit < 0 || r.mem_budget < 0 || r.n_objectives < 0)
     return set_err(MOS_E_INVALID_ARG, "negative option");
   if (r.steps > 1024) return set_err(MOS_E_INVALID_ARG, "steps_per_poll too large");

@@ -21,7 +21,7 @@ constexpr int SPLIT_WORDS = 5;    // per split tile: goal, regular, out-degree s
 constexpr int TIECAP = 256;       // tie sets up to this size are ranked in LDS; larger ones
                                   // are first narrowed by exact radix refinement
 constexpr int MINCAP = 8;         // smallest frontier block, in entries
-constexpr int BATCH_MAX = 16384;  // largest popped batch (16 entries per thread of one workgroup)
+constexpr int BATCH_MAX = 32768;  // largest popped batch
 // near-tier sizing, in multiples of B: refill below LOW, refill up to TARGET,
 // spill to far above HIGH (keeping TARGET)
 constexpr int NEAR_LOW = 4, NEAR_TARGET = 16, NEAR_HIGH = 48;

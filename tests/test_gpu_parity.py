@@ -148,7 +148,7 @@ def test_ship_grid_front(mos, size):
     check_paths(g, s, t, r.costs, r.paths, 3)
 
 
-@pytest.mark.parametrize("B", [4096, 16384])
+@pytest.mark.parametrize("B", [4096, 32768])
 def test_widest_batches(mos, B):
     """Batches up to the largest width (16 popped labels per thread of the
     per-query workgroup) on the 32x32 grid and the 96x96 ship grid."""
