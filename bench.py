@@ -71,6 +71,9 @@ def parse():
                     help="routes workload: batch width B")
     ap.add_argument("--route-repeats", type=int, default=3,
                     help="routes workload: timed solves per route (the median is reported)")
+    ap.add_argument("--route-sweep", type=int, nargs="*", default=None, metavar="B",
+                    help="routes workload: also solve routes 1 and 5 at these batch widths and "
+                         "report labels popped against the oracle's (work efficiency)")
     ap.add_argument("--served-queries", type=int, default=600,
                     help="queries per arrival-rate point of the served workload")
     ap.add_argument("--radius", type=float, default=0.02,
@@ -374,6 +377,27 @@ def routes_bench(a):
                                   "objective count (12, 4, 12, 12, 6)",
                       "batch_width": a.route_width, "repeats": a.route_repeats},
            "seconds_all_routes": tot_s, "routes": rows}
+    if a.route_sweep:
+        # labels popped per batch width against the sequential oracle's pops
+        # (the paper's work-efficiency measure for its multi-pop), and time
+        sweep = []
+        for r in (1, 5):
+            d = gen.ROUTE_MAX_OBJECTIVES[r]
+            g, s, t = gen.tmplar_route(r, 12, 0)
+            G = mos.Graph.from_gen(g)
+            ref = next((x for x in rows if x["route"] == r), {})
+            for B in a.route_sweep:
+                mos.mos_solve(G, s, t, n_objectives=d, batch_width=B, costs_only=True)
+                t0 = time.perf_counter()
+                res = mos.mos_solve(G, s, t, n_objectives=d, batch_width=B, costs_only=True)
+                wall = time.perf_counter() - t0
+                pt = {"route": r, "d": d, "batch_width": B, "seconds": wall,
+                      "steps": res.stats["steps"], "pops": res.stats["pops"], "front": len(res.costs)}
+                if "oracle_pops" in ref:
+                    pt["pops_vs_oracle"] = res.stats["pops"] / ref["oracle_pops"]
+                sweep.append(pt)
+                print(f"routes sweep: {pt}", file=sys.stderr, flush=True)
+        out["batch_width_sweep"] = sweep
     if a.cpu_seconds > 0:
         import oracle
 
