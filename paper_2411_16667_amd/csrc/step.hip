@@ -2,9 +2,10 @@
 //
 // A step follows the paper's Algorithm 1 body (NAMOA*), applied to a batch of
 // labels popped in lexicographic order as Algorithm 2 (OPMOS) does:
-//   pop      k_open_hist, k_open_threshold, k_open_scatter, k_batch_finalize:
-//            the B lexicographically smallest live OPEN labels (labels pruned
-//            since they were queued are skipped lazily, Section 5.1)
+//   pop      k_open_hist, k_open_threshold, k_open_scatter, k_batch_finalize,
+//            k_split_count, k_split_scan: the B lexicographically smallest live
+//            OPEN labels (labels pruned since they were queued are skipped
+//            lazily, Section 5.1), split into goal and regular labels
 //   goal     k_goal_pairs, k_goal_merge: Prune(P, l) and NotDominated(l, P),
 //            P <- minimal(P + goal labels)
 //   prune    k_popcheck: PruneOPEN applied to the popped labels
@@ -19,9 +20,9 @@
 //            into OPEN and G_OP
 //   filter   k_pfilter: NotDominated(F', P) for the labels inserted this step
 //
-// All arithmetic is exact int32.  Tiled kernels run on a (gx, slots) grid and
-// grid-stride over the slot's items; per-slot kernels run one 1024-thread
-// workgroup per slot.  Each kernel copies its slot descriptor once (scalar
+// All arithmetic is exact int32.  Tiled kernels run on a (workgroups, slots)
+// grid and grid-stride over the slot's items; per-slot kernels run one
+// 1024-thread workgroup per slot.  Each kernel copies its slot descriptor once (scalar
 // registers); writes to descriptor fields go through the pointer.  Objective
 // loops are unrolled to the engine's compile-time bound DM (d <= DM).
 #include "kernels.h"
