@@ -67,8 +67,9 @@ def parse():
                          "served: the request loop on the 1M-node road-like graph; "
                          "routes: whole queries on the time-expanded routes at up to 12 "
                          "objectives")
-    ap.add_argument("--route-width", type=int, default=4096,
-                    help="routes workload: batch width B")
+    ap.add_argument("--route-width", type=int, default=0,
+                    help="routes workload: batch width B (0 = picked per route by the "
+                         "autotuner from 1024, 4096, 16384, 32768)")
     ap.add_argument("--route-repeats", type=int, default=3,
                     help="routes workload: timed solves per route (the median is reported)")
     ap.add_argument("--route-sweep", type=int, nargs="*", default=None, metavar="B",
@@ -324,9 +325,10 @@ def served_bench(a):
 
 def routes_bench(a):
     """Whole queries on the five time-expanded routes (Table 2 shapes), each at
-    Table 2's largest objective count for that route: one untimed solve, then
-    the median of --route-repeats timed solves (wall clock around mos_solve:
-    heuristic, search, harvest and paths).  The CPU baseline is the oracle on
+    Table 2's largest objective count for that route and at the batch width
+    the autotuner picks for it: one untimed solve, then the median of
+    --route-repeats timed solves (wall clock around mos_solve: heuristic,
+    search, harvest and paths).  The CPU baseline is the oracle on
     the smallest route (whole query) and on a bounded sample of route 1."""
     import gzip
 
@@ -340,7 +342,13 @@ def routes_bench(a):
         d = gen.ROUTE_MAX_OBJECTIVES[r]
         g, s, t = gen.tmplar_route(r, 12, 0)
         G = mos.Graph.from_gen(g)
-        kw = dict(n_objectives=d, batch_width=a.route_width)
+        B = a.route_width
+        if B == 0:
+            from paper_2411_16667_amd.autotune import tune_batch_width
+
+            B = tune_batch_width(G, [s], [t], n_objectives=[d], widths=(1024, 4096, 16384, 32768),
+                                 sample=1, costs_only=False)["batch_width"]
+        kw = dict(n_objectives=d, batch_width=B)
         res = mos.mos_solve(G, s, t, **kw)
         walls = []
         for _ in range(a.route_repeats):
@@ -350,7 +358,8 @@ def routes_bench(a):
         wall = float(np.median(walls))
         st = res.stats
         pairs = st["p_pairs"] + st["group_pairs"] + st["frontier_pairs"]
-        row = {"route": r, "nodes": g.n, "arcs": g.n_arcs, "d": d, "front": len(res.costs),
+        row = {"route": r, "nodes": g.n, "arcs": g.n_arcs, "d": d, "batch_width": B,
+               "front": len(res.costs),
                "seconds": wall, "search_ms": st["search_ms"], "heuristic_ms": st["heuristic_ms"],
                "pops": st["pops"], "steps": st["steps"], "pairs": pairs, "checks_per_s": pairs / wall}
         # the stored oracle front of this route, when there is one (tests/golden/routes)
@@ -379,7 +388,8 @@ def routes_bench(a):
            "config": {"workload": "five time-expanded ship routes shaped like Table 2 "
                                   "(10 time windows per cell), each at Table 2's largest "
                                   "objective count (12, 4, 12, 12, 6)",
-                      "batch_width": a.route_width, "repeats": a.route_repeats},
+                      "batch_width": a.route_width or "autotuned per route",
+                      "repeats": a.route_repeats},
            "seconds_all_routes": tot_s, "routes": rows}
     if a.route_sweep:
         # labels popped per batch width against the sequential oracle's pops
