@@ -1,0 +1,47 @@
+"""The bench's bookkeeping on the CPU: the kernel-source digest that keys the
+committed HBM-traffic counters follows the code, not its comments, and the
+committed summary is read back only for its own batch width."""
+import os
+import shutil
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def _copy_sources(tmp):
+    for f in bench.KERNEL_SOURCES:
+        dst = os.path.join(tmp, f)
+        os.makedirs(os.path.dirname(dst), exist_ok=True)
+        shutil.copy(os.path.join(ROOT, f), dst)
+
+
+def test_digest_ignores_comments_not_code(tmp_path, monkeypatch):
+    _copy_sources(str(tmp_path))
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    d0 = bench.kernel_source_digest()
+    assert d0 == bench.kernel_source_digest()
+    p = os.path.join(str(tmp_path), bench.KERNEL_SOURCES[0])
+    with open(p, "a", encoding="utf-8") as f:
+        f.write("\n// a note\n\n")
+    assert bench.kernel_source_digest() == d0
+    with open(p, "a", encoding="utf-8") as f:
+        f.write("static int extra_symbol = 1;\n")
+    assert bench.kernel_source_digest() != d0
+
+
+def test_committed_traffic_summary_reads_back():
+    text = open(bench.TRAFFIC_FILE, encoding="utf-8").read()
+    meta = dict(line[2:].split(": ", 1) for line in text.splitlines()
+                if line.startswith("- ") and ": " in line)
+    bw = int(meta["batch width"])
+    got = bench.measured_traffic("k_group_pairs", bw)
+    if meta["kernel sources sha256/16"].split()[0] == bench.kernel_source_digest():
+        assert got is not None and got > 0
+    else:
+        assert got is None  # counters of other kernel code are never reported
+    assert bench.measured_traffic("k_group_pairs", bw + 1) is None
+    assert bench.measured_traffic("no_such_kernel", bw) is None
