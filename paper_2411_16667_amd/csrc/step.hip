@@ -43,6 +43,38 @@ static_assert(SPLIT_TILE % NT_TILE == 0, "a split tile is whole chunks of one wo
 #define FOR_K(k) _Pragma("unroll") for (int k = 0; k < DM; ++k) if (k < d)
 
 // Exclusive scan of one value per thread across a workgroup of NT threads.
+// Four exclusive scans at once (one set of barriers for all four).
+template <int NT>
+__device__ int4 block_exscan4(int4 v, int4* total, int4* tmp /* >= NT/64 int4 */) {
+  const int lane = lane_id(), w = threadIdx.x / WAVE;
+  int4 x = v;
+#pragma unroll
+  for (int o = 1; o < WAVE; o <<= 1) {
+    const int4 y = make_int4(__shfl_up(x.x, o), __shfl_up(x.y, o), __shfl_up(x.z, o),
+                             __shfl_up(x.w, o));
+    if (lane >= o) x = make_int4(x.x + y.x, x.y + y.y, x.z + y.z, x.w + y.w);
+  }
+  if (lane == WAVE - 1) tmp[w] = x;
+  __syncthreads();
+  if (w == 0) {
+    constexpr int NW = NT / WAVE;
+    int4 t = lane < NW ? tmp[lane] : make_int4(0, 0, 0, 0);
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) {
+      const int4 y = make_int4(__shfl_up(t.x, o), __shfl_up(t.y, o), __shfl_up(t.z, o),
+                               __shfl_up(t.w, o));
+      if (lane >= o) t = make_int4(t.x + y.x, t.y + y.y, t.z + y.z, t.w + y.w);
+    }
+    if (lane < NW) tmp[lane] = t;
+  }
+  __syncthreads();
+  const int4 before = w > 0 ? tmp[w - 1] : make_int4(0, 0, 0, 0);
+  *total = tmp[NT / WAVE - 1];
+  __syncthreads();
+  return make_int4(before.x + x.x - v.x, before.y + x.y - v.y, before.z + x.z - v.z,
+                   before.w + x.w - v.w);
+}
+
 template <int NT>
 __device__ int block_exscan(int v, int* total, int* tmp /* >= NT/64 ints */) {
   const int lane = lane_id(), w = threadIdx.x / WAVE;
@@ -1390,7 +1422,7 @@ __global__ __launch_bounds__(NT_SLOT) void k_group_offsets(Slot* slots) {
   Slot* Sp = &slots[blockIdx.x];
   const Slot S = *Sp;
   if (S.status != S_RUN) return;
-  __shared__ int tmp[NT_SLOT / WAVE];
+  __shared__ int4 tmp4[NT_SLOT / WAVE];
   const int ng = S.ngroups;
   int carry = 0, ns = 0, nb = 0, nt = 0;
   for (int base = 0; base < ng; base += NT_SLOT) {
@@ -1405,11 +1437,11 @@ __global__ __launch_bounds__(NT_SLOT) void k_group_offsets(Slot* slots) {
     const bool small = i < ng && !big;
     const int nct = (sz + WAVE - 1) / WAVE, nft = (cnt + BT_ENTRIES - 1) / BT_ENTRIES;
     const int tiles = big ? nct * nct + nft * nct : 0;
-    int tot, ts, tb, tt;
-    const int ex = block_exscan<NT_SLOT>(sz, &tot, tmp);
-    const int ps = block_exscan<NT_SLOT>(small ? 1 : 0, &ts, tmp);
-    const int pb = block_exscan<NT_SLOT>(big ? 1 : 0, &tb, tmp);
-    const int pt = block_exscan<NT_SLOT>(tiles, &tt, tmp);
+    int4 tot4;
+    const int4 pre = block_exscan4<NT_SLOT>(make_int4(sz, small ? 1 : 0, big ? 1 : 0, tiles),
+                                            &tot4, tmp4);
+    const int ex = pre.x, ps = pre.y, pb = pre.z, pt = pre.w;
+    const int tot = tot4.x, ts = tot4.y, tb = tot4.z, tt = tot4.w;
     if (i < ng) S.grp_off[i] = carry + ex;
     if (small) S.small_list[ns + ps] = i;
     if (big) {
