@@ -1161,34 +1161,58 @@ __global__ __launch_bounds__(NT_SLOT) void k_goal_merge(Slot* slots) {
   }
 }
 
-// A tile of labels, two per thread (F packed as int4 words), against the front
+// A tile of labels, L per thread (F packed as int4 words), against the front
 // chunks c0 .. c1-1, each staged in LDS in turn (each row read from LDS serves
-// both of a thread's tests); stops early once every label of the tile is
-// dominated, and sets dom0 / dom1 for this thread's labels.  Work items are
+// all of a thread's tests); stops early once every label of the tile is
+// dominated, and sets dom[] for this thread's labels.  Work items are
 // (label tile, run of chunks) pairs with runs sized so that the items about
 // fill the grid: a label's F is formed once per run.
-template <int DM>
-__device__ void tile_vs_front2(FrontChunk<DM>& ch, const int32_t* Pg, int Pc, int np, int d,
-                               int c0, int c1, bool have0, bool have1,
-                               const int4 (&F0)[FrontChunk<DM>::NW],
-                               const int4 (&F1)[FrontChunk<DM>::NW], bool& dom0, bool& dom1) {
+template <int DM, int L>
+__device__ void tile_vs_frontL(FrontChunk<DM>& ch, const int32_t* Pg, int Pc, int np, int d,
+                               int c0, int c1, const bool (&have)[L],
+                               const int4 (&F)[L][FrontChunk<DM>::NW], bool (&dom)[L]) {
   for (int c = c0; c < c1; ++c) {
     const int p0 = c * PCH;
     __syncthreads();
     stage_chunk<DM>(ch, Pg, Pc, p0, min(PCH, np - p0), d);
     __syncthreads();
-    if ((have0 && !dom0) || (have1 && !dom1)) {
-      int a0 = -1, a1 = -1;
+    bool open = false;
+#pragma unroll
+    for (int h = 0; h < L; ++h) open = open || (have[h] && !dom[h]);
+    if (open) {
+      int a[L];
+#pragma unroll
+      for (int h = 0; h < L; ++h) a[h] = -1;
 #pragma unroll 8
-      for (int q = 0; q < PCH; ++q) {
-        a0 &= or_diff<DM>(ch.w[q], F0);
-        a1 &= or_diff<DM>(ch.w[q], F1);
-      }
-      dom0 = dom0 || a0 >= 0;
-      dom1 = dom1 || a1 >= 0;
+      for (int q = 0; q < PCH; ++q)
+#pragma unroll
+        for (int h = 0; h < L; ++h) a[h] &= or_diff<DM>(ch.w[q], F[h]);
+#pragma unroll
+      for (int h = 0; h < L; ++h) dom[h] = dom[h] || a[h] >= 0;
     }
-    if (__syncthreads_and((!have0 || dom0) && (!have1 || dom1))) break;
+    bool done = true;
+#pragma unroll
+    for (int h = 0; h < L; ++h) done = done && (!have[h] || dom[h]);
+    if (__syncthreads_and(done)) break;
   }
+}
+
+template <int DM>
+__device__ void tile_vs_front2(FrontChunk<DM>& ch, const int32_t* Pg, int Pc, int np, int d,
+                               int c0, int c1, bool have0, bool have1,
+                               const int4 (&F0)[FrontChunk<DM>::NW],
+                               const int4 (&F1)[FrontChunk<DM>::NW], bool& dom0, bool& dom1) {
+  const bool have[2] = {have0, have1};
+  int4 F[2][FrontChunk<DM>::NW];
+#pragma unroll
+  for (int w = 0; w < FrontChunk<DM>::NW; ++w) {
+    F[0][w] = F0[w];
+    F[1][w] = F1[w];
+  }
+  bool dom[2] = {dom0, dom1};
+  tile_vs_frontL<DM, 2>(ch, Pg, Pc, np, d, c0, c1, have, F, dom);
+  dom0 = dom[0];
+  dom1 = dom[1];
 }
 
 __device__ __forceinline__ int chunks_per_item(int nlt, int npc) {
@@ -1333,8 +1357,8 @@ __global__ __launch_bounds__(NT_TILE) void k_expand(Slot* slots, GraphDev G) {
 // it rejected or pruned has a g no better than its own, so the goal front
 // dominates that label's F as well.  Weak dominance: a completion of F = p
 // cannot improve on p.  Work items are (label tile, front chunk) pairs so that
-// a large front spreads over the whole chip; a label tile holds two labels per
-// thread, so each front row read from LDS serves two tests.
+// a large front spreads over the whole chip; a label tile holds four labels
+// per thread, so each front row read from LDS serves four tests.
 template <int DM>
 __global__ __launch_bounds__(NT_TILE) void k_pfilter(Slot* slots, GraphDev G) {
   Slot* Sp = &slots[blockIdx.y];
@@ -1344,7 +1368,8 @@ __global__ __launch_bounds__(NT_TILE) void k_pfilter(Slot* slots, GraphDev G) {
   if (R == 0 || np == 0) return;
   if (blockIdx.x == 0 && threadIdx.x == 0)
     atomicAdd((unsigned long long*)&Sp->st[ST_PPAIRS], (unsigned long long)((int64_t)R * (np - S.P_dead)));
-  constexpr int LT = 2 * NT_TILE;  // labels per tile: two per thread
+  constexpr int LPT = 4;           // labels per thread
+  constexpr int LT = LPT * NT_TILE;  // labels per tile
   const int nlt = (R + LT - 1) / LT, npc = (np + PCH - 1) / PCH;
   const int cpi = chunks_per_item(nlt, npc), ngrp = (npc + cpi - 1) / cpi;
   const int ntiles = nlt * ngrp;
@@ -1355,11 +1380,12 @@ __global__ __launch_bounds__(NT_TILE) void k_pfilter(Slot* slots, GraphDev G) {
   const int32_t* Pg = pick(S.Pg, S.P_sel);
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const int lt = t / ngrp, gi = t - lt * ngrp;
-    int ii[2];
-    bool have[2], dom[2] = {false, false};
-    int4 F[2][NW];
+    int ii[LPT];
+    bool have[LPT], dom[LPT];
+    int4 F[LPT][NW];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
+    for (int h = 0; h < LPT; ++h) {
+      dom[h] = false;
       ii[h] = lt * LT + h * NT_TILE + threadIdx.x;
       const int id = base + ii[h];
       have[h] = ii[h] < R && S.Lstate[id] != L_DEAD;
@@ -1375,10 +1401,9 @@ __global__ __launch_bounds__(NT_TILE) void k_pfilter(Slot* slots, GraphDev G) {
 #pragma unroll
       for (int w = 0; w < NW; ++w) F[h][w] = make_int4(x[4 * w], x[4 * w + 1], x[4 * w + 2], x[4 * w + 3]);
     }
-    tile_vs_front2<DM>(ch, Pg, Pc, np, d, gi * cpi, min(npc, (gi + 1) * cpi), have[0], have[1],
-                       F[0], F[1], dom[0], dom[1]);
+    tile_vs_frontL<DM, LPT>(ch, Pg, Pc, np, d, gi * cpi, min(npc, (gi + 1) * cpi), have, F, dom);
 #pragma unroll
-    for (int h = 0; h < 2; ++h)
+    for (int h = 0; h < LPT; ++h)
       if (have[h] && dom[h]) {
         S.Lstate[base + ii[h]] = L_DEAD;
         S.fw[S.c_fslot[S.order[ii[h]]]] = FW_REMOVED;  // leaves its node's frontier
