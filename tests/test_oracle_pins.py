@@ -15,8 +15,13 @@ The oracle (sequential NAMOA*, paper Algorithm 1) is checked against:
   * metamorphic relations (zero heuristic, node relabelling, objective
     permutation, reversal, scaling, a redundant objective) and the readings of
     the paper's ambiguous points (strict vs weak P tests, eager vs lazy PruneOPEN).
-A mistake such as a dropped prune, a flipped comparison, a wrong heuristic
-direction or an off-by-one in cost accumulation breaks at least one of these.
+  * the work: the number of extractions equals the count of cost vectors that
+    are Pareto-optimal at their node and not heuristic-dominated by the front,
+    taken by brute force (NAMOA* with a consistent heuristic extracts exactly
+    those).
+A mistake such as a dropped prune, a transposed comparison, a wrong heuristic
+direction or a wrong cost index breaks at least one of these; the mutant
+tests plant such mistakes and check that.
 """
 import heapq
 import itertools
@@ -281,3 +286,70 @@ def test_brute_force_random_high_d(seed):
         ref = brute_front(g, s, t, d)
         r = oracle.solve(g, s, t, d)
         assert np.array_equal(r.costs, ref), (seed, s, t)
+
+
+def nondominated_costs_per_node(g, s, t, d):
+    """For every node v, the distinct minimal costs over all simple s->v paths
+    that do not pass through the goal t before their end (DFS; a label at the
+    goal is never expanded, so nothing beyond the goal is searched)."""
+    rp, col, cost = g.row_ptr, g.col, g.cost[:, :d].astype(np.int64)
+    seen = [set() for _ in range(g.n)]
+    onpath = np.zeros(g.n, dtype=bool)
+
+    def dfs(u, acc):
+        seen[u].add(tuple(int(x) for x in acc))
+        if u == t:
+            return
+        onpath[u] = True
+        for e in range(rp[u], rp[u + 1]):
+            v = int(col[e])
+            if not onpath[v]:
+                dfs(v, acc + cost[e])
+        onpath[u] = False
+
+    dfs(s, np.zeros(d, dtype=np.int64))
+    out = []
+    for S in seen:
+        a = np.array(sorted(S), dtype=np.int64).reshape(-1, d)
+        keep = [y for y in a if not (np.all(a <= y, axis=1) & np.any(a < y, axis=1)).any()]
+        out.append(np.array(keep, dtype=np.int64).reshape(-1, d))
+    return out
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_pops_are_the_pareto_optimal_labels(seed):
+    """Work pin.  With OPEN in lexicographic order and a consistent heuristic
+    (the exact per-objective distance is one, and so is h = 0), every label
+    the sequential search extracts is Pareto-optimal at its node and its F is
+    not dominated by the final front, and every such cost vector is extracted
+    once (paper, Sections 1 and 4: the sequential lexicographic extraction is
+    the work-efficiency baseline because each label it extracts is globally
+    Pareto-optimal).  So the number of extractions equals a count taken by
+    brute force over the simple paths that stop at the goal.  A dropped or
+    misplaced prune changes the work but not the front; this pin sees it."""
+    d = 1 + seed % 4
+    if seed < 10:
+        g = gen.random_small(8, 20, d, seed=200 + seed)
+        pairs = [(0, 7), (4, 2)]
+    else:  # zero-cost sink arcs and cycles inside each time window
+        g, s0, t0 = gen.time_expanded_route(3, 2, d, seed=seed, windows=3)
+        pairs = [(s0, t0)]
+    for s, t in pairs:
+        nd = nondominated_costs_per_node(g, s, t, d)
+        front = brute_front(g, s, t, d)
+        for mode in (0, oracle.LAZY_PRUNEOPEN, oracle.ZERO_H,
+                     oracle.ZERO_H | oracle.LAZY_PRUNEOPEN):
+            h = (np.zeros((d, g.n), dtype=np.int64) if mode & oracle.ZERO_H
+                 else oracle.heuristic(g, t, d))
+            want = 0
+            for v in range(g.n):
+                if nd[v].shape[0] == 0 or (h[:, v] == oracle.INF).any():
+                    continue
+                F = nd[v] + h[:, v]
+                for f in F:
+                    dom = (np.all(front <= f, axis=1) & np.any(front < f, axis=1)).any()
+                    want += not dom
+            r = oracle.solve(g, s, t, d, flags=mode)
+            assert np.array_equal(r.costs, front)
+            assert r.stats["pops"] == want, (seed, s, t, mode)
+            assert r.stats["goal_pops"] == front.shape[0]
