@@ -440,8 +440,9 @@ def routes_bench(a):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {a.gpus}); queries shard "
-              "across GPUs with no exchange, see the design notes", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for --gpus {a.gpus}); queries are "
+              "independent, so several GPUs run one server process each, with the graph "
+              "replicated and no exchange between them", file=sys.stderr)
         sys.exit(2)
     import numpy as np
 

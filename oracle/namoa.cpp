@@ -17,8 +17,7 @@
 // objective k alone (Section 4: admissible heuristic computed with SSSP per
 // objective), obtained by binary-heap Dijkstra on the reversed arcs.
 //
-// Readings where the paper is silent or ambiguous (each is listed in the
-// design notes as well):
+// Readings where the paper is silent or ambiguous:
 //  * Dominance is strict (<= everywhere, < somewhere), Section 3; a separate
 //    Duplicate test handles equal vectors.  Goal insertion also rejects an
 //    equal vector so that P stays cost-unique.
