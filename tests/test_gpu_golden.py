@@ -61,6 +61,28 @@ def test_ship_grid_mid_range(mos):
         check_paths(g, int(s), int(t), r.costs, r.paths, 3)
 
 
+def test_ship_grid_at_bench_width(mos):
+    """The benchmark's launch configuration on its full graph: one resident
+    query on the 256x256 ship grid at the widest batch (B = 32768, the device
+    polled every 16 steps, steps replayed from a captured graph).  The
+    benchmark's corner-to-corner query has a front the oracle cannot finish,
+    so the stored oracle fronts of shorter queries on the same graph stand in
+    as sampled outputs."""
+    read_front = _read_front()
+    files = sorted(glob.glob(os.path.join(HERE, "c4mid", "q*.txt.gz")))
+    assert len(files) >= 8
+    g = gen.ship_grid(256, 256, 3, 0)
+    G = mos.Graph.from_gen(g)
+    for f in files:
+        h, costs = read_front(f)
+        assert h["graph_sha256_16"] == g.digest()
+        s, t = int(h["start"]), int(h["goal"])
+        print(f"bench width: {h['workload']}", flush=True)
+        r = mos.mos_solve(G, s, t, batch_width=32768, steps_per_poll=16)
+        assert np.array_equal(r.costs.astype(np.int64), costs), h["workload"]
+        check_paths(g, s, t, r.costs, r.paths, 3)
+
+
 def test_time_expanded_routes(mos):
     """Routes shaped like Table 2 at that table's largest objective counts."""
     read_front = _read_front()
