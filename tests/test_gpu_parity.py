@@ -44,6 +44,26 @@ def test_heuristic_matches_dijkstra(mos, seed):
     assert np.array_equal(h, ref32)
 
 
+@pytest.mark.parametrize("which", ["ship256", "route1_d12", "road1m"])
+def test_heuristic_full_size(mos, which):
+    """The heuristic at full size, every node compared: the benchmark's graph
+    and goal (256x256 ship grid), the largest time-expanded route at 12
+    objectives, and the served workload's 1M-node road-like graph with its
+    five stored objectives."""
+    if which == "ship256":
+        g, s, t = gen.config2(0)
+    elif which == "route1_d12":
+        g, s, t = gen.tmplar_route(1, 12, seed=0)
+    else:
+        g, _, _ = gen.config5_graph(0)
+        t = 12345
+    G = mos.Graph.from_gen(g)
+    h = mos.mos_heuristic(G, t)
+    ref = oracle.heuristic(g, t)
+    ref32 = np.where(ref == oracle.INF, np.iinfo(np.int32).max, ref).astype(np.int32)
+    assert np.array_equal(h, ref32)
+
+
 def test_heuristic_unreachable_nodes(mos):
     g = gen.random_small(12, 14, 3, seed=5, self_loops=True)
     G = mos.Graph.from_gen(g)
