@@ -212,6 +212,26 @@ def test_unreachable_and_trivial(mos):
     assert r.costs.tolist() == [[0, 0]] and len(r.paths[0]) == 0
 
 
+def test_invalid_arguments_rejected(mos):
+    """Out-of-range options and queries fail with MOS_E_INVALID_ARG before any
+    search runs, and the library keeps working afterwards."""
+    g = gen.random_small(9, 26, 2, seed=1)
+    G = mos.Graph.from_gen(g)
+    bad = [dict(batch_width=32769), dict(batch_width=-1), dict(steps_per_poll=1025),
+           dict(label_limit=-1), dict(n_objectives=3)]
+    for kw in bad:
+        with pytest.raises(mos.MosError) as e:
+            mos.mos_solve(G, 0, 8, **kw)
+        assert e.value.status == mos.MOS_E_INVALID_ARG, kw
+    for s, t in [(-1, 8), (0, g.n)]:
+        with pytest.raises(mos.MosError) as e:
+            mos.mos_solve(G, s, t)
+        assert e.value.status == mos.MOS_E_INVALID_ARG, (s, t)
+    # the widest batch is accepted, and the front is still the oracle's
+    r = mos.mos_solve(G, 0, 8, batch_width=32768)
+    assert np.array_equal(r.costs.astype(np.int64), oracle.solve(g, 0, 8).costs)
+
+
 def test_session_matches_solve(mos):
     g, s, t = gen.config1(1)
     G = mos.Graph.from_gen(g)
