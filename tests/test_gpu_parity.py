@@ -44,14 +44,16 @@ def test_heuristic_matches_dijkstra(mos, seed):
     assert np.array_equal(h, ref32)
 
 
-@pytest.mark.parametrize("which", ["ship256", "route1_d12", "road1m"])
+@pytest.mark.parametrize("which", ["ship256", "road200k", "route1_d12", "road1m"])
 def test_heuristic_full_size(mos, which):
     """The heuristic at full size, every node compared: the benchmark's graph
-    and goal (256x256 ship grid), the largest time-expanded route at 12
-    objectives, and the served workload's 1M-node road-like graph with its
-    five stored objectives."""
+    and goal (256x256 ship grid), the 200k-node road-like query's graph and
+    goal, the largest time-expanded route at 12 objectives, and the served
+    workload's 1M-node road-like graph with its five stored objectives."""
     if which == "ship256":
         g, s, t = gen.config2(0)
+    elif which == "road200k":
+        g, s, t = gen.config3(0)
     elif which == "route1_d12":
         g, s, t = gen.tmplar_route(1, 12, seed=0)
     else:
