@@ -100,6 +100,12 @@ def kernel_bytes(name, c, d, steps):
         "k_open_threshold": 8 * 4096 * steps,               # histogram read + reset
         "k_open_scatter": 17 * c["near_scanned"],
         "k_batch_finalize": 28 * pops + (8 + 8 * d + 4) * c["tie_entries"],
+        # per batch label: id, node and (regular ones) two row offsets; per tie
+        # entry: state, label, F1.  The scan reads the same again and writes
+        # reg/reg_off/reg_kill or goal_lab/goal flag, and an entry sent back
+        # to OPEN (F1, label; every tie entry counted: an upper bound)
+        "k_split_count": 24 * pops - 16 * c["goal_pops"] + 12 * c["tie_entries"],
+        "k_split_scan": 36 * pops - 20 * c["goal_pops"] + 20 * c["tie_entries"],
         "k_goal_pairs": 4 * d * c["front_reads"] + 4 * d * c["goal_pops"],
         "k_goal_merge": (8 + 8 * d) * c["goal_pops"],
         "k_popcheck": (8 + 8 * d) * pops,

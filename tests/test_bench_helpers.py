@@ -45,3 +45,37 @@ def test_committed_traffic_summary_reads_back():
         assert got is None  # counters of other kernel code are never reported
     assert bench.measured_traffic("k_group_pairs", bw + 1) is None
     assert bench.measured_traffic("no_such_kernel", bw) is None
+
+
+def test_every_step_kernel_has_byte_accounting():
+    """The benchmark's algorithmic-byte table names every kernel of the step
+    (read from the library's own name table), so no kernel reports 0 bytes
+    by omission."""
+    import re
+
+    src = open(os.path.join(ROOT, "paper_2411_16667_amd", "csrc", "step.hip")).read()
+    table = src[src.index("kStepKernelNames[kStepKernels] = {"):]
+    names = re.findall(r'"(k_\w+)"', table[:table.index("};")])
+    n = int(re.search(r"kStepKernels\s*=\s*(\d+)",
+                      open(os.path.join(ROOT, "paper_2411_16667_amd", "csrc", "kernels.h")).read())
+            .group(1))
+    assert len(names) == n == len(set(names))
+    c = {k: 1 for k in ("pops", "killed", "candidates", "inserted", "frontier_bytes",
+                        "frontier_bytes_onepass", "far_scanned", "near_scanned", "tie_entries",
+                        "front_reads", "goal_pops", "pairs_onepass", "frontier_pairs",
+                        "group_pairs", "p_pairs")}
+    c["frontier_bytes"] = 2
+    for k in names:
+        assert bench.kernel_bytes(k, c, 3, 1) > 0 or k == "k_step_end", k
+    assert bench.kernel_ops("k_group_pairs", c, 3) > 0
+
+
+def test_cpu_baseline_fields():
+    """The CPU leg times the oracle on a bounded prefix and reports the
+    contract's fields."""
+    import gen
+
+    g, s, t = gen.config1(0)
+    r = bench.cpu_baseline(g, s, t, 0.5)
+    assert r["kind"] == "oracle" and r["cores"] == 1 and r["unit"] == "checks/s"
+    assert r["value"] > 0 and "labels processed" in r["sample"]
