@@ -44,15 +44,20 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200, help="timed label steps")
-    ap.add_argument("--warmup", type=int, default=480,
-                    help="untimed label steps before timing (480 steps of B = 32768 and the "
-                         "timed steps take the search about 20M labels deep)")
+    ap.add_argument("--warmup", type=int, default=16,
+                    help="untimed label steps right before the timed ones, launched the same "
+                         "way (after the depth steps and the per-kernel table)")
+    ap.add_argument("--depth-steps", type=int, default=480,
+                    help="label steps run first, always, to take the search to the depth where "
+                         "the timed steps start (480 steps of B = 32768 reach about 16M "
+                         "labels; frontiers and the goal front are then near their "
+                         "steady-state sizes)")
     ap.add_argument("--batch-width", type=int, default=32768,
                     help="labels popped per step (the widest batch the library takes; at this "
                          "depth 16384 gives 21.8M pops/s and 32768 about 25M)")
-    ap.add_argument("--profile-steps", type=int, default=50,
-                    help="last warm-up steps with every kernel timed (per-kernel table; "
-                         "picks the dominant kernel)")
+    ap.add_argument("--profile-steps", type=int, default=32,
+                    help="steps after the depth steps with every kernel timed (per-kernel "
+                         "table at depth; picks the dominant kernel)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="length of the oracle sample for the CPU baseline (0 = skip)")
     ap.add_argument("--queries", type=int, default=64,
@@ -208,20 +213,20 @@ def batched_vs_plain(mos, gen, G, a):
     # engines are cached per (slot count, width, ...): one untimed call of each
     # form first, so that both timed forms reuse their engine
     mos.mos_solve_batch(G, S, T, batch_width=B)
+    mos.mos_solve(G, int(S[0]), int(T[0]), batch_width=B)
     t0 = time.perf_counter()
     res = mos.mos_solve_batch(G, S, T, batch_width=B)
-    t1 = time.perf_counter()
-    mos.mos_solve(G, int(S[0]), int(T[0]), batch_width=B)
-    t1 = time.perf_counter()
+    t_batched = time.perf_counter() - t0
+    t0 = time.perf_counter()
     plain = [mos.mos_solve(G, int(S[q]), int(T[q]), batch_width=B) for q in range(len(S))]
-    t2 = time.perf_counter()
+    t_plain = time.perf_counter() - t0
     same = all(st == mos.MOS_OK and np.array_equal(r.costs, p.costs)
                for (st, r), p in zip(res, plain))
     fronts = [len(p.costs) for p in plain]
     return {"queries": len(S), "manhattan_distance": list(a.qdist), "batch_width": B,
             "autotune": tuned,
-            "batched_qps": len(S) / (t1 - t0), "plain_qps": len(S) / (t2 - t1),
-            "speedup": (t2 - t1) / (t1 - t0), "same_fronts": bool(same),
+            "batched_qps": len(S) / t_batched, "plain_qps": len(S) / t_plain,
+            "speedup": t_plain / t_batched, "same_fronts": bool(same),
             "front_sizes": {"min": min(fronts), "median": int(np.median(fronts)), "max": max(fronts)}}
 
 
@@ -477,32 +482,42 @@ def main():
     g, s, t = gen.config2(0)
     G = mos.Graph.from_gen(g)
     d = 3
-    sess = mos.Session(G, s, t, batch_width=a.batch_width, steps_per_poll=16)
-    pre = max(1, min(a.profile_steps, a.warmup))
-    left = a.warmup - pre
+    # steps per captured graph: a divisor of the timed step count, so that every
+    # timed step is replayed from the captured graph (the form mos_solve uses)
+    K = next(k for k in range(min(32, a.steps), 0, -1) if a.steps % k == 0)
+    sess = mos.Session(G, s, t, batch_width=a.batch_width, steps_per_poll=K)
+    left = a.depth_steps
     while left > 0:  # in chunks, with a progress line each
-        n = min(left, 500)
+        n = min(left, 256)
         sess.step(n)
         left -= n
-        print(f"bench: warm-up, {a.warmup - pre - left} steps", file=sys.stderr, flush=True)
-    # per-kernel table from the last warm-up steps (every kernel bracketed by events)
+        print(f"bench: depth, {a.depth_steps - left} steps", file=sys.stderr, flush=True)
+    # per-kernel table at depth (every kernel bracketed by event records inside
+    # the replayed step graph); the kernel with the largest share is the dominant one
+    pre = max(K, a.profile_steps - a.profile_steps % K)
     sess.set_profile(-1)
     p0 = sess.kernel_times()
     sess.step(pre)
     p1 = sess.kernel_times()
     table = {n: (p1[n][0] - p0[n][0], p1[n][1] - p0[n][1]) for n in p1}
     dom = max(table, key=lambda n: table[n][0])
-    # timed steps: only the dominant kernel is bracketed by events
+    # warm-up and timed steps: only the dominant kernel is bracketed, inside
+    # the replayed graph
     sess.set_profile(1 << list(p1).index(dom))
-    s0, k0 = sess.stats(), sess.kernel_times()
+    if a.warmup > 0:
+        sess.step(a.warmup)
+    s0, k0, l0 = sess.stats(), sess.kernel_times(), sess.launch_counts()
     t0 = time.perf_counter()
     done = sess.step(a.steps)
     t1 = time.perf_counter()
-    s1, k1 = sess.stats(), sess.kernel_times()
+    s1, k1, l1 = sess.stats(), sess.kernel_times(), sess.launch_counts()
     steps = s1["steps"] - s0["steps"]
     if steps <= 0:
-        raise SystemExit("the search finished before the timed steps; lower --warmup")
+        raise SystemExit("the search finished before the timed steps; lower --depth-steps")
     wall = t1 - t0
+    launch = {"graph_replays": l1["graph_replays"] - l0["graph_replays"],
+              "steps_per_replay": l1["steps_per_replay"],
+              "direct_steps": l1["direct_steps"] - l0["direct_steps"]}
     pairs = sum(s1[k] - s0[k] for k in ("frontier_pairs", "p_pairs", "group_pairs"))
     value = pairs / wall
 
@@ -546,7 +561,8 @@ def main():
         "config": {"workload": "ship-routing grid 256x256, 8-connected, d=3 smooth-field costs, "
                                "corner to corner; one step = one batched label step",
                    "batch_width": a.batch_width, "label_steps_timed": steps,
-                   "search_finished": bool(done)},
+                   "depth_steps": a.depth_steps, "search_finished": bool(done)},
+        "timed_launches": launch,
         "roofline": roof,
         "kernel_us_per_step": {n: round(1e3 * v[0] / max(v[1], 1), 2)
                                for n, v in sorted(table.items(), key=lambda x: -x[1][0])},

@@ -64,8 +64,8 @@ typedef enum {
  * then override fields.  NULL options means all defaults. */
 typedef struct {
   uint32_t struct_size;
-  int32_t n_objectives; /* 0 = all D; else use the first n objectives (the
-                           paper's Table 1 rule: "the first n are used") */
+  int32_t n_objectives; /* 0 = all D; else objectives 0..n-1 in stored order
+                           (the paper's convention for its objective subsets, Table 1) */
   int32_t batch_width;  /* B, labels popped per step (paper: NUM_POP), 1..32768; 0 = default */
   int32_t max_slots;    /* mos_solve_batch: queries resident at once; 0 = auto */
   int64_t label_limit;  /* per query; 0 = bounded only by mem_budget */
@@ -74,8 +74,9 @@ typedef struct {
   int32_t costs_only;   /* 0 (default) = also reconstruct witness paths; 1 = costs only */
   int32_t steps_per_poll; /* device steps between host status polls; 0 = default */
   int32_t profile_kernels; /* sessions only: bit i set = time kernel i of every step with
-                              HIP events (-1 = every kernel); the kernels are then
-                              launched one by one instead of from a captured graph */
+                              HIP events (-1 = every kernel), recorded inside the
+                              captured step graph (steps that do not fill a replay
+                              are launched one by one with the same events) */
   int32_t heuristic_radius; /* heuristic (Section 4's reverse SSSP per objective): the
                               reverse search is cut at r * h_k(start) for r > 0, nodes
                               beyond the cut get the admissible lower bound cut + 1;
@@ -174,7 +175,10 @@ mos_status mos_server_submit(mos_server* s, int32_t start, int32_t goal, int32_t
 /* MOS_E_NOT_READY until the query is done; then MOS_OK and *out (owned by the
  * caller), or the query's error.  A ticket can be collected once. */
 mos_status mos_server_poll(mos_server* s, uint64_t ticket, mos_result** out);
-/* Blocks until the ticket is done (or timeout_ms elapses: MOS_E_NOT_READY). */
+/* Blocks until the ticket is done (or timeout_ms elapses: MOS_E_NOT_READY;
+ * timeout_ms < 0 waits without limit).  If the server's loop stops on a device
+ * error, every query it has not finished is reported with that error: wait
+ * and poll then return it instead of MOS_E_NOT_READY, and submit fails. */
 mos_status mos_server_wait(mos_server* s, uint64_t ticket, int64_t timeout_ms, mos_result** out);
 mos_status mos_server_cancel(mos_server* s, uint64_t ticket);
 /* Server counters: [0] submitted, [1] finished, [2] resident now, [3] queued now,
@@ -202,10 +206,17 @@ mos_status mos_session_stats(const mos_session* s, mos_stats* out);
 mos_status mos_session_result(mos_session* s, mos_result** out);
 int32_t mos_session_kernel_count(void);
 /* Change which kernels are timed from the next step on (same mask as
- * options.profile_kernels; 0 = none, steps then replay a captured graph). */
+ * options.profile_kernels; 0 = none).  Steps are replayed from a captured
+ * graph either way; timed kernels are bracketed by event records inside it. */
 mos_status mos_session_set_profile(mos_session* s, int32_t mask);
 mos_status mos_session_kernel_times(const mos_session* s, int32_t i, const char** name, double* ms,
                                     int64_t* launches);
+/* How the session's steps were launched so far: *graph_replays replays of a
+ * captured graph of *steps_per_replay steps each (the form mos_solve uses; in
+ * profile mode the graph carries the event records), and *direct_steps steps
+ * whose kernels were launched one by one. */
+mos_status mos_session_launch_counts(const mos_session* s, int64_t* graph_replays,
+                                     int64_t* steps_per_replay, int64_t* direct_steps);
 void mos_session_destroy(mos_session* s);
 
 const char* mos_status_string(mos_status s);

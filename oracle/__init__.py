@@ -19,6 +19,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "namoa.cpp")
+_SRCS = [_SRC, os.path.join(_HERE, "necessary.cpp")]
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 ZERO_H = 1
@@ -32,10 +33,12 @@ INF = np.iinfo(np.int64).max
 
 
 def build(force: bool = False) -> str:
-    """Compile namoa.cpp with g++ into liboracle.so (next to this file)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    """Compile namoa.cpp and necessary.cpp with g++ into liboracle.so (next to this file)."""
+    stale = not os.path.exists(_LIB) or any(
+        os.path.getmtime(_LIB) < os.path.getmtime(f) for f in _SRCS)
+    if force or stale:
         tmp = _LIB + ".tmp"
-        subprocess.check_call(["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-o", tmp, _SRC])
+        subprocess.check_call(["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-o", tmp, *_SRCS])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -53,6 +56,12 @@ def _load():
         lib.oracle_namoa.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_int, i64p, i32p, i32p,
                                      ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                      ctypes.c_int64, ctypes.c_double]
+        lib.oracle_namoa_ex.restype = ctypes.c_void_p
+        lib.oracle_namoa_ex.argtypes = lib.oracle_namoa.argtypes + [ctypes.c_int64]
+        lib.oracle_open_min.argtypes = [ctypes.c_void_p, i64p]
+        lib.oracle_lex_dijkstra.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_int, i64p,
+                                            i32p, i32p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                            i32p, i64p]
         lib.oracle_status.argtypes = [ctypes.c_void_p]
         lib.oracle_size.restype = ctypes.c_int64
         lib.oracle_size.argtypes = [ctypes.c_void_p]
@@ -79,6 +88,10 @@ class Front:
     costs: np.ndarray          # int64[size, d], lexicographically ascending
     paths: list                # list of int32 arc-id arrays
     stats: dict
+    # after an early stop (time or extraction limit): F of the smallest label
+    # left in OPEN.  The front so far is then the part of the final front that
+    # is lexicographically below it (see prefix_bound).
+    open_min: np.ndarray | None = None
 
 
 def _arrays(g):
@@ -89,14 +102,19 @@ def _arrays(g):
 
 
 def solve(g, s: int, t: int, d: int | None = None, flags: int = 0, label_limit: int = 0,
-          time_limit: float = 0.0) -> Front:
-    """Exact Pareto front of s->t costs over the first d objectives of g."""
+          time_limit: float = 0.0, pop_limit: int = 0) -> Front:
+    """Exact Pareto front of s->t costs over the first d objectives of g.
+
+    With a time limit or an extraction limit (pop_limit: labels taken from
+    OPEN) the search may stop early (status "time limit"); the result then
+    holds the goal front so far and ``open_min``."""
     lib = _load()
     d = g.D if d is None else d
     rp, col, cost = _arrays(g)
-    r = lib.oracle_namoa(g.n, g.n_arcs, g.D, _ptr(rp, ctypes.c_int64), _ptr(col, ctypes.c_int32),
-                         _ptr(cost, ctypes.c_int32), int(s), int(t), int(d), int(flags),
-                         int(label_limit), float(time_limit))
+    r = lib.oracle_namoa_ex(g.n, g.n_arcs, g.D, _ptr(rp, ctypes.c_int64),
+                            _ptr(col, ctypes.c_int32), _ptr(cost, ctypes.c_int32), int(s), int(t),
+                            int(d), int(flags), int(label_limit), float(time_limit),
+                            int(pop_limit))
     try:
         st = STATUS[lib.oracle_status(r)]
         n = lib.oracle_size(r)
@@ -116,9 +134,59 @@ def solve(g, s: int, t: int, d: int | None = None, flags: int = 0, label_limit: 
         stats = dict(zip(STAT_NAMES, (int(x) for x in sv)))
         stats["search_seconds"] = secs.value
         stats["front"] = int(n)
+        om = np.zeros(d, dtype=np.int64)
+        open_min = om if lib.oracle_open_min(r, _ptr(om, ctypes.c_int64)) else None
     finally:
         lib.oracle_free(r)
-    return Front(st, costs, paths, stats)
+    return Front(st, costs, paths, stats, open_min)
+
+
+def lex_less(a, b) -> bool:
+    """a < b in lexicographic order (objective 0 first)."""
+    for x, y in zip(a, b):
+        if x != y:
+            return x < y
+    return False
+
+
+def prefix_bound(front_so_far: Front):
+    """For an early-stopped search: (bound, rows) where bound is the F of the
+    smallest label left in OPEN and rows are the goal-front vectors found so
+    far that are lexicographically below it.  Any exact front of the same
+    query restricted to the vectors below `bound` must equal `rows`."""
+    b = front_so_far.open_min
+    rows = [r for r in front_so_far.costs if lex_less(r, b)]
+    return b, np.array(rows, dtype=np.int64).reshape(-1, front_so_far.costs.shape[1])
+
+
+def lex_dijkstra(g, s: int, t: int, perm, d: int | None = None):
+    """Cost vector (original objective order) of the lexicographically shortest
+    s->t path with objectives compared in the order perm; None if t is
+    unreachable."""
+    lib = _load()
+    d = len(perm) if d is None else d
+    rp, col, cost = _arrays(g)
+    pm = np.ascontiguousarray(perm, dtype=np.int32)
+    out = np.zeros(d, dtype=np.int64)
+    rc = lib.oracle_lex_dijkstra(g.n, g.n_arcs, g.D, _ptr(rp, ctypes.c_int64),
+                                 _ptr(col, ctypes.c_int32), _ptr(cost, ctypes.c_int32), int(s),
+                                 int(t), int(d), _ptr(pm, ctypes.c_int32), _ptr(out, ctypes.c_int64))
+    if rc < 0:
+        raise ValueError("bad lex_dijkstra input")
+    return tuple(int(x) for x in out) if rc == 1 else None
+
+
+def scalar_dijkstra(g, s: int, w) -> np.ndarray:
+    """Shortest distances from s under the scalar arc cost sum_k w[k] * c_k(e)."""
+    lib = _load()
+    rp, col, cost = _arrays(g)
+    w = np.asarray(w, dtype=np.int64)
+    we = np.ascontiguousarray(cost[:, :len(w)].astype(np.int64) @ w)
+    dist = np.zeros(g.n, dtype=np.int64)
+    if lib.oracle_dijkstra(g.n, _ptr(rp, ctypes.c_int64), _ptr(col, ctypes.c_int32),
+                           _ptr(we, ctypes.c_int64), int(s), _ptr(dist, ctypes.c_int64)):
+        raise ValueError("bad dijkstra input")
+    return dist
 
 
 def heuristic(g, goal: int, d: int | None = None) -> np.ndarray:

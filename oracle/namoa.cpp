@@ -149,6 +149,12 @@ struct Result {
   i64 max_open = 0;      // largest OPEN size seen
   i64 max_alpha = 0;     // largest |alpha(v)| seen
   double search_seconds = 0;
+  // A search stopped early (time or extraction limit) still reports its goal
+  // front so far, and the F of the smallest label left in OPEN: with OPEN in
+  // lexicographic order and a consistent heuristic, the front so far is
+  // exactly the part of the final front lexicographically below that F.
+  bool stopped_open = false;
+  std::vector<i64> open_min;  // d values when stopped_open
 };
 
 namespace {
@@ -177,6 +183,8 @@ struct Search {
       return a < b;
     }
   };
+
+  i64 pop_limit = 0;  // extractions before an early stop (0 = none)
 
   Search(const Csr& g_, int s_, int t_, int d_, int f_, i64 lim, double tl)
       : g(g_), s(s_), t(t_), d(d_), flags(f_), label_limit(lim), time_limit(tl) {}
@@ -253,13 +261,19 @@ struct Search {
 
     i64 iter = 0;
     while (!OPEN.empty()) {
-      if ((++iter & 4095) == 0) {
-        double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-        if (time_limit > 0 && el > time_limit) {
-          R.status = ORACLE_TIME_LIMIT;
-          R.search_seconds = el;  // counters so far describe the searched prefix
-          return;
-        }
+      ++iter;
+      bool stop = pop_limit > 0 && iter > pop_limit;
+      if (!stop && (iter & 4095) == 0 && time_limit > 0)
+        stop = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count() >
+               time_limit;
+      if (stop) {
+        R.status = ORACLE_TIME_LIMIT;
+        // counters so far describe the searched prefix
+        R.search_seconds =
+            std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        R.stopped_open = true;
+        for (int k = 0; k < d; ++k) R.open_min.push_back(F(*OPEN.begin(), k));
+        break;
       }
       R.max_open = std::max<i64>(R.max_open, (i64)OPEN.size());
       int l = *OPEN.begin();  // lexicographically smallest open label
@@ -385,8 +399,9 @@ struct Search {
         }
       }
     }
-    R.search_seconds =
-        std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (!R.stopped_open)
+      R.search_seconds =
+          std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
 
     // the result: P sorted lexicographically, with parent-chain paths
     std::sort(P.begin(), P.end(), [&](int a, int b) {
@@ -406,9 +421,9 @@ struct Search {
 
 }  // namespace
 
-extern "C" void* oracle_namoa(int n, i64 m, int D, const i64* row_ptr, const int* col,
-                              const int* cost, int s, int t, int d, int flags, i64 label_limit,
-                              double time_limit) {
+extern "C" void* oracle_namoa_ex(int n, i64 m, int D, const i64* row_ptr, const int* col,
+                                 const int* cost, int s, int t, int d, int flags, i64 label_limit,
+                                 double time_limit, i64 pop_limit) {
   Result* R = new Result();
   if (n <= 0 || d <= 0 || d > D || d > 16 || s < 0 || s >= n || t < 0 || t >= n) {
     R->status = ORACLE_BAD_INPUT;
@@ -418,12 +433,27 @@ extern "C" void* oracle_namoa(int n, i64 m, int D, const i64* row_ptr, const int
     if (cost[e] < 0) { R->status = ORACLE_BAD_INPUT; return R; }
   Csr g{n, m, D, row_ptr, col, cost};
   Search S(g, s, t, d, flags, label_limit, time_limit);
+  S.pop_limit = pop_limit;
   try {
     S.run(*R);
   } catch (const std::overflow_error&) {
     R->status = ORACLE_BAD_INPUT;
   }
   return R;
+}
+
+extern "C" void* oracle_namoa(int n, i64 m, int D, const i64* row_ptr, const int* col,
+                              const int* cost, int s, int t, int d, int flags, i64 label_limit,
+                              double time_limit) {
+  return oracle_namoa_ex(n, m, D, row_ptr, col, cost, s, t, d, flags, label_limit, time_limit, 0);
+}
+
+// After an early stop: 1 and the F of the smallest label left in OPEN; else 0.
+extern "C" int oracle_open_min(void* r, i64* out) {
+  Result* R = (Result*)r;
+  if (!R->stopped_open) return 0;
+  std::copy(R->open_min.begin(), R->open_min.end(), out);
+  return 1;
 }
 
 extern "C" int oracle_status(void* r) { return ((Result*)r)->status; }

@@ -96,6 +96,7 @@ _SIGS = {
     "mos_session_kernel_times": (ctypes.c_int, [_vp, ctypes.c_int32,
                                                 ctypes.POINTER(ctypes.c_char_p),
                                                 ctypes.POINTER(ctypes.c_double), _i64p]),
+    "mos_session_launch_counts": (ctypes.c_int, [_vp, _i64p, _i64p, _i64p]),
     "mos_session_destroy": (None, [_vp]),
 }
 for _name, (_res, _args) in _SIGS.items():
@@ -317,6 +318,13 @@ class Session:
                                                  ctypes.byref(n)), "mos_session_kernel_times")
             out[name.value.decode()] = (ms.value, n.value)
         return out
+
+    def launch_counts(self) -> dict:
+        """Graph replays (and steps per replay) and directly launched steps so far."""
+        a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(_lib.mos_session_launch_counts(self._h, ctypes.byref(a), ctypes.byref(b),
+                                              ctypes.byref(c)), "mos_session_launch_counts")
+        return {"graph_replays": a.value, "steps_per_replay": b.value, "direct_steps": c.value}
 
     def close(self):
         if getattr(self, "_h", None):

@@ -431,6 +431,9 @@ class Engine {
     hipStreamSynchronize(st_);
     for (auto& e : pev_) hipEventDestroy(e);
     if (graph_exec_) hipGraphExecDestroy(graph_exec_);
+    for (auto& x : pgraph_exec_)
+      if (x) hipGraphExecDestroy(x);
+    for (auto& e : gev_) hipEventDestroy(e);
     if (hslots_) hipHostFree(hslots_);
     hipEventDestroy(ev0_);
     hipEventDestroy(ev1_);
@@ -615,8 +618,12 @@ class Engine {
   const SlotHost& host0() const { return sh_[0]; }
   void set_profile(uint32_t mask) {
     drain_profile();
+    if (mask != profile_ && pgraph_exec_[0]) drop_profile_graphs();
     profile_ = mask;
   }
+  int64_t graph_replays() const { return graph_replays_; }
+  int64_t direct_steps() const { return direct_steps_; }
+  int steps_per_replay() const { return K_; }
   double kernel_ms(int i) const { return kms_[i]; }
   int64_t kernel_launches(int i) const { return klaunch_[i]; }
   mos_result* harvest_slot0() {
@@ -651,6 +658,12 @@ class Engine {
   }
 
   int64_t readmissions() const { return readmissions_; }
+  std::vector<int64_t> resident_ids() const {
+    std::vector<int64_t> v;
+    for (auto& h : sh_)
+      if (h.busy) v.push_back(h.q.id);
+    return v;
+  }
 
   void report_progress() {
     const auto now = std::chrono::steady_clock::now();
@@ -766,34 +779,101 @@ class Engine {
     return a;
   }
 
-  // K_ steps are captured once into a graph and replayed; the remainder (and
-  // everything in profile mode) is launched directly.
+  // Capture K_ steps into an executable graph; with `events`, the kernels
+  // selected by profile_ are bracketed by event-record nodes (one event set
+  // per captured step).  Returns nullptr when capture is not possible.
+  hipGraphExec_t capture_steps(const StepArgs& a, hipEvent_t* events) {
+    constexpr int NE = kStepKernels + 1;
+    hipGraph_t gr = nullptr;
+    hipGraphExec_t ex = nullptr;
+    if (hipStreamBeginCapture(st_, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+      for (int k = 0; k < K_; ++k)
+        launch_step(a, st_, events ? events + (size_t)k * NE : nullptr, events ? profile_ : 0u);
+      if (hipStreamEndCapture(st_, &gr) != hipSuccess || !gr ||
+          hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0) != hipSuccess)
+        ex = nullptr;
+      if (gr) hipGraphDestroy(gr);
+    }
+    hipGetLastError();
+    return ex;
+  }
+
+  // K_ steps are captured once into a graph and replayed; the remainder is
+  // launched directly.  In profile mode the replayed graph carries event
+  // records around the timed kernels and is drained after every replay; if
+  // such a graph cannot be captured the profiled steps are launched one by one.
   void launch_steps(int64_t n) {
     const StepArgs a = step_args();
     if (profile_) {
-      for (int64_t i = 0; i < n; ++i) profiled_step(a);
+      constexpr int NE = kStepKernels + 1;
+      if (use_graph_ && n >= K_ && !pgraph_failed_ && !pgraph_exec_[0]) {
+        if (gev_.empty()) {
+          gev_.resize((size_t)2 * K_ * NE);
+          for (auto& e : gev_) HIPCHK(hipEventCreate(&e));
+        }
+        drain_profile();
+        // two graphs with their own event sets: one is read back while the
+        // other runs, so the device never waits for the host between replays
+        for (int b = 0; b < 2 && !pgraph_failed_; ++b) {
+          pgraph_exec_[b] = capture_steps(a, gev_.data() + (size_t)b * K_ * NE);
+          pgraph_failed_ = pgraph_exec_[b] == nullptr;
+        }
+        if (pgraph_failed_) drop_profile_graphs();
+      }
+      if (pgraph_exec_[0]) {
+        int prev = -1;
+        for (; n >= K_; n -= K_) {
+          const int b = prev == 0 ? 1 : 0;
+          HIPCHK(hipGraphLaunch(pgraph_exec_[b], st_));
+          ++graph_replays_;
+          if (prev >= 0) drain_graph_events(prev);
+          prev = b;
+        }
+        if (prev >= 0) drain_graph_events(prev);
+      }
+      for (; n > 0; --n) profiled_step(a);
       return;
     }
     if (use_graph_ && !graph_exec_ && !graph_failed_ && n >= K_) {
-      hipGraph_t gr = nullptr;
-      if (hipStreamBeginCapture(st_, hipStreamCaptureModeThreadLocal) == hipSuccess) {
-        for (int k = 0; k < K_; ++k) launch_step(a, st_);
-        if (hipStreamEndCapture(st_, &gr) != hipSuccess || !gr ||
-            hipGraphInstantiate(&graph_exec_, gr, nullptr, nullptr, 0) != hipSuccess) {
-          graph_exec_ = nullptr;
-          graph_failed_ = true;
-        }
-        if (gr) hipGraphDestroy(gr);
-      } else {
-        graph_failed_ = true;
-      }
-      hipGetLastError();
+      graph_exec_ = capture_steps(a, nullptr);
+      graph_failed_ = graph_exec_ == nullptr;
     }
     if (graph_exec_) {
-      for (; n >= K_; n -= K_) HIPCHK(hipGraphLaunch(graph_exec_, st_));
+      for (; n >= K_; n -= K_) {
+        HIPCHK(hipGraphLaunch(graph_exec_, st_));
+        ++graph_replays_;
+      }
     }
-    for (; n > 0; --n) launch_step(a, st_);
+    for (; n > 0; --n) {
+      launch_step(a, st_);
+      ++direct_steps_;
+    }
     HIPCHK(hipGetLastError());
+  }
+
+  void drop_profile_graphs() {
+    HIPCHK(hipStreamSynchronize(st_));
+    for (auto& x : pgraph_exec_) {
+      if (x) hipGraphExecDestroy(x);
+      x = nullptr;
+    }
+  }
+
+  // Read the event sets of one replay of profiling graph b.
+  void drain_graph_events(int b) {
+    constexpr int NE = kStepKernels + 1;
+    hipEvent_t* base = &gev_[(size_t)b * K_ * NE];
+    HIPCHK(hipEventSynchronize(base[(size_t)(K_ - 1) * NE + kStepKernels]));
+    for (int k = 0; k < K_; ++k) {
+      hipEvent_t* set = base + (size_t)k * NE;
+      for (int i = 0; i < kStepKernels; ++i) {
+        if (!((profile_ >> i) & 1u)) continue;
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, set[i], set[i + 1]));
+        kms_[i] += ms;
+        klaunch_[i]++;
+      }
+    }
   }
 
   // Profile mode: every kernel of every step is bracketed by events; a ring of
@@ -810,6 +890,7 @@ class Engine {
     launch_step(a, st_, set, profile_);
     HIPCHK(hipGetLastError());
     ++ring_used_;
+    ++direct_steps_;
   }
   void drain_one() {
     constexpr int NE = kStepKernels + 1;
@@ -908,6 +989,10 @@ class Engine {
   hipEvent_t ev0_ = nullptr, ev1_ = nullptr;
   hipGraphExec_t graph_exec_ = nullptr;
   bool graph_failed_ = false;
+  hipGraphExec_t pgraph_exec_[2] = {};    // profiling graphs (event records inside)
+  bool pgraph_failed_ = false;
+  std::vector<hipEvent_t> gev_;           // K_ event sets of the profiling graph
+  int64_t graph_replays_ = 0, direct_steps_ = 0;
   bool use_graph_ = true;
   bool progress_ = false;
   int progress_level_ = 0;
@@ -1333,6 +1418,16 @@ mos_status mos_session_result(mos_session* s, mos_result** out) {
 
 int32_t mos_session_kernel_count(void) { return kStepKernels; }
 
+mos_status mos_session_launch_counts(const mos_session* s, int64_t* graph_replays,
+                                     int64_t* steps_per_replay, int64_t* direct_steps) {
+  if (!s || !graph_replays || !steps_per_replay || !direct_steps)
+    return set_err(MOS_E_INVALID_ARG, "NULL argument");
+  *graph_replays = s->eng->graph_replays();
+  *steps_per_replay = s->eng->steps_per_replay();
+  *direct_steps = s->eng->direct_steps();
+  return MOS_OK;
+}
+
 mos_status mos_session_set_profile(mos_session* s, int32_t mask) {
   if (!s) return set_err(MOS_E_INVALID_ARG, "NULL session");
   return guarded([&]() -> mos_status {
@@ -1373,6 +1468,34 @@ struct mos_server {
   std::vector<uint64_t> cancels;
   std::string fatal;
   mos_status fatal_st = MOS_OK;
+  int64_t fail_at_tick = -1;  // test hook (MOS_SERVER_FAIL_AT_TICK): throw before this tick
+
+  // The loop cannot go on (a device error): every query that has not been
+  // reported yet -- finished this tick, resident in a slot, queued here or
+  // still in the inbox -- gets an error entry, so that no wait blocks forever.
+  void fail_all(std::deque<QueryReq>& pending, std::vector<Finished>& done, mos_status st,
+                const std::string& what) {
+    std::lock_guard<std::mutex> lk(mu);
+    fatal = what;
+    fatal_st = st;
+    auto put = [&](int64_t id, const Finished& f) {
+      if (finished.count((uint64_t)id) == 0 && !known[(uint64_t)id]) {
+        finished[(uint64_t)id] = f;
+        nfinished++;
+      }
+    };
+    for (auto& f : done) put(f.id, f);
+    done.clear();
+    for (int64_t id : eng->resident_ids()) put(id, Finished{id, st, nullptr, what});
+    for (auto& q : pending) put(q.id, Finished{q.id, st, nullptr, what});
+    for (auto& q : inbox) put(q.id, Finished{q.id, st, nullptr, what});
+    pending.clear();
+    inbox.clear();
+    resident = 0;
+    queued = 0;
+    stop = true;
+    cv_done.notify_all();
+  }
 
   void loop() {
     hipSetDevice(g->device);
@@ -1409,15 +1532,12 @@ struct mos_server {
       }
       done.clear();
       try {
+        if (fail_at_tick >= 0 && ticks >= fail_at_tick)
+          throw MosError(MOS_E_DEVICE, "injected server failure (test hook)");
         eng->tick(pending, done);
-      } catch (const MosError& e) {
-        std::lock_guard<std::mutex> lk(mu);
-        fatal = e.what();
-        fatal_st = e.st;
-        for (auto& q : pending) finished[q.id] = Finished{q.id, e.st, nullptr, e.what()};
-        pending.clear();
-        stop = true;
-        cv_done.notify_all();
+      } catch (const std::exception& e) {
+        const MosError* me = dynamic_cast<const MosError*>(&e);
+        fail_all(pending, done, me ? me->st : MOS_E_DEVICE, e.what());
         return;
       }
       {
@@ -1447,6 +1567,7 @@ mos_status mos_server_create(const mos_graph* g, int64_t mem_budget, int32_t max
     s->g = g;
     const int S = max_slots > 0 ? max_slots : 64;
     s->eng.reset(new Engine(g, S, dm_for(g->D), default_budget(mem_budget), nullptr, 256, 0, true, 4));
+    if (const char* x = std::getenv("MOS_SERVER_FAIL_AT_TICK")) s->fail_at_tick = std::atoll(x);
     s->th = std::thread([p = s.get()] { p->loop(); });
     *out = s.release();
     return MOS_OK;
@@ -1477,7 +1598,13 @@ mos_status mos_server_submit(mos_server* s, int32_t start, int32_t goal, int32_t
 
 static mos_status collect(mos_server* s, uint64_t ticket, mos_result** out) {
   auto it = s->finished.find(ticket);
-  if (it == s->finished.end()) return MOS_E_NOT_READY;
+  if (it == s->finished.end()) {
+    // a stopped server finishes nothing more: report why instead of NOT_READY
+    if (s->stop)
+      return set_err(s->fatal_st == MOS_OK ? MOS_E_DEVICE : s->fatal_st,
+                     "server stopped: " + s->fatal);
+    return MOS_E_NOT_READY;
+  }
   Finished f = it->second;
   s->finished.erase(it);
   s->known[ticket] = true;
@@ -1499,7 +1626,7 @@ mos_status mos_server_wait(mos_server* s, uint64_t ticket, int64_t timeout_ms, m
   std::unique_lock<std::mutex> lk(s->mu);
   auto k = s->known.find(ticket);
   if (k == s->known.end() || k->second) return set_err(MOS_E_INVALID_ARG, "unknown ticket");
-  auto ready = [&] { return s->finished.count(ticket) > 0; };
+  auto ready = [&] { return s->finished.count(ticket) > 0 || s->stop; };
   if (timeout_ms < 0) s->cv_done.wait(lk, ready);
   else if (!s->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), ready))
     return MOS_E_NOT_READY;

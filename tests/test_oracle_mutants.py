@@ -24,6 +24,8 @@ import pytest
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SRC = os.path.join(ROOT, "oracle", "namoa.cpp")
+# the rest of the oracle library, built unchanged beside each mutant
+OTHER = [os.path.join(ROOT, "oracle", "necessary.cpp")]
 PINS = os.path.join(HERE, "test_oracle_pins.py")
 
 # (name, text in the oracle, replacement)
@@ -78,7 +80,7 @@ def _run_pins(tmp_path, source: str):
     lib = tmp_path / "liboracle_mutant.so"
     cpp.write_text(source)
     subprocess.check_call(["g++", "-O1", "-std=c++17", "-shared", "-fPIC", "-o", str(lib),
-                           str(cpp)])
+                           str(cpp), *OTHER])
     code = CHILD.format(root=ROOT, tests=HERE, lib=str(lib), pins=PINS)
     return subprocess.run([sys.executable, "-c", code], cwd=str(tmp_path), capture_output=True,
                           text=True, timeout=120, preexec_fn=_limit)
