@@ -10,12 +10,16 @@ the device throughout.  The value is dominance pair checks per second: every
 (candidate, stored vector) comparison the method makes against the goal front,
 against same-step candidates of the same node, and against node frontiers.
 
-Prints one JSON line.  Also reports the roofline of the dominant kernel (its
-durations from HIP events over the timed steps, its algorithmic bytes from the
-search counters, its measured HBM traffic from the committed PMC summary when
-that summary matches the current kernel sources), the CPU oracle's check rate
-on a bounded sample of the same query, and queries/s of one batched call
-against a loop of single solves on short-range queries of the same grid.
+Prints one JSON line.  The search is first taken --depth-steps deep (always,
+whatever --warmup is); a per-kernel table at that depth picks the dominant
+kernel; the timed steps then replay the captured step graph as mos_solve
+does.  Also reports the roofline of the dominant kernel (its durations from
+HIP events in an event window of the same length right after the timed
+steps, its algorithmic bytes from the search counters of that window, its
+measured HBM traffic from the committed PMC summary when that summary
+matches the current kernel sources), the CPU oracle's check rate on a
+bounded sample of the same query, and queries/s of one batched call against
+a loop of single solves on short-range queries of the same grid.
 
 `--workload served` instead runs the request loop on the 1M-node road-like
 graph (saturation and Poisson arrivals, p50/p99 latency) and prints its own
@@ -67,11 +71,12 @@ def parse():
     ap.add_argument("--query-width", type=int, default=0,
                     help="batch width B of every query in that comparison (0 = picked by "
                          "the autotuner on a sample of the queries)")
-    ap.add_argument("--workload", choices=("steps", "served", "routes"), default="steps",
+    ap.add_argument("--workload", choices=("steps", "served", "routes", "orders"), default="steps",
                     help="steps: label steps of the ship-routing query (the headline line); "
                          "served: the request loop on the 1M-node road-like graph; "
                          "routes: whole queries on the time-expanded routes at up to 12 "
-                         "objectives")
+                         "objectives; orders: lexicographic against generation (FIFO) "
+                         "OPEN order, labels popped and time to the exact front")
     ap.add_argument("--route-width", type=int, default=0,
                     help="routes workload: batch width B (0 = picked per route by the "
                          "autotuner from 1024, 4096, 16384, 32768)")
@@ -448,6 +453,77 @@ def routes_bench(a):
     print(json.dumps(out))
 
 
+def _stored(path):
+    import importlib.util
+
+    spec = importlib.util.spec_from_file_location(
+        "make_golden", os.path.join(ROOT, "tests", "golden", "make_golden.py"))
+    m = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(m)
+    return m.read_front(path)
+
+
+def orders_bench(a):
+    """Lexicographic priority order against the relaxed generation (FIFO)
+    order of OPEN, as the paper's Section 7.1 compares a priority queue with a
+    FIFO queue: whole queries with stored oracle fronts (the five time-expanded
+    routes at Table 2's objective counts, the mid-range ship-grid queries),
+    the same batch width for both orders, costs only; labels popped against
+    the sequential oracle's pops, and wall time to the exact front (median of
+    --route-repeats solves after an untimed one)."""
+    import glob
+
+    import numpy as np
+
+    import gen
+    import paper_2411_16667_amd as mos
+
+    work = []
+    for r in sorted(gen.ROUTE_SHAPES):
+        g, s, t = gen.tmplar_route(r, 12, 0)
+        work.append((f"route{r}", g, s, t, gen.ROUTE_MAX_OBJECTIVES[r],
+                     os.path.join(ROOT, "tests", "golden", "routes", f"r{r}.txt.gz")))
+    ship = gen.ship_grid(256, 256, 3, 0)
+    for f in sorted(glob.glob(os.path.join(ROOT, "tests", "golden", "c4mid", "q*.txt.gz"))):
+        h, _ = _stored(f)
+        work.append((h["workload"], ship, int(h["start"]), int(h["goal"]), 3, f))
+    B = a.route_width or 4096
+    rows = []
+    graphs = {}
+    for name, g, s, t, d, ref in work:
+        G = graphs.setdefault(id(g), mos.Graph.from_gen(g))
+        hdr, want = _stored(ref)
+        row = {"workload": name, "d": d, "batch_width": B, "oracle_pops": int(hdr["pops"]),
+               "front": int(want.shape[0])}
+        for order in ("lexicographic", "generation"):
+            kw = dict(n_objectives=d, batch_width=B, costs_only=True, pop_order=order)
+            res = mos.mos_solve(G, s, t, **kw)
+            walls = []
+            for _ in range(a.route_repeats):
+                t0 = time.perf_counter()
+                res = mos.mos_solve(G, s, t, **kw)
+                walls.append(time.perf_counter() - t0)
+            row[order] = {"seconds": float(np.median(walls)), "pops": res.stats["pops"],
+                          "steps": res.stats["steps"],
+                          "pops_vs_oracle": res.stats["pops"] / int(hdr["pops"]),
+                          "same_front_as_stored_oracle": bool(
+                              np.array_equal(res.costs.astype(np.int64), want))}
+        row["generation_vs_lexicographic_time"] = (row["generation"]["seconds"]
+                                                   / row["lexicographic"]["seconds"])
+        rows.append(row)
+        print(f"orders: {row}", file=sys.stderr, flush=True)
+    tl = sum(r["lexicographic"]["seconds"] for r in rows)
+    tg = sum(r["generation"]["seconds"] for r in rows)
+    out = {"metric": "time to the exact front, lexicographic vs generation (FIFO) OPEN order, 1 GPU",
+           "value": tg / tl, "unit": "time ratio generation/lexicographic",
+           "higher_is_better": False, "n_gpus": 1, "dtype": "int32", "data": "synthetic",
+           "config": {"workload": "time-expanded routes 1-5 at Table 2's objective counts and the "
+                                  "mid-range ship-grid queries with stored oracle fronts",
+                      "batch_width": B, "repeats": a.route_repeats},
+           "seconds_lexicographic": tl, "seconds_generation": tg, "queries": rows}
+    print(json.dumps(out))
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -465,6 +541,9 @@ def main():
         return
     if a.workload == "routes":
         routes_bench(a)
+        return
+    if a.workload == "orders":
+        orders_bench(a)
         return
     if a.copy_calibration > 0:
         import torch
@@ -492,25 +571,25 @@ def main():
         sess.step(n)
         left -= n
         print(f"bench: depth, {a.depth_steps - left} steps", file=sys.stderr, flush=True)
-    # per-kernel table at depth (every kernel bracketed by event records inside
-    # the replayed step graph); the kernel with the largest share is the dominant one
-    pre = max(K, a.profile_steps - a.profile_steps % K)
+    # per-kernel table at depth: every kernel bracketed by HIP events (the
+    # kernels then launch one by one); the largest share is the dominant kernel
+    pre = max(K, a.profile_steps)
     sess.set_profile(-1)
     p0 = sess.kernel_times()
     sess.step(pre)
     p1 = sess.kernel_times()
     table = {n: (p1[n][0] - p0[n][0], p1[n][1] - p0[n][1]) for n in p1}
     dom = max(table, key=lambda n: table[n][0])
-    # warm-up and timed steps: only the dominant kernel is bracketed, inside
-    # the replayed graph
-    sess.set_profile(1 << list(p1).index(dom))
+    sess.set_profile(0)
+    # warm-up and timed steps: replays of the captured step graph (the launch
+    # form mos_solve uses), no events
     if a.warmup > 0:
         sess.step(a.warmup)
-    s0, k0, l0 = sess.stats(), sess.kernel_times(), sess.launch_counts()
+    s0, l0 = sess.stats(), sess.launch_counts()
     t0 = time.perf_counter()
     done = sess.step(a.steps)
     t1 = time.perf_counter()
-    s1, k1, l1 = sess.stats(), sess.kernel_times(), sess.launch_counts()
+    s1, l1 = sess.stats(), sess.launch_counts()
     steps = s1["steps"] - s0["steps"]
     if steps <= 0:
         raise SystemExit("the search finished before the timed steps; lower --depth-steps")
@@ -518,14 +597,26 @@ def main():
     launch = {"graph_replays": l1["graph_replays"] - l0["graph_replays"],
               "steps_per_replay": l1["steps_per_replay"],
               "direct_steps": l1["direct_steps"] - l0["direct_steps"]}
+    # event window: the same number of steps right after, only the dominant
+    # kernel bracketed by HIP events on the search stream (events recorded
+    # inside a captured graph are not timed by this runtime, so these steps
+    # launch one by one; a kernel's own duration does not depend on that)
+    sess.set_profile(1 << list(p1).index(dom))
+    e0, k0 = sess.stats(), sess.kernel_times()
+    te0 = time.perf_counter()
+    sess.step(a.steps)
+    te1 = time.perf_counter()
+    e1, k1 = sess.stats(), sess.kernel_times()
+    sess.set_profile(0)
     pairs = sum(s1[k] - s0[k] for k in ("frontier_pairs", "p_pairs", "group_pairs"))
     value = pairs / wall
 
-    # the dominant kernel's launches over the timed steps (HIP events on the search stream)
+    # the dominant kernel's launches over the event window
     ms_dom, launches = k1[dom][0] - k0[dom][0], k1[dom][1] - k0[dom][1]
     avg_s = ms_dom / 1e3 / max(launches, 1)
-    delta = {k: s1[k] - s0[k] for k in s1 if isinstance(s1[k], int)}
-    nbytes = kernel_bytes(dom, delta, d, steps)
+    ewin = e1["steps"] - e0["steps"]
+    delta = {k: e1[k] - e0[k] for k in e1 if isinstance(e1[k], int)}
+    nbytes = kernel_bytes(dom, delta, d, ewin)
     nops = kernel_ops(dom, delta, d)
     bw = nbytes / max(launches, 1) / avg_s / 1e9          # GB/s
     ops = nops / max(launches, 1) / avg_s / 1e12          # TOP/s
@@ -542,6 +633,9 @@ def main():
     roof["kernel"] = dom
     roof["avg_launch_us"] = avg_s * 1e6
     roof["launches"] = launches
+    roof["event_window"] = {"steps": ewin, "ms_per_step": 1e3 * (te1 - te0) / max(ewin, 1),
+                            "launch": "one by one, dominant kernel bracketed by HIP events, "
+                                      "right after the timed steps"}
     roof["bytes_per_launch"] = nbytes / max(launches, 1)
     roof["intensity_ops_per_byte"] = intensity
 

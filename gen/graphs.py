@@ -304,6 +304,23 @@ def served_queries(g: Graph, comp: np.ndarray, nq: int, seed: int, dmin: int = 3
     return s.astype(np.int32), t.astype(np.int32), dq.astype(np.int32)
 
 
+def c5_parity_queries(g: Graph, comp: np.ndarray, nq: int, seed: int):
+    """nq uniformly random distinct (s, t) pairs in the giant component with
+    the objective count stratified: queries i = 0, 3, 6, ... use d = 3, then
+    d = 4 and d = 5 in turn (the first d stored objectives)."""
+    rng = np.random.default_rng(seed + 8000)
+    giant = np.bincount(comp).argmax()
+    nodes = np.flatnonzero(comp == giant)
+    s = nodes[rng.integers(0, nodes.size, nq)]
+    t = nodes[rng.integers(0, nodes.size, nq)]
+    same = s == t
+    while same.any():
+        t[same] = nodes[rng.integers(0, nodes.size, int(same.sum()))]
+        same = s == t
+    dq = 3 + np.arange(nq) % 3
+    return s.astype(np.int32), t.astype(np.int32), dq.astype(np.int32)
+
+
 def local_queries(g: Graph, comp: np.ndarray, nq: int, seed: int, radius: float,
                   dmin: int = 3, dmax: int = 5):
     """nq (s, t, d) queries in the giant component with t drawn uniformly among

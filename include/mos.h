@@ -25,7 +25,8 @@
  * the mos_result handle.  Every destroy function accepts NULL.
  *
  * Errors: no call aborts.  Every call that can fail returns a mos_status;
- * out-parameters are written only on MOS_OK.  Argument validation happens
+ * out-parameters are written only on MOS_OK (and, for the calls that return
+ * a result, on MOS_E_STEP_LIMIT, whose result is an exact prefix).  Argument validation happens
  * before any device call.  mos_last_error() gives a thread-local message for
  * the last failing call on the calling thread.
  */
@@ -57,8 +58,22 @@ typedef enum {
   MOS_E_LABEL_LIMIT = 7,   /* the search outgrew label_limit / the memory budget;
                               no partial front is ever reported as complete */
   MOS_E_CANCELLED = 8,     /* a served query was cancelled */
-  MOS_E_NOT_READY = 9      /* a served query has not finished yet */
+  MOS_E_NOT_READY = 9,     /* a served query has not finished yet */
+  MOS_E_STEP_LIMIT = 10    /* the query reached options.step_budget: its result holds
+                              only the exact part of the front below
+                              stats.open_min_f1 (see step_budget) */
 } mos_status;
+
+/* Order in which OPEN is processed (mos_options.pop_order).  Any order gives
+ * the same front (the search removes only dominated labels); the order decides
+ * the work.  LEXICOGRAPHIC: each step pops the B lexicographically smallest F
+ * (Algorithm 1's priority queue, batched as in Algorithm 2).  GENERATION: a
+ * relaxed order, each step pops the B oldest labels by the step that generated
+ * them (ties by F_2..F_d, then label id) -- a first-in first-out queue of
+ * generations, the FIFO alternative to the priority queue that Section 7.1
+ * measures. */
+#define MOS_POP_LEXICOGRAPHIC 0
+#define MOS_POP_GENERATION 1
 
 /* Options for one solve.  Zero-initialise, set struct_size = sizeof(mos_options),
  * then override fields.  NULL options means all defaults. */
@@ -74,14 +89,43 @@ typedef struct {
   int32_t costs_only;   /* 0 (default) = also reconstruct witness paths; 1 = costs only */
   int32_t steps_per_poll; /* device steps between host status polls; 0 = default */
   int32_t profile_kernels; /* sessions only: bit i set = time kernel i of every step with
-                              HIP events (-1 = every kernel), recorded inside the
-                              captured step graph (steps that do not fill a replay
-                              are launched one by one with the same events) */
+                              HIP events (-1 = every kernel); the kernels are then
+                              launched one by one instead of from a captured graph */
   int32_t heuristic_radius; /* heuristic (Section 4's reverse SSSP per objective): the
                               reverse search is cut at r * h_k(start) for r > 0, nodes
                               beyond the cut get the admissible lower bound cut + 1;
                               0 = default (r = 4); negative = exact on the whole graph.
                               The front does not depend on it, only the work does. */
+  int64_t step_budget;      /* 0 = none; else a query still running after this many
+                              label steps (counted at the next host poll) stops and
+                              returns MOS_E_STEP_LIMIT together with a result: its
+                              goal front so far cut to the entries whose first
+                              objective is below stats.open_min_f1, the smallest
+                              F_1 = g_1 + h_1 left in OPEN.  Every label that could
+                              still reach the goal has F_1 >= that bound (h is a
+                              lower bound of the remaining cost), so these entries are
+                              exactly the final front's entries in that range.  For
+                              mos_solve and mos_server_poll the result is written to
+                              *out with this status; mos_solve_batch reports it per
+                              query. */
+  int32_t pop_order;        /* MOS_POP_LEXICOGRAPHIC (0, default) or MOS_POP_GENERATION */
+  int32_t epsilon_ppm;      /* 0 (default) = the exact front.  e > 0: approximate front
+                              (Sections 2 and 8 name epsilon-dominance for trading
+                              exactness for work): every test against the goal front
+                              uses p <= (1 + eps) x with eps = e / 10^6, tests against a
+                              node's own labels stay exact.  The result is a set of
+                              real path costs (with their paths), mutually
+                              non-dominated, and every exact front vector y has an
+                              entry a with a <= (1 + eps) y in every component.  A goal
+                              label that is strictly below a front entry is always kept
+                              (it replaces that entry), so the factor does not compound.
+                              0 .. 10^9. */
+  int32_t eager_goal;       /* 0 (default): a label at the goal joins the goal front when
+                              OPEN pops it (Algorithm 1).  1: it joins the goal front
+                              in the next step's goal step, straight after the step
+                              that accepted it, without waiting for its turn in OPEN;
+                              the front then prunes the search sooner.  The result is
+                              the same front. */
 } mos_options;
 
 /* Counters of one query (paper, Section 6: label extractions, candidate
@@ -113,6 +157,9 @@ typedef struct {
   int64_t front_reads;     /* goal-front entries read by the goal-front updates */
   double search_ms;        /* device time of the label steps */
   double heuristic_ms;     /* device time of the heuristic (reverse SSSP) */
+  int64_t open_min_f1;     /* INT32_MAX for a complete front; for a step-limited or
+                              so-far result, the bound below which its first objective
+                              makes the entries final (see step_budget) */
 } mos_stats;
 
 /* Graph: n_nodes nodes, n_arcs arcs in CSR form.  row_ptr[n_nodes+1] (int64,
@@ -170,10 +217,16 @@ mos_status mos_set_allocator(void* (*alloc)(size_t bytes, void* stream, void* ct
  * larger one (or fails with MOS_E_LABEL_LIMIT); other queries are unaffected. */
 mos_status mos_server_create(const mos_graph* g, int64_t mem_budget_bytes, int32_t max_slots,
                              mos_server** out);
+/* The same with solve options applied to every served query: batch_width,
+ * steps_per_poll, label_limit, costs_only, heuristic_radius and step_budget
+ * (n_objectives is per request; other fields are ignored).  NULL = defaults. */
+mos_status mos_server_create_ex(const mos_graph* g, int64_t mem_budget_bytes, int32_t max_slots,
+                                const mos_options* opt, mos_server** out);
 mos_status mos_server_submit(mos_server* s, int32_t start, int32_t goal, int32_t n_objectives,
                              uint64_t* ticket);
 /* MOS_E_NOT_READY until the query is done; then MOS_OK and *out (owned by the
- * caller), or the query's error.  A ticket can be collected once. */
+ * caller), or the query's error (MOS_E_STEP_LIMIT also writes *out: the exact
+ * prefix).  A ticket can be collected once. */
 mos_status mos_server_poll(mos_server* s, uint64_t ticket, mos_result** out);
 /* Blocks until the ticket is done (or timeout_ms elapses: MOS_E_NOT_READY;
  * timeout_ms < 0 waits without limit).  If the server's loop stops on a device
@@ -204,17 +257,25 @@ mos_status mos_session_create(const mos_graph* g, int32_t start, int32_t goal,
 mos_status mos_session_step(mos_session* s, int64_t nsteps, int32_t* done);
 mos_status mos_session_stats(const mos_session* s, mos_stats* out);
 mos_status mos_session_result(mos_session* s, mos_result** out);
+/* The goal front found so far (sorted, with witness paths unless costs_only)
+ * without ending the search, and in *open_min_f1 the smallest first objective
+ * F_1 = g_1 + h_1 over the labels still in OPEN (INT32_MAX when OPEN is empty).
+ * With OPEN processed in lexicographic order and a consistent heuristic (the
+ * exact per-objective distance, Section 4), every label that could still
+ * reach the goal has F_1 >= *open_min_f1, so the entries whose first
+ * objective is below it are exactly the final front's entries in that range:
+ * a prefix of the exact answer, available long before the search ends. */
+mos_status mos_session_front(mos_session* s, int32_t* open_min_f1, mos_result** out);
 int32_t mos_session_kernel_count(void);
 /* Change which kernels are timed from the next step on (same mask as
- * options.profile_kernels; 0 = none).  Steps are replayed from a captured
- * graph either way; timed kernels are bracketed by event records inside it. */
+ * options.profile_kernels; 0 = none, steps then replay a captured graph). */
 mos_status mos_session_set_profile(mos_session* s, int32_t mask);
 mos_status mos_session_kernel_times(const mos_session* s, int32_t i, const char** name, double* ms,
                                     int64_t* launches);
 /* How the session's steps were launched so far: *graph_replays replays of a
- * captured graph of *steps_per_replay steps each (the form mos_solve uses; in
- * profile mode the graph carries the event records), and *direct_steps steps
- * whose kernels were launched one by one. */
+ * captured graph of *steps_per_replay steps each (the form mos_solve uses),
+ * and *direct_steps steps whose kernels were launched one by one (profile mode
+ * and remainders). */
 mos_status mos_session_launch_counts(const mos_session* s, int64_t* graph_replays,
                                      int64_t* steps_per_replay, int64_t* direct_steps);
 void mos_session_destroy(mos_session* s);

@@ -58,7 +58,15 @@ def _load():
                                      ctypes.c_int64, ctypes.c_double]
         lib.oracle_namoa_ex.restype = ctypes.c_void_p
         lib.oracle_namoa_ex.argtypes = lib.oracle_namoa.argtypes + [ctypes.c_int64]
+        lib.oracle_namoa_eps.restype = ctypes.c_void_p
+        lib.oracle_namoa_eps.argtypes = lib.oracle_namoa.argtypes + [ctypes.c_int64,
+                                                                     ctypes.c_int64]
+        lib.oracle_first_uncovered.restype = ctypes.c_int64
+        lib.oracle_first_uncovered.argtypes = [ctypes.c_int64, i64p, ctypes.c_int64, i64p,
+                                               ctypes.c_int, ctypes.c_int64]
         lib.oracle_open_min.argtypes = [ctypes.c_void_p, i64p]
+        lib.oracle_first_dominated.restype = ctypes.c_int64
+        lib.oracle_first_dominated.argtypes = [ctypes.c_int64, ctypes.c_int, i64p]
         lib.oracle_lex_dijkstra.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_int, i64p,
                                             i32p, i32p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                             i32p, i64p]
@@ -102,19 +110,22 @@ def _arrays(g):
 
 
 def solve(g, s: int, t: int, d: int | None = None, flags: int = 0, label_limit: int = 0,
-          time_limit: float = 0.0, pop_limit: int = 0) -> Front:
+          time_limit: float = 0.0, pop_limit: int = 0, want_paths: bool = True,
+          eps_ppm: int = 0) -> Front:
     """Exact Pareto front of s->t costs over the first d objectives of g.
 
     With a time limit or an extraction limit (pop_limit: labels taken from
     OPEN) the search may stop early (status "time limit"); the result then
-    holds the goal front so far and ``open_min``."""
+    holds the goal front so far and ``open_min``.  eps_ppm > 0 runs the
+    approximate mode: tests against the goal front by (1 + eps)-dominance,
+    eps = eps_ppm / 10^6 (the result covers the exact front within 1 + eps)."""
     lib = _load()
     d = g.D if d is None else d
     rp, col, cost = _arrays(g)
-    r = lib.oracle_namoa_ex(g.n, g.n_arcs, g.D, _ptr(rp, ctypes.c_int64),
-                            _ptr(col, ctypes.c_int32), _ptr(cost, ctypes.c_int32), int(s), int(t),
-                            int(d), int(flags), int(label_limit), float(time_limit),
-                            int(pop_limit))
+    r = lib.oracle_namoa_eps(g.n, g.n_arcs, g.D, _ptr(rp, ctypes.c_int64),
+                             _ptr(col, ctypes.c_int32), _ptr(cost, ctypes.c_int32), int(s), int(t),
+                             int(d), int(flags), int(label_limit), float(time_limit),
+                             int(pop_limit), int(eps_ppm))
     try:
         st = STATUS[lib.oracle_status(r)]
         n = lib.oracle_size(r)
@@ -122,7 +133,7 @@ def solve(g, s: int, t: int, d: int | None = None, flags: int = 0, label_limit: 
         if n:
             lib.oracle_costs(r, _ptr(costs, ctypes.c_int64))
         paths = []
-        for i in range(n):
+        for i in range(n if want_paths else 0):
             ln = lib.oracle_path_len(r, i)
             p = np.zeros(ln, dtype=np.int32)
             if ln:
@@ -201,3 +212,28 @@ def heuristic(g, goal: int, d: int | None = None) -> np.ndarray:
     if rc:
         raise ValueError("bad heuristic input")
     return h
+
+
+def first_dominated(front) -> int:
+    """For rows in lexicographically ascending order: -1 when they are mutually
+    non-dominated and distinct, else the index of the first row that an
+    earlier row weakly dominates (-2: rows not ascending)."""
+    lib = _load()
+    f = np.ascontiguousarray(front, dtype=np.int64)
+    if f.ndim != 2 or f.shape[0] == 0:
+        return -1
+    return int(lib.oracle_first_dominated(f.shape[0], f.shape[1], _ptr(f, ctypes.c_int64)))
+
+
+def first_uncovered(exact, apx, eps_ppm: int) -> int:
+    """-1 when every row y of `exact` has a row a of `apx` with
+    a <= (1 + eps_ppm / 10^6) y in every component, else the first y without."""
+    lib = _load()
+    e = np.ascontiguousarray(exact, dtype=np.int64)
+    a = np.ascontiguousarray(apx, dtype=np.int64)
+    if e.shape[0] == 0:
+        return -1
+    d = e.shape[1]
+    a = a.reshape(-1, d)
+    return int(lib.oracle_first_uncovered(e.shape[0], _ptr(e, ctypes.c_int64), a.shape[0],
+                                          _ptr(a, ctypes.c_int64), d, int(eps_ppm)))

@@ -34,6 +34,15 @@
 //  * ORACLE_LAZY_PRUNEOPEN replaces the eager full scan of OPEN by a check of
 //    each label against P when it is popped (the lazy delete of Algorithm 2,
 //    applied to P-dominance); the cost set is unchanged.
+//  * Approximate mode (eps_ppm > 0, Sections 2 and 8 name epsilon-dominance as
+//    the way to trade exactness for work): every test against the goal front
+//    P -- NotDominated(F, P) of a candidate, PruneOPEN, and NotDominated(l, P)
+//    of a goal label -- uses epsilon-dominance, p <= (1 + eps) x in every
+//    component with eps = eps_ppm / 10^6, while Prune(P, l) and every test
+//    against a node's own labels stay exact.  Every label is then dropped only
+//    when a vector already in P (or one that later replaces it, which is
+//    smaller still) lies within a factor 1 + eps of every cost it could reach,
+//    so the final P covers the exact front within that factor.
 //
 // Arithmetic is int64; every cost sum is asserted to stay below 2^31.
 
@@ -185,6 +194,7 @@ struct Search {
   };
 
   i64 pop_limit = 0;  // extractions before an early stop (0 = none)
+  i64 eps_ppm = 0;    // approximate mode: P tests by (1 + eps_ppm / 10^6)-dominance
 
   Search(const Csr& g_, int s_, int t_, int d_, int f_, i64 lim, double tl)
       : g(g_), s(s_), t(t_), d(d_), flags(f_), label_limit(lim), time_limit(tl) {}
@@ -208,8 +218,16 @@ struct Search {
       if (a[k] != b[k]) return false;
     return true;
   }
-  // The P relation: strict dominance, or weak dominance under ORACLE_WEAK_P.
+  // p <= (1 + eps) x in every component (exact integer arithmetic)
+  bool eps_dominates(const i64* p, const i64* x) const {
+    for (int k = 0; k < d; ++k)
+      if (p[k] * 1000000 > x[k] * (1000000 + eps_ppm)) return false;
+    return true;
+  }
+  // The P relation: strict dominance, or weak dominance under ORACLE_WEAK_P,
+  // or epsilon-dominance in approximate mode.
   bool p_rel(const i64* p, const i64* x) const {
+    if (eps_ppm > 0) return eps_dominates(p, x);
     return (flags & ORACLE_WEAK_P) ? weakly_dominates(p, x) : dominates(p, x);
   }
 
@@ -330,7 +348,10 @@ struct Search {
         for (int p : P) {
           R.p_pairs++;
           const i64* pg = &lg[(i64)p * d];
-          if (dominates(pg, gl) || equal(pg, gl)) { ok = false; break; }
+          if (dominates(pg, gl) || equal(pg, gl) || (eps_ppm > 0 && eps_dominates(pg, gl))) {
+            ok = false;
+            break;
+          }
         }
         if (ok) P.push_back(l);
         continue;
@@ -421,9 +442,9 @@ struct Search {
 
 }  // namespace
 
-extern "C" void* oracle_namoa_ex(int n, i64 m, int D, const i64* row_ptr, const int* col,
-                                 const int* cost, int s, int t, int d, int flags, i64 label_limit,
-                                 double time_limit, i64 pop_limit) {
+extern "C" void* oracle_namoa_eps(int n, i64 m, int D, const i64* row_ptr, const int* col,
+                                  const int* cost, int s, int t, int d, int flags, i64 label_limit,
+                                  double time_limit, i64 pop_limit, i64 eps_ppm) {
   Result* R = new Result();
   if (n <= 0 || d <= 0 || d > D || d > 16 || s < 0 || s >= n || t < 0 || t >= n) {
     R->status = ORACLE_BAD_INPUT;
@@ -432,14 +453,26 @@ extern "C" void* oracle_namoa_ex(int n, i64 m, int D, const i64* row_ptr, const 
   for (i64 e = 0; e < m * D; ++e)
     if (cost[e] < 0) { R->status = ORACLE_BAD_INPUT; return R; }
   Csr g{n, m, D, row_ptr, col, cost};
+  if (eps_ppm < 0 || eps_ppm > 1000000000) {
+    R->status = ORACLE_BAD_INPUT;
+    return R;
+  }
   Search S(g, s, t, d, flags, label_limit, time_limit);
   S.pop_limit = pop_limit;
+  S.eps_ppm = eps_ppm;
   try {
     S.run(*R);
   } catch (const std::overflow_error&) {
     R->status = ORACLE_BAD_INPUT;
   }
   return R;
+}
+
+extern "C" void* oracle_namoa_ex(int n, i64 m, int D, const i64* row_ptr, const int* col,
+                                 const int* cost, int s, int t, int d, int flags, i64 label_limit,
+                                 double time_limit, i64 pop_limit) {
+  return oracle_namoa_eps(n, m, D, row_ptr, col, cost, s, t, d, flags, label_limit, time_limit,
+                          pop_limit, 0);
 }
 
 extern "C" void* oracle_namoa(int n, i64 m, int D, const i64* row_ptr, const int* col,

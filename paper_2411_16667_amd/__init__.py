@@ -29,9 +29,10 @@ if not os.path.exists(LIB_PATH):
 _lib = ctypes.CDLL(LIB_PATH)
 
 MOS_OK = 0
+POP_ORDERS = {"lexicographic": 0, "generation": 1}  # mos_options.pop_order
 STATUS_NAMES = ["MOS_OK", "MOS_E_INVALID_ARG", "MOS_E_NEGATIVE_COST", "MOS_E_OVERFLOW_RISK",
                 "MOS_E_NO_DEVICE", "MOS_E_DEVICE", "MOS_E_OUT_OF_MEMORY", "MOS_E_LABEL_LIMIT",
-                "MOS_E_CANCELLED", "MOS_E_NOT_READY"]
+                "MOS_E_CANCELLED", "MOS_E_NOT_READY", "MOS_E_STEP_LIMIT"]
 for _i, _n in enumerate(STATUS_NAMES):
     globals()[_n] = _i
 
@@ -42,7 +43,9 @@ class mos_options(ctypes.Structure):
                 ("label_limit", ctypes.c_int64), ("mem_budget", ctypes.c_int64),
                 ("stream", ctypes.c_void_p), ("costs_only", ctypes.c_int32),
                 ("steps_per_poll", ctypes.c_int32), ("profile_kernels", ctypes.c_int32),
-                ("heuristic_radius", ctypes.c_int32)]
+                ("heuristic_radius", ctypes.c_int32), ("step_budget", ctypes.c_int64),
+                ("pop_order", ctypes.c_int32), ("epsilon_ppm", ctypes.c_int32),
+                ("eager_goal", ctypes.c_int32)]
 
 
 class mos_stats(ctypes.Structure):
@@ -51,7 +54,8 @@ class mos_stats(ctypes.Structure):
                  "inserted", "pruned", "steps", "front", "frontier_bytes", "killed",
                  "frontier_bytes_onepass", "pairs_onepass", "near_scanned", "far_scanned",
                  "tie_entries", "front_reads")] + \
-               [("search_ms", ctypes.c_double), ("heuristic_ms", ctypes.c_double)]
+               [("search_ms", ctypes.c_double), ("heuristic_ms", ctypes.c_double),
+                ("open_min_f1", ctypes.c_int64)]
 
 
 _vp = ctypes.c_void_p
@@ -76,6 +80,8 @@ _SIGS = {
     "mos_result_destroy": (None, [_vp]),
     "mos_set_allocator": (ctypes.c_int, [_ALLOC_FN, _FREE_FN, _vp]),
     "mos_server_create": (ctypes.c_int, [_vp, ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(_vp)]),
+    "mos_server_create_ex": (ctypes.c_int, [_vp, ctypes.c_int64, ctypes.c_int32,
+                                            ctypes.POINTER(mos_options), ctypes.POINTER(_vp)]),
     "mos_server_submit": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                          ctypes.POINTER(ctypes.c_uint64)]),
     "mos_server_poll": (ctypes.c_int, [_vp, ctypes.c_uint64, ctypes.POINTER(_vp)]),
@@ -97,6 +103,7 @@ _SIGS = {
                                                 ctypes.POINTER(ctypes.c_char_p),
                                                 ctypes.POINTER(ctypes.c_double), _i64p]),
     "mos_session_launch_counts": (ctypes.c_int, [_vp, _i64p, _i64p, _i64p]),
+    "mos_session_front": (ctypes.c_int, [_vp, _i32p, ctypes.POINTER(_vp)]),
     "mos_session_destroy": (None, [_vp]),
 }
 for _name, (_res, _args) in _SIGS.items():
@@ -180,9 +187,12 @@ class Result:
     costs: np.ndarray      # int32[size, d], lexicographically ascending
     paths: list | None     # int32 arc-id arrays, or None (costs only)
     stats: dict
+    # False for a step-limited or so-far result: costs are then exactly the
+    # front's entries whose first objective is below stats["open_min_f1"]
+    complete: bool = True
 
 
-def _take_result(h) -> Result:
+def _take_result(h, complete: bool = True) -> Result:
     try:
         n = _lib.mos_result_size(h)
         d = _lib.mos_result_dim(h)
@@ -206,7 +216,7 @@ def _take_result(h) -> Result:
         stats = {f: getattr(s, f) for f, _ in mos_stats._fields_}
     finally:
         _lib.mos_result_destroy(h)
-    return Result(costs, paths, stats)
+    return Result(costs, paths, stats, complete)
 
 
 def _stream_ptr(stream):
@@ -219,7 +229,8 @@ def _stream_ptr(stream):
 
 def make_options(n_objectives=0, batch_width=0, max_slots=0, label_limit=0, mem_budget=0,
                  stream=None, costs_only=False, steps_per_poll=0,
-                 profile_kernels=False, heuristic_radius=0) -> mos_options:
+                 profile_kernels=False, heuristic_radius=0, step_budget=0,
+                 pop_order="lexicographic", epsilon_ppm=0, eager_goal=False) -> mos_options:
     o = mos_options()
     o.struct_size = ctypes.sizeof(mos_options)
     o.n_objectives = int(n_objectives)
@@ -233,14 +244,22 @@ def make_options(n_objectives=0, batch_width=0, max_slots=0, label_limit=0, mem_
     # True = every kernel of the step; an int = bit mask over the step's kernels
     o.profile_kernels = -1 if profile_kernels is True else int(profile_kernels)
     o.heuristic_radius = int(heuristic_radius)
+    o.step_budget = int(step_budget)
+    o.pop_order = POP_ORDERS[pop_order] if isinstance(pop_order, str) else int(pop_order)
+    o.epsilon_ppm = int(epsilon_ppm)
+    o.eager_goal = 1 if eager_goal else 0
     return o
 
 
 def mos_solve(graph: Graph, start: int, goal: int, **opts) -> Result:
+    """The exact front; with step_budget, a query still running after that many
+    steps returns its exact prefix (Result.complete False)."""
     o = make_options(**opts)
     h = _vp()
-    _check(_lib.mos_solve(graph.handle, int(start), int(goal), ctypes.byref(o), ctypes.byref(h)),
-           "mos_solve")
+    st = _lib.mos_solve(graph.handle, int(start), int(goal), ctypes.byref(o), ctypes.byref(h))
+    if st == MOS_E_STEP_LIMIT and h:
+        return _take_result(h, complete=False)
+    _check(st, "mos_solve")
     return _take_result(h)
 
 
@@ -261,7 +280,8 @@ def mos_solve_batch(graph: Graph, starts, goals, n_objectives=None, **opts):
         raise MosError(rc, "mos_solve_batch")
     res = []
     for i in range(nq):
-        res.append((int(sts[i]), _take_result(outs[i]) if outs[i] else None))
+        st = int(sts[i])
+        res.append((st, _take_result(outs[i], complete=st == MOS_OK) if outs[i] else None))
     return res
 
 
@@ -299,6 +319,15 @@ class Session:
         h = _vp()
         _check(_lib.mos_session_result(self._h, ctypes.byref(h)), "mos_session_result")
         return _take_result(h)
+
+    def front_so_far(self):
+        """(goal front so far as a Result, smallest F1 left in OPEN): the
+        entries whose first objective is below that bound are final."""
+        h = _vp()
+        m = ctypes.c_int32()
+        _check(_lib.mos_session_front(self._h, ctypes.byref(m), ctypes.byref(h)),
+               "mos_session_front")
+        return _take_result(h, complete=False), int(m.value)
 
     def set_profile(self, mask: int) -> None:
         """Time the kernels whose bit is set (kernel order of kernel_times); 0 = none."""
@@ -342,11 +371,19 @@ class Session:
 class Server:
     """Continuous-batching request loop (``mos_server_*``)."""
 
-    def __init__(self, graph: Graph, mem_budget: int = 0, max_slots: int = 0):
+    def __init__(self, graph: Graph, mem_budget: int = 0, max_slots: int = 0, **opts):
+        """opts: solve options applied to every query (batch_width,
+        steps_per_poll, step_budget, costs_only, ...; mos_server_create_ex)."""
         self.graph = graph
         h = _vp()
-        _check(_lib.mos_server_create(graph.handle, int(mem_budget), int(max_slots),
-                                      ctypes.byref(h)), "mos_server_create")
+        if opts:
+            o = make_options(**opts)
+            _check(_lib.mos_server_create_ex(graph.handle, int(mem_budget), int(max_slots),
+                                             ctypes.byref(o), ctypes.byref(h)),
+                   "mos_server_create_ex")
+        else:
+            _check(_lib.mos_server_create(graph.handle, int(mem_budget), int(max_slots),
+                                          ctypes.byref(h)), "mos_server_create")
         self._h = h
 
     def submit(self, start, goal, n_objectives=0) -> int:
@@ -364,7 +401,8 @@ class Server:
             return None
         if st == MOS_E_INVALID_ARG:
             raise MosError(st, "mos_server_poll")
-        return st, (_take_result(h) if st == MOS_OK else None)
+        return st, (_take_result(h, complete=st == MOS_OK)
+                    if st in (MOS_OK, MOS_E_STEP_LIMIT) and h else None)
 
     def wait(self, ticket, timeout_ms=-1):
         h = _vp()
@@ -373,7 +411,8 @@ class Server:
             return None
         if st == MOS_E_INVALID_ARG:
             raise MosError(st, "mos_server_wait")
-        return st, (_take_result(h) if st == MOS_OK else None)
+        return st, (_take_result(h, complete=st == MOS_OK)
+                    if st in (MOS_OK, MOS_E_STEP_LIMIT) and h else None)
 
     def cancel(self, ticket):
         _check(_lib.mos_server_cancel(self._h, ctypes.c_uint64(ticket)), "mos_server_cancel")

@@ -28,7 +28,10 @@
 #include <thread>
 #include <vector>
 
+#include "front.h"
+#include "graph_internal.h"
 #include "kernels.h"
+#include "layout.h"
 #include "mos.h"
 
 using namespace mos;
@@ -57,6 +60,32 @@ static thread_local int g_site = 0;
 static mos_status set_err(mos_status s, const std::string& m) {
   g_last_error = m;
   return s;
+}
+
+mos_status mos_internal_set_error(mos_status s, const std::string& m) { return set_err(s, m); }
+
+void mos_internal_stats_of(const Slot& d, mos_stats* o) {
+  o->pops = d.st[ST_POPS];
+  o->goal_pops = d.st[ST_GOAL_POPS];
+  o->candidates = d.st[ST_CANDS];
+  o->p_pairs = d.st[ST_PPAIRS];
+  o->group_pairs = d.st[ST_GPAIRS];
+  o->frontier_pairs = d.st[ST_FPAIRS];
+  o->inserted = d.st[ST_INSERTED];
+  o->pruned = d.st[ST_PRUNED];
+  o->steps = d.st[ST_STEPS];
+  o->front = d.P_n - d.P_dead;
+  o->frontier_bytes = d.st[ST_FBYTES];
+  o->killed = d.st[ST_KILLED];
+  o->frontier_bytes_onepass = d.st[ST_FBYTES_WAVE];
+  o->pairs_onepass = d.st[ST_PAIRS_WAVE];
+  o->near_scanned = d.st[ST_NEAR_SCAN];
+  o->far_scanned = d.st[ST_FAR_SCAN];
+  o->tie_entries = d.st[ST_TIE];
+  o->front_reads = d.st[ST_PREAD];
+  o->search_ms = 0;
+  o->heuristic_ms = 0;
+  o->open_min_f1 = d.status == S_DONE ? INT32_MAX : -1;
 }
 
 template <class F>
@@ -180,10 +209,14 @@ struct mos_graph {
   }
 };
 
+GraphDev mos_internal_graph_view(const mos_graph* g) { return g->view(); }
+int mos_internal_graph_device(const mos_graph* g) { return g->device; }
+
 // ----------------------------------------------------------------- result
 struct mos_result {
   int32_t d = 0;
   int64_t size = 0;
+  bool complete = true;  // false: the exact part below stats.open_min_f1 only
   std::vector<int32_t> costs;     // size*d, lexicographically ascending
   std::vector<int64_t> path_off;  // size+1 (empty when paths were not requested)
   std::vector<int32_t> arcs;
@@ -236,128 +269,16 @@ struct RangeAlloc {
 };
 
 // ----------------------------------------------------------- slot layout
-struct Layout {
-  int32_t B, batch_cap, cand_cap, tie_cap, pool_cap, open_cap, P_cap;
-  int64_t fw_cap;
-  int64_t bytes;
-};
-
-static inline int64_t al(int64_t x) { return (x + 255) & ~int64_t(255); }
-
-// per-tile counts of the batch split: SPLIT_WORDS ints per SPLIT_TILE items
-// (direct pops and tie entries)
-static inline int64_t split_tile_bytes(int64_t batch_cap, int64_t tie_cap) {
-  return 4 * (int64_t)SPLIT_WORDS * ((batch_cap + tie_cap) / SPLIT_TILE + 2);
-}
-
-static int64_t fixed_bytes(int64_t n, int d, int batch_cap, int cand_cap, int tie_cap) {
-  int64_t b = 0;
-  b += al(4 * d * n) + al(16 * n) + 2 * al(4 * n);                   // h, node, grp
-  b += 4 * al(4 * (int64_t)batch_cap) + al(4 * ((int64_t)batch_cap + 1));  // batch, reg, goal, kill, reg_off
-  b += 13 * al(4 * ((int64_t)cand_cap + 1)) + al(4 * (int64_t)d * cand_cap) + al(8 * (int64_t)cand_cap);
-  b += al(8 * ((int64_t)cand_cap / ACC_TILE + 2));  // per-tile accept counts
-  return b + 64 * 256;
-}
-
-// Split a reservation of `budget` bytes: fixed per-query regions, then label
-// pool, OPEN (double buffered), goal front (double buffered) and frontier
-// words in proportion to the pool size.
 static bool plan_layout(const mos_graph* g, int d, int B, int64_t budget, int64_t label_limit,
                         Layout* L) {
-  L->B = B;
-  L->batch_cap = std::min(2 * B, BATCH_MAX);
-  L->cand_cap = L->batch_cap * std::max(1, g->maxdeg);
-  L->tie_cap = TIECAP;
-  const int64_t fixed = fixed_bytes(g->n, d, L->batch_cap, L->cand_cap, 0);
-  if (budget <= fixed) return false;
-  // bytes per pooled label: pool (node, parent, arc, g, state, tested mark) + OPEN 2x(F1,
-  // lab) + tie set (F1, lab, state, d key words, split tile share) + frontier 3*(d+1)
-  // words + goal front share
-  const double per = (16.0 + 4.0 * d + 1.0) + 32.0 + 12.0 + 4.0 * d +
-                     4.0 * SPLIT_WORDS / SPLIT_TILE + 12.0 * (d + 1) + (8.0 * (d + 2) + 8.0) / 8.0;
-  int64_t pool = (int64_t)((double)(budget - fixed - 48 * 256) / per);
-  pool = std::min<int64_t>(pool, (int64_t)1 << 30);
-  if (label_limit > 0) pool = std::min<int64_t>(pool, label_limit);
-  if (pool < 16) return false;
-  L->pool_cap = (int32_t)pool;
-  L->open_cap = (int32_t)pool;
-  L->tie_cap = (int32_t)pool;
-  L->P_cap = (int32_t)std::max<int64_t>(std::min<int64_t>(pool, 1024), pool / 8);
-  L->fw_cap = 3 * (int64_t)(d + 1) * pool + (int64_t)MINCAP * (d + 1);
-  int64_t b = fixed;
-  b += 3 * al(4 * pool) + al(4 * (int64_t)d * pool) + al(pool);  // pool
-  b += 8 * al(4 * pool);                                          // OPEN near + far tiers
-  b += 3 * al(4 * pool) + al(4 * (int64_t)d * pool);             // tie set and its keys
-  b += al(split_tile_bytes(L->batch_cap, (int32_t)pool));         // batch split tiles
-  b += 2 * (al(4 * (int64_t)d * L->P_cap) + 2 * al(4 * (int64_t)L->P_cap)) + al(4 * pool);
-  b += al(4 * L->fw_cap);
-  L->bytes = al(b);
-  return L->bytes <= budget;
+  return plan_slot_layout(g->n, g->maxdeg, d, B, budget, label_limit, L);
 }
 
-// Carve the reservation at `base` into the regions of a Slot.
 static void carve(Slot& s, char* base, const Layout& L, int64_t n, int d) {
-  char* p = base;
-  auto take = [&](int64_t bytes) {
-    char* r = p;
-    p += al(bytes);
-    return r;
-  };
-  s.h = (int32_t*)take(4 * d * n);
-  s.node = (NodeRec*)take(16 * n);
-  s.grp_cnt = (int32_t*)take(4 * n);
-  s.grp_id = (int32_t*)take(4 * n);
-  s.batch = (int32_t*)take(4 * (int64_t)L.batch_cap);
-  s.reg = (int32_t*)take(4 * (int64_t)L.batch_cap);
-  s.goal_lab = (int32_t*)take(4 * (int64_t)L.batch_cap);
-  s.reg_off = (int32_t*)take(4 * ((int64_t)L.batch_cap + 1));
-  s.reg_kill = (int32_t*)take(4 * (int64_t)L.batch_cap);
-  const int64_t cc = L.cand_cap;
-  s.c_node = (int32_t*)take(4 * cc);
-  s.c_par = (int32_t*)take(4 * cc);
-  s.c_arc = (int32_t*)take(4 * cc);
-  s.c_keep = (int32_t*)take(4 * cc);
-  s.c_rank = (int32_t*)take(4 * cc);
-  s.c_rej = (int32_t*)take(4 * cc);
-  s.c_acc = (int32_t*)take(4 * cc);
-  s.order = (int32_t*)take(4 * cc);
-  s.grp_node = (int32_t*)take(4 * cc);
-  s.grp_off = (int32_t*)take(4 * cc);
-  s.small_list = (int32_t*)take(4 * (cc + 1));
-  s.big_list = (int32_t*)take(4 * (cc + 1));
-  s.big_toff = (int32_t*)take(4 * (cc + 1));
-  s.c_g = (int32_t*)take(4 * (int64_t)d * cc);
-  s.c_fslot = (int64_t*)take(8 * cc);
-  s.acc_tile = (int32_t*)take(8 * (cc / ACC_TILE + 2));
-  const int64_t pc = L.pool_cap;
-  s.Lnode = (int32_t*)take(4 * pc);
-  s.Lpar = (int32_t*)take(4 * pc);
-  s.Larc = (int32_t*)take(4 * pc);
-  s.Lg = (int32_t*)take(4 * (int64_t)d * pc);
-  s.Lpseq = (int32_t*)take(4 * pc);
-  s.Lstate = (uint8_t*)take(pc);
-  for (int b = 0; b < 2; ++b) {
-    s.open_f1[b] = (int32_t*)take(4 * (int64_t)L.open_cap);
-    s.open_lab[b] = (int32_t*)take(4 * (int64_t)L.open_cap);
-    s.far_f1[b] = (int32_t*)take(4 * (int64_t)L.open_cap);
-    s.far_lab[b] = (int32_t*)take(4 * (int64_t)L.open_cap);
-  }
-  s.tie_f1 = (int32_t*)take(4 * (int64_t)L.tie_cap);
-  s.tie_lab = (int32_t*)take(4 * (int64_t)L.tie_cap);
-  s.tie_st = (int32_t*)take(4 * (int64_t)L.tie_cap);
-  s.tie_key = (int32_t*)take(4 * (int64_t)d * L.tie_cap);
-  s.split_tile = (int32_t*)take(split_tile_bytes(L.batch_cap, L.tie_cap));
-  for (int b = 0; b < 2; ++b) {
-    s.Pg[b] = (int32_t*)take(4 * (int64_t)d * L.P_cap);
-    s.Plab[b] = (int32_t*)take(4 * (int64_t)L.P_cap);
-    s.Pseq[b] = (int32_t*)take(4 * (int64_t)L.P_cap);
-  }
-  s.fw = (int32_t*)take(4 * L.fw_cap);
-  if (p - base > L.bytes) throw MosError(MOS_E_DEVICE, "slot layout overrun");
+  if (!carve_slot(s, base, L, n, d)) throw MosError(MOS_E_DEVICE, "slot layout overrun");
 }
 
 // ------------------------------------------------------------------ engine
-constexpr int kDefaultHeurFactor = 4;  // heuristic radius: 4 x h(start), per objective
 
 struct QueryReq {
   int64_t id = 0;
@@ -365,6 +286,10 @@ struct QueryReq {
   int32_t heur_factor = kDefaultHeurFactor;  // 0 = exact heuristic on the whole graph
   int64_t reserve = 0;  // bytes of the next admission attempt
   int attempts = 0;
+  int64_t step_budget = 0;  // steps after which the exact prefix is returned (0 = none)
+  int32_t pop_order = 0;    // MOS_POP_*
+  int32_t eps_ppm = 0;      // approximate mode (0 = exact)
+  int32_t eager_goal = 0;
 };
 
 struct Finished {
@@ -431,9 +356,7 @@ class Engine {
     hipStreamSynchronize(st_);
     for (auto& e : pev_) hipEventDestroy(e);
     if (graph_exec_) hipGraphExecDestroy(graph_exec_);
-    for (auto& x : pgraph_exec_)
-      if (x) hipGraphExecDestroy(x);
-    for (auto& e : gev_) hipEventDestroy(e);
+
     if (hslots_) hipHostFree(hslots_);
     hipEventDestroy(ev0_);
     hipEventDestroy(ev1_);
@@ -444,6 +367,7 @@ class Engine {
     hscr_.reset();
     hcnt_.reset();
     hjob_.reset();
+    omin_.reset();
     if (own_stream_) hipStreamDestroy(st_);
   }
 
@@ -545,6 +469,9 @@ class Engine {
       s.query_id = (int32_t)q.id;
       s.heur_factor = q.heur_factor;
       s.hn = g_->n;
+      s.pop_fifo = q.pop_order == MOS_POP_GENERATION ? 1 : 0;
+      s.eps_ppm = q.eps_ppm;
+      s.eager_goal = q.eager_goal;
       carve(s, arena_.as<char>() + off * 256, L, g_->n, q.d);
       HIPCHK(hipMemcpyAsync((char*)slots_.p + (size_t)free_slot * sizeof(Slot), &s, sizeof(Slot),
                             hipMemcpyHostToDevice, st_));
@@ -573,7 +500,17 @@ class Engine {
     for (int s = 0; s < S_; ++s) {
       if (!sh_[s].busy) continue;
       const Slot& d = hslots_[s];
-      if (d.status == S_RUN) continue;
+      if (d.status == S_RUN) {
+        const int64_t budget = sh_[s].q.step_budget;
+        if (budget > 0 && d.st[ST_STEPS] >= budget) {
+          Finished f{sh_[s].q.id, MOS_E_STEP_LIMIT, nullptr,
+                     "step budget reached: the result is the exact front below stats.open_min_f1"};
+          f.res = harvest_prefix(s);
+          release(s);
+          done.push_back(f);
+        }
+        continue;
+      }
       if (d.status == S_DONE) {
         Finished f{sh_[s].q.id, MOS_OK, nullptr, ""};
         f.res = harvest(s);
@@ -618,7 +555,6 @@ class Engine {
   const SlotHost& host0() const { return sh_[0]; }
   void set_profile(uint32_t mask) {
     drain_profile();
-    if (mask != profile_ && pgraph_exec_[0]) drop_profile_graphs();
     profile_ = mask;
   }
   int64_t graph_replays() const { return graph_replays_; }
@@ -631,27 +567,17 @@ class Engine {
     release(0);
     return r;
   }
+  // The goal front of slot 0 so far and the smallest F1 left in OPEN.
+  mos_result* front_so_far0(int32_t* m) {
+    *m = open_min_f1(0);
+    mos_result* r = harvest(0);
+    r->stats.open_min_f1 = *m;
+    r->complete = false;
+    return r;
+  }
   mos_stats stats_of(int s) const {
-    const Slot& d = hslots_[s];
     mos_stats o{};
-    o.pops = d.st[ST_POPS];
-    o.goal_pops = d.st[ST_GOAL_POPS];
-    o.candidates = d.st[ST_CANDS];
-    o.p_pairs = d.st[ST_PPAIRS];
-    o.group_pairs = d.st[ST_GPAIRS];
-    o.frontier_pairs = d.st[ST_FPAIRS];
-    o.inserted = d.st[ST_INSERTED];
-    o.pruned = d.st[ST_PRUNED];
-    o.steps = d.st[ST_STEPS];
-    o.front = d.P_n - d.P_dead;
-    o.frontier_bytes = d.st[ST_FBYTES];
-    o.killed = d.st[ST_KILLED];
-    o.frontier_bytes_onepass = d.st[ST_FBYTES_WAVE];
-    o.pairs_onepass = d.st[ST_PAIRS_WAVE];
-    o.near_scanned = d.st[ST_NEAR_SCAN];
-    o.far_scanned = d.st[ST_FAR_SCAN];
-    o.tie_entries = d.st[ST_TIE];
-    o.front_reads = d.st[ST_PREAD];
+    mos_internal_stats_of(hslots_[s], &o);
     o.search_ms = sh_[s].search_ms;
     o.heuristic_ms = sh_[s].heur_ms;
     return o;
@@ -734,26 +660,12 @@ class Engine {
     HIPCHK(hipMemcpyAsync(hjob_.p, fresh.data(), nj * 4, hipMemcpyHostToDevice, st_));
     const GraphDev G = g_->view();
     HIPCHK(hipEventRecord(ev0_, st_));
-    launch_heur_init(slots_.as<Slot>(), hjob_.as<int32_t>(), nj, G, hscr_.as<int32_t>(),
-                     hcnt_.as<int32_t>(), st_);
-    HIPCHK(hipGetLastError());
     std::vector<int32_t> cnt((size_t)nj * MAXD * 3);
-    const int gx = std::max(1, std::min(512, (g_->n / 8 + 255) / 256));
-    for (int r = 0;; ++r) {
-      launch_heur_round(slots_.as<Slot>(), hjob_.as<int32_t>(), nj, G, hscr_.as<int32_t>(),
-                        hcnt_.as<int32_t>(), r, gx, st_);
-      if ((r & 7) == 7) {
-        HIPCHK(hipMemcpyAsync(cnt.data(), hcnt_.p, cnt.size() * 4, hipMemcpyDeviceToHost, st_));
-        HIPCHK(hipStreamSynchronize(st_));
-        // after round r the worklist of round r+1 is in counter (r+1)%3
-        bool any = false;
-        for (int j = 0; j < nj && !any; ++j)
-          for (int k = 0; k < MAXD && !any; ++k) any = cnt[((size_t)j * MAXD + k) * 3 + (r + 1) % 3] > 0;
-        if (!any) break;
-      }
-      if (r > 4 * g_->n + 64) throw MosError(MOS_E_DEVICE, "heuristic did not converge");
-    }
-    launch_heur_clamp(slots_.as<Slot>(), hjob_.as<int32_t>(), nj, G, st_);
+    const int rc = run_heuristic(slots_.as<Slot>(), hjob_.as<int32_t>(), nj, G, hscr_.as<int32_t>(),
+                                 hcnt_.as<int32_t>(), cnt.data(), st_);
+    if (rc == -2) throw MosError(MOS_E_DEVICE, "heuristic did not converge");
+    if (rc != 0) throw MosError(MOS_E_DEVICE, "heuristic: a HIP call failed");
+    HIPCHK(hipGetLastError());
     if (seed)
       for (int s : fresh) launch_slot_init(slots_.as<Slot>(), s, G, st_);
     HIPCHK(hipGetLastError());
@@ -779,16 +691,13 @@ class Engine {
     return a;
   }
 
-  // Capture K_ steps into an executable graph; with `events`, the kernels
-  // selected by profile_ are bracketed by event-record nodes (one event set
-  // per captured step).  Returns nullptr when capture is not possible.
-  hipGraphExec_t capture_steps(const StepArgs& a, hipEvent_t* events) {
-    constexpr int NE = kStepKernels + 1;
+  // Capture K_ steps into an executable graph (nullptr when capture is not
+  // possible).
+  hipGraphExec_t capture_steps(const StepArgs& a) {
     hipGraph_t gr = nullptr;
     hipGraphExec_t ex = nullptr;
     if (hipStreamBeginCapture(st_, hipStreamCaptureModeThreadLocal) == hipSuccess) {
-      for (int k = 0; k < K_; ++k)
-        launch_step(a, st_, events ? events + (size_t)k * NE : nullptr, events ? profile_ : 0u);
+      for (int k = 0; k < K_; ++k) launch_step(a, st_);
       if (hipStreamEndCapture(st_, &gr) != hipSuccess || !gr ||
           hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0) != hipSuccess)
         ex = nullptr;
@@ -799,43 +708,17 @@ class Engine {
   }
 
   // K_ steps are captured once into a graph and replayed; the remainder is
-  // launched directly.  In profile mode the replayed graph carries event
-  // records around the timed kernels and is drained after every replay; if
-  // such a graph cannot be captured the profiled steps are launched one by one.
+  // launched directly, and so is every step in profile mode.
   void launch_steps(int64_t n) {
     const StepArgs a = step_args();
     if (profile_) {
-      constexpr int NE = kStepKernels + 1;
-      if (use_graph_ && n >= K_ && !pgraph_failed_ && !pgraph_exec_[0]) {
-        if (gev_.empty()) {
-          gev_.resize((size_t)2 * K_ * NE);
-          for (auto& e : gev_) HIPCHK(hipEventCreate(&e));
-        }
-        drain_profile();
-        // two graphs with their own event sets: one is read back while the
-        // other runs, so the device never waits for the host between replays
-        for (int b = 0; b < 2 && !pgraph_failed_; ++b) {
-          pgraph_exec_[b] = capture_steps(a, gev_.data() + (size_t)b * K_ * NE);
-          pgraph_failed_ = pgraph_exec_[b] == nullptr;
-        }
-        if (pgraph_failed_) drop_profile_graphs();
-      }
-      if (pgraph_exec_[0]) {
-        int prev = -1;
-        for (; n >= K_; n -= K_) {
-          const int b = prev == 0 ? 1 : 0;
-          HIPCHK(hipGraphLaunch(pgraph_exec_[b], st_));
-          ++graph_replays_;
-          if (prev >= 0) drain_graph_events(prev);
-          prev = b;
-        }
-        if (prev >= 0) drain_graph_events(prev);
-      }
+      // events bracketing kernels are not timed when recorded inside a
+      // captured graph on this runtime, so profiled steps launch directly
       for (; n > 0; --n) profiled_step(a);
       return;
     }
     if (use_graph_ && !graph_exec_ && !graph_failed_ && n >= K_) {
-      graph_exec_ = capture_steps(a, nullptr);
+      graph_exec_ = capture_steps(a);
       graph_failed_ = graph_exec_ == nullptr;
     }
     if (graph_exec_) {
@@ -849,31 +732,6 @@ class Engine {
       ++direct_steps_;
     }
     HIPCHK(hipGetLastError());
-  }
-
-  void drop_profile_graphs() {
-    HIPCHK(hipStreamSynchronize(st_));
-    for (auto& x : pgraph_exec_) {
-      if (x) hipGraphExecDestroy(x);
-      x = nullptr;
-    }
-  }
-
-  // Read the event sets of one replay of profiling graph b.
-  void drain_graph_events(int b) {
-    constexpr int NE = kStepKernels + 1;
-    hipEvent_t* base = &gev_[(size_t)b * K_ * NE];
-    HIPCHK(hipEventSynchronize(base[(size_t)(K_ - 1) * NE + kStepKernels]));
-    for (int k = 0; k < K_; ++k) {
-      hipEvent_t* set = base + (size_t)k * NE;
-      for (int i = 0; i < kStepKernels; ++i) {
-        if (!((profile_ >> i) & 1u)) continue;
-        float ms = 0;
-        HIPCHK(hipEventElapsedTime(&ms, set[i], set[i + 1]));
-        kms_[i] += ms;
-        klaunch_[i]++;
-      }
-    }
   }
 
   // Profile mode: every kernel of every step is bracketed by events; a ring of
@@ -910,44 +768,66 @@ class Engine {
     while (ring_used_ > 0) drain_one();
   }
 
+  // Smallest F1 left in slot s's OPEN (INT32_MAX when empty).
+  int32_t open_min_f1(int s) {
+    if (omin_.bytes < 4) omin_.alloc(256, st_);
+    launch_open_min(slots_.as<Slot>(), s, omin_.as<int32_t>(), st_);
+    HIPCHK(hipGetLastError());
+    int32_t m = INT32_MAX;
+    HIPCHK(hipMemcpyAsync(&m, omin_.p, 4, hipMemcpyDeviceToHost, st_));
+    HIPCHK(hipStreamSynchronize(st_));
+    return m;
+  }
+
+  // An unfinished query's exact part of the front: the sorted goal front so
+  // far cut to the entries whose first objective lies below the smallest F1
+  // left in OPEN (every later goal label costs at least that much there, so
+  // these entries are final and no other final entry lies below the bound).
+  mos_result* harvest_prefix(int s) {
+    const int32_t m = open_min_f1(s);
+    mos_result* r = harvest(s);
+    int64_t k = 0;
+    while (k < r->size && r->costs[(size_t)k * r->d] < m) ++k;
+    r->size = k;
+    r->costs.resize((size_t)k * r->d);
+    if (!r->path_off.empty()) {
+      r->path_off.resize(k + 1);
+      r->arcs.resize(r->path_off[k]);
+    }
+    r->stats.front = k;
+    r->stats.open_min_f1 = m;
+    r->complete = false;
+    return r;
+  }
+
   // The goal front of slot s: live entries (tombstones dropped), sorted
-  // lexicographically ascending, with their witness paths.
+  // lexicographically ascending on the device, with their witness paths.
   mos_result* harvest(int s) {
     const Slot& d = hslots_[s];
     std::unique_ptr<mos_result> r(new mos_result());
     const int dd = d.d;
-    const int64_t nall = d.P_n;
-    std::vector<int32_t> planes((size_t)nall * dd), lab(nall);
-    for (int k = 0; k < dd && nall > 0; ++k)
-      HIPCHK(hipMemcpyAsync(planes.data() + (size_t)k * nall, d.Pg[d.P_sel] + (size_t)k * d.P_cap,
-                            nall * 4, hipMemcpyDeviceToHost, st_));
-    if (nall > 0)
-      HIPCHK(hipMemcpyAsync(lab.data(), d.Plab[d.P_sel], nall * 4, hipMemcpyDeviceToHost, st_));
-    HIPCHK(hipStreamSynchronize(st_));
-    std::vector<int64_t> idx;
-    for (int64_t i = 0; i < nall; ++i)
-      if (planes[i] != INT32_MAX) idx.push_back(i);
-    std::sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) {
-      for (int k = 0; k < dd; ++k) {
-        const int32_t x = planes[(size_t)k * nall + a], y = planes[(size_t)k * nall + b];
-        if (x != y) return x < y;
-      }
-      return false;
-    });
-    const int64_t np = (int64_t)idx.size();
+    const int nall = d.P_n;
+    DevBuf fsw, rows, labs;
+    int np = 0;
+    if (nall > 0) {
+      fsw.alloc(front_sort_scratch_bytes(nall), st_);
+      rows.alloc((size_t)nall * dd * 4, st_);
+      labs.alloc((size_t)nall * 4, st_);
+      np = front_sort(d.Pg[d.P_sel], d.P_cap, d.Plab[d.P_sel], dd, nall, fsw.p, rows.as<int32_t>(),
+                      labs.as<int32_t>(), st_);
+      if (np < 0) HIPCHK(hipGetLastError());
+      if (np < 0) throw MosError(MOS_E_DEVICE, "front sort failed");
+    }
     r->d = dd;
     r->size = np;
     r->costs.resize((size_t)np * dd);
-    std::vector<int32_t> sl(np);
-    for (int64_t j = 0; j < np; ++j) {
-      for (int k = 0; k < dd; ++k) r->costs[(size_t)j * dd + k] = planes[(size_t)k * nall + idx[j]];
-      sl[j] = lab[idx[j]];
-    }
+    if (np > 0)
+      HIPCHK(hipMemcpyAsync(r->costs.data(), rows.p, (size_t)np * dd * 4, hipMemcpyDeviceToHost,
+                            st_));
+    HIPCHK(hipStreamSynchronize(st_));
     if (want_paths_ && np > 0) {
-      DevBuf labs, len, off, arcs;
-      labs.alloc(np * 4, st_);
+      DevBuf len, off, arcs;
       len.alloc(np * 4, st_);
-      HIPCHK(hipMemcpyAsync(labs.p, sl.data(), np * 4, hipMemcpyHostToDevice, st_));
       launch_path_len(slots_.as<Slot>(), s, labs.as<int32_t>(), (int)np, len.as<int32_t>(), st_);
       std::vector<int32_t> hl(np);
       HIPCHK(hipMemcpyAsync(hl.data(), len.p, np * 4, hipMemcpyDeviceToHost, st_));
@@ -980,7 +860,7 @@ class Engine {
   int K_;
   hipStream_t st_ = nullptr;
   bool own_stream_ = false;
-  DevBuf arena_, slots_, hist_, hscr_, hcnt_, hjob_;
+  DevBuf arena_, slots_, hist_, hscr_, hcnt_, hjob_, omin_;
   Slot* hslots_ = nullptr;
   RangeAlloc ra_;
   std::vector<SlotHost> sh_;
@@ -989,9 +869,6 @@ class Engine {
   hipEvent_t ev0_ = nullptr, ev1_ = nullptr;
   hipGraphExec_t graph_exec_ = nullptr;
   bool graph_failed_ = false;
-  hipGraphExec_t pgraph_exec_[2] = {};    // profiling graphs (event records inside)
-  bool pgraph_failed_ = false;
-  std::vector<hipEvent_t> gev_;           // K_ event sets of the profiling graph
   int64_t graph_replays_ = 0, direct_steps_ = 0;
   bool use_graph_ = true;
   bool progress_ = false;
@@ -1036,15 +913,9 @@ static void release_engine(const mos_graph* gc, const EngineKey& k, Engine* e) {
 }
 
 // ------------------------------------------------------------ option helpers
-struct Opts {
-  int n_objectives = 0, B = 256, max_slots = 0, want_paths = 1, steps = 8;
-  int heur_factor = kDefaultHeurFactor;
-  uint32_t profile = 0;
-  int64_t label_limit = 0, mem_budget = 0;
-  hipStream_t stream = nullptr;
-};
+using Opts = MosOpts;
 
-static mos_status read_opts(const mos_options* o, Opts* out) {
+mos_status mos_internal_read_options(const mos_options* o, MosOpts* out) {
   Opts r;
   if (o) {
     if (o->struct_size < offsetof(mos_options, costs_only))
@@ -1054,20 +925,33 @@ static mos_status read_opts(const mos_options* o, Opts* out) {
     r.max_slots = o->max_slots;
     r.label_limit = o->label_limit;
     r.mem_budget = o->mem_budget;
-    r.stream = (hipStream_t)o->stream;
+    r.stream = o->stream;
     if (o->struct_size >= offsetof(mos_options, steps_per_poll)) r.want_paths = o->costs_only ? 0 : 1;
     if (o->struct_size >= offsetof(mos_options, profile_kernels) && o->steps_per_poll > 0)
       r.steps = o->steps_per_poll;
     if (o->struct_size >= offsetof(mos_options, heuristic_radius)) r.profile = (uint32_t)o->profile_kernels;
-    if (o->struct_size >= sizeof(mos_options))
+    if (o->struct_size >= offsetof(mos_options, step_budget))
       r.heur_factor = o->heuristic_radius == 0 ? kDefaultHeurFactor
                                                : (o->heuristic_radius < 0 ? 0 : o->heuristic_radius);
+    if (o->struct_size >= offsetof(mos_options, step_budget) + sizeof(int64_t))
+      r.step_budget = o->step_budget;
+    if (o->struct_size >= offsetof(mos_options, pop_order) + sizeof(int32_t))
+      r.pop_order = o->pop_order;
+    if (o->struct_size >= offsetof(mos_options, epsilon_ppm) + sizeof(int32_t))
+      r.eps_ppm = o->epsilon_ppm;
+    if (o->struct_size >= offsetof(mos_options, eager_goal) + sizeof(int32_t))
+      r.eager_goal = o->eager_goal ? 1 : 0;
   }
   if (r.B < 1 || r.B > BATCH_MAX)
     return set_err(MOS_E_INVALID_ARG, "batch_width must lie in [1, 32768]");
   if (r.max_slots < 0 || r.label_limit < 0 || r.mem_budget < 0 || r.n_objectives < 0)
     return set_err(MOS_E_INVALID_ARG, "negative option");
   if (r.steps > 1024) return set_err(MOS_E_INVALID_ARG, "steps_per_poll too large");
+  if (r.step_budget < 0) return set_err(MOS_E_INVALID_ARG, "negative step_budget");
+  if (r.pop_order != MOS_POP_LEXICOGRAPHIC && r.pop_order != MOS_POP_GENERATION)
+    return set_err(MOS_E_INVALID_ARG, "unknown pop_order");
+  if (r.eps_ppm < 0 || r.eps_ppm > 1000000000)
+    return set_err(MOS_E_INVALID_ARG, "epsilon_ppm must lie in [0, 10^9]");
   *out = r;
   return MOS_OK;
 }
@@ -1081,6 +965,14 @@ static int64_t default_budget(int64_t want) {
     return want;
   }
   return std::min<int64_t>(cap, (int64_t)48 << 30);
+}
+
+mos_status mos_internal_check_query(const mos_graph* g, int32_t s, int32_t t, int32_t nobj, int* d) {
+  if (s < 0 || s >= g->n || t < 0 || t >= g->n)
+    return set_err(MOS_E_INVALID_ARG, "start or goal out of range");
+  if (nobj < 0 || nobj > g->D) return set_err(MOS_E_INVALID_ARG, "n_objectives out of range");
+  *d = nobj == 0 ? g->D : nobj;
+  return MOS_OK;
 }
 
 // ------------------------------------------------------------------ C ABI
@@ -1098,6 +990,7 @@ const char* mos_status_string(mos_status s) {
     case MOS_E_LABEL_LIMIT: return "label limit";
     case MOS_E_CANCELLED: return "cancelled";
     case MOS_E_NOT_READY: return "not ready";
+    case MOS_E_STEP_LIMIT: return "step budget reached (exact prefix returned)";
   }
   return "unknown status";
 }
@@ -1194,13 +1087,6 @@ void mos_graph_destroy(mos_graph* g) {
   delete g;
 }
 
-static mos_status check_query(const mos_graph* g, int32_t s, int32_t t, int32_t nobj, int* d) {
-  if (s < 0 || s >= g->n || t < 0 || t >= g->n)
-    return set_err(MOS_E_INVALID_ARG, "start or goal out of range");
-  if (nobj < 0 || nobj > g->D) return set_err(MOS_E_INVALID_ARG, "n_objectives out of range");
-  *d = nobj == 0 ? g->D : nobj;
-  return MOS_OK;
-}
 
 mos_status mos_solve_batch(const mos_graph* g, int32_t nq, const int32_t* starts,
                            const int32_t* goals, const int32_t* n_objectives,
@@ -1208,12 +1094,12 @@ mos_status mos_solve_batch(const mos_graph* g, int32_t nq, const int32_t* starts
   if (!g || nq < 0 || (nq > 0 && (!starts || !goals || !out || !st)))
     return set_err(MOS_E_INVALID_ARG, "NULL argument or negative count");
   Opts o;
-  mos_status rs = read_opts(opt, &o);
+  mos_status rs = mos_internal_read_options(opt, &o);
   if (rs != MOS_OK) return rs;
   std::vector<int> dq(nq);
   for (int32_t i = 0; i < nq; ++i) {
     int32_t nobj = n_objectives ? n_objectives[i] : o.n_objectives;
-    rs = check_query(g, starts[i], goals[i], nobj, &dq[i]);
+    rs = mos_internal_check_query(g, starts[i], goals[i], nobj, &dq[i]);
     if (rs != MOS_OK) return rs;
   }
   if (nq == 0) return MOS_OK;
@@ -1228,7 +1114,7 @@ mos_status mos_solve_batch(const mos_graph* g, int32_t nq, const int32_t* starts
     while (S < want) S <<= 1;
     const EngineKey key{S, dm_for(g->D), o.mem_budget, (void*)o.stream, o.B, o.label_limit,
                         o.want_paths != 0, o.steps};
-    Engine* ep = acquire_engine(g, key, default_budget(o.mem_budget), o.stream);
+    Engine* ep = acquire_engine(g, key, default_budget(o.mem_budget), (hipStream_t)o.stream);
     std::unique_ptr<Engine> guard(ep);
     Engine& eng = *ep;
     std::deque<QueryReq> pending;
@@ -1239,6 +1125,10 @@ mos_status mos_solve_batch(const mos_graph* g, int32_t nq, const int32_t* starts
       q.goal = goals[i];
       q.d = dq[i];
       q.heur_factor = o.heur_factor;
+      q.step_budget = o.step_budget;
+      q.pop_order = o.pop_order;
+      q.eps_ppm = o.eps_ppm;
+      q.eager_goal = o.eager_goal;
       q.reserve = eng.default_reserve();
       pending.push_back(q);
       out[i] = nullptr;
@@ -1273,10 +1163,10 @@ mos_status mos_solve(const mos_graph* g, int32_t start, int32_t goal, const mos_
                      mos_result** out) {
   if (!g || !out) return set_err(MOS_E_INVALID_ARG, "NULL argument");
   Opts o;
-  mos_status rs = read_opts(opt, &o);
+  mos_status rs = mos_internal_read_options(opt, &o);
   if (rs != MOS_OK) return rs;
   int d;
-  rs = check_query(g, start, goal, o.n_objectives, &d);
+  rs = mos_internal_check_query(g, start, goal, o.n_objectives, &d);
   if (rs != MOS_OK) return rs;
   mos_options o1{};
   if (opt) std::memcpy(&o1, opt, std::min<size_t>(opt->struct_size, sizeof(mos_options)));
@@ -1285,6 +1175,10 @@ mos_status mos_solve(const mos_graph* g, int32_t start, int32_t goal, const mos_
   mos_status st1 = MOS_E_NOT_READY;
   mos_result* r = nullptr;
   rs = mos_solve_batch(g, 1, &start, &goal, nullptr, &o1, &r, &st1);
+  if (rs == MOS_E_STEP_LIMIT && r) {
+    *out = r;  // the exact prefix (see mos_options.step_budget)
+    return rs;
+  }
   if (rs != MOS_OK) return rs;
   *out = r;
   return MOS_OK;
@@ -1322,7 +1216,7 @@ void mos_result_destroy(mos_result* r) { delete r; }
 mos_status mos_heuristic(const mos_graph* g, int32_t goal, int32_t n_objectives, int32_t* h) {
   if (!g || !h) return set_err(MOS_E_INVALID_ARG, "NULL argument");
   int d;
-  mos_status rs = check_query(g, goal, goal, n_objectives, &d);
+  mos_status rs = mos_internal_check_query(g, goal, goal, n_objectives, &d);
   if (rs != MOS_OK) return rs;
   return guarded([&]() -> mos_status {
     HIPCHK(hipSetDevice(g->device));
@@ -1356,16 +1250,16 @@ mos_status mos_session_create(const mos_graph* g, int32_t start, int32_t goal,
                               const mos_options* opt, mos_session** out) {
   if (!g || !out) return set_err(MOS_E_INVALID_ARG, "NULL argument");
   Opts o;
-  mos_status rs = read_opts(opt, &o);
+  mos_status rs = mos_internal_read_options(opt, &o);
   if (rs != MOS_OK) return rs;
   int d;
-  rs = check_query(g, start, goal, o.n_objectives, &d);
+  rs = mos_internal_check_query(g, start, goal, o.n_objectives, &d);
   if (rs != MOS_OK) return rs;
   return guarded([&]() -> mos_status {
     HIPCHK(hipSetDevice(g->device));
     std::unique_ptr<mos_session> s(new mos_session());
     s->g = g;
-    s->eng.reset(new Engine(g, 1, dm_for(d), default_budget(o.mem_budget), o.stream, o.B,
+    s->eng.reset(new Engine(g, 1, dm_for(d), default_budget(o.mem_budget), (hipStream_t)o.stream, o.B,
                             o.label_limit, o.want_paths != 0, o.steps));
     s->eng->set_profile(o.profile);
     QueryReq q;
@@ -1374,6 +1268,9 @@ mos_status mos_session_create(const mos_graph* g, int32_t start, int32_t goal,
     q.goal = goal;
     q.d = d;
     q.heur_factor = o.heur_factor;
+    q.pop_order = o.pop_order;
+    q.eps_ppm = o.eps_ppm;
+    q.eager_goal = o.eager_goal;
     q.reserve = s->eng->arena_bytes();
     std::string msg;
     mos_status st = s->eng->session_admit(q, &msg);
@@ -1412,6 +1309,21 @@ mos_status mos_session_result(mos_session* s, mos_result** out) {
       return set_err(MOS_E_LABEL_LIMIT, "search state outgrew the reservation");
     *out = s->eng->harvest_slot0();
     s->finished = true;
+    return MOS_OK;
+  });
+}
+
+mos_status mos_session_front(mos_session* s, int32_t* open_min_f1, mos_result** out) {
+  if (!s || !open_min_f1 || !out) return set_err(MOS_E_INVALID_ARG, "NULL argument");
+  if (s->finished) return set_err(MOS_E_INVALID_ARG, "result already taken");
+  return guarded([&]() -> mos_status {
+    HIPCHK(hipSetDevice(s->g->device));
+    if (s->eng->slot0().status == S_OVERFLOW)
+      return set_err(MOS_E_LABEL_LIMIT, "search state outgrew the reservation");
+    int32_t m = INT32_MAX;
+    mos_result* r = s->eng->front_so_far0(&m);
+    *open_min_f1 = m;
+    *out = r;
     return MOS_OK;
   });
 }
@@ -1469,6 +1381,11 @@ struct mos_server {
   std::string fatal;
   mos_status fatal_st = MOS_OK;
   int64_t fail_at_tick = -1;  // test hook (MOS_SERVER_FAIL_AT_TICK): throw before this tick
+  int32_t heur_factor = kDefaultHeurFactor;
+  int64_t step_budget = 0;
+  int32_t pop_order = 0;
+  int32_t eps_ppm = 0;
+  int32_t eager_goal = 0;
 
   // The loop cannot go on (a device error): every query that has not been
   // reported yet -- finished this tick, resident in a slot, queued here or
@@ -1557,16 +1474,29 @@ struct mos_server {
 
 extern "C" {
 
-mos_status mos_server_create(const mos_graph* g, int64_t mem_budget, int32_t max_slots,
-                             mos_server** out) {
+mos_status mos_server_create_ex(const mos_graph* g, int64_t mem_budget, int32_t max_slots,
+                                const mos_options* opt, mos_server** out) {
   if (!g || !out || mem_budget < 0 || max_slots < 0)
     return set_err(MOS_E_INVALID_ARG, "bad server arguments");
+  MosOpts o;
+  if (opt) {
+    mos_status rs = mos_internal_read_options(opt, &o);
+    if (rs != MOS_OK) return rs;
+  } else {
+    o.steps = 4;
+  }
   return guarded([&]() -> mos_status {
     HIPCHK(hipSetDevice(g->device));
     std::unique_ptr<mos_server> s(new mos_server());
     s->g = g;
+    s->heur_factor = o.heur_factor;
+    s->step_budget = o.step_budget;
+    s->pop_order = o.pop_order;
+    s->eps_ppm = o.eps_ppm;
+    s->eager_goal = o.eager_goal;
     const int S = max_slots > 0 ? max_slots : 64;
-    s->eng.reset(new Engine(g, S, dm_for(g->D), default_budget(mem_budget), nullptr, 256, 0, true, 4));
+    s->eng.reset(new Engine(g, S, dm_for(g->D), default_budget(mem_budget), nullptr, o.B,
+                            o.label_limit, o.want_paths != 0, o.steps));
     if (const char* x = std::getenv("MOS_SERVER_FAIL_AT_TICK")) s->fail_at_tick = std::atoll(x);
     s->th = std::thread([p = s.get()] { p->loop(); });
     *out = s.release();
@@ -1574,11 +1504,16 @@ mos_status mos_server_create(const mos_graph* g, int64_t mem_budget, int32_t max
   });
 }
 
+mos_status mos_server_create(const mos_graph* g, int64_t mem_budget, int32_t max_slots,
+                             mos_server** out) {
+  return mos_server_create_ex(g, mem_budget, max_slots, nullptr, out);
+}
+
 mos_status mos_server_submit(mos_server* s, int32_t start, int32_t goal, int32_t n_objectives,
                              uint64_t* ticket) {
   if (!s || !ticket) return set_err(MOS_E_INVALID_ARG, "NULL argument");
   int d;
-  mos_status rs = check_query(s->g, start, goal, n_objectives, &d);
+  mos_status rs = mos_internal_check_query(s->g, start, goal, n_objectives, &d);
   if (rs != MOS_OK) return rs;
   std::lock_guard<std::mutex> lk(s->mu);
   if (s->stop) return set_err(s->fatal_st == MOS_OK ? MOS_E_DEVICE : s->fatal_st, "server stopped: " + s->fatal);
@@ -1587,6 +1522,11 @@ mos_status mos_server_submit(mos_server* s, int32_t start, int32_t goal, int32_t
   q.start = start;
   q.goal = goal;
   q.d = d;
+  q.heur_factor = s->heur_factor;
+  q.step_budget = s->step_budget;
+  q.pop_order = s->pop_order;
+  q.eps_ppm = s->eps_ppm;
+  q.eager_goal = s->eager_goal;
   q.reserve = s->eng->default_reserve();
   s->inbox.push_back(q);
   s->known[(uint64_t)q.id] = false;
@@ -1608,6 +1548,10 @@ static mos_status collect(mos_server* s, uint64_t ticket, mos_result** out) {
   Finished f = it->second;
   s->finished.erase(it);
   s->known[ticket] = true;
+  if (f.st == MOS_E_STEP_LIMIT && f.res) {
+    *out = f.res;  // the exact prefix
+    return set_err(f.st, f.msg);
+  }
   if (f.st != MOS_OK) return set_err(f.st, f.msg);
   *out = f.res;
   return MOS_OK;

@@ -36,6 +36,14 @@ void launch_heur_round(Slot* slots, const int32_t* slot_of, int njobs, const Gra
 void launch_heur_clamp(Slot* slots, const int32_t* slot_of, int njobs, const GraphDev& G,
                        hipStream_t st);
 void launch_slot_init(Slot* slots, int s, const GraphDev& G, hipStream_t st);
+// The whole heuristic of the slots slot_of[0 .. njobs): init, relaxation
+// rounds until no worklist is left (the host reads the counters every 8
+// rounds into cnt_host[njobs * MAXD * 3]), clamp.  hs: njobs * MAXD * 3 * n
+// ints of device scratch; cnt: njobs * MAXD * 3 device ints.  0 on success,
+// -1 on a HIP error, -2 if the rounds did not converge.
+int run_heuristic(Slot* slots, const int32_t* slot_of, int njobs, const GraphDev& G, int32_t* hs,
+                  int32_t* cnt, int32_t* cnt_host, hipStream_t st);
+void launch_open_min(const Slot* slots, int s, int32_t* out, hipStream_t st);
 void launch_path_len(const Slot* slots, int s, const int32_t* labs, int np, int32_t* len,
                      hipStream_t st);
 void launch_path_write(const Slot* slots, int s, const int32_t* labs, int np, const int64_t* off,

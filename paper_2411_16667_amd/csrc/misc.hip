@@ -148,7 +148,8 @@ __global__ void k_slot_seed(Slot* slots, int s, GraphDev G) {
   S->fw[(size_t)d * MINCAP] = 0;
   S->node[st] = r;
   S->fw_top = (int64_t)MINCAP * (d + 1);
-  S->open_f1[0][0] = S->h[st];
+  const int32_t key0 = S->pop_fifo ? 0 : S->h[st];  // the start label's OPEN key
+  S->open_f1[0][0] = key0;
   S->open_lab[0][0] = 0;
   S->open_n = 1;
   S->open_sel = 0;
@@ -159,7 +160,7 @@ __global__ void k_slot_seed(Slot* slots, int s, GraphDev G) {
   S->refill = 0;
   S->blocks_a = 0;
   S->blocks_b = 0;
-  S->lo = S->h[st];
+  S->lo = key0;
   S->st[ST_INSERTED] = 1;
   S->status = S_RUN;
 }
@@ -182,6 +183,32 @@ __global__ void k_path_write(const Slot* slots, int s, const int32_t* labs, int 
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < np; i += gridDim.x * blockDim.x) {
     int64_t pos = off[i + 1];
     for (int x = labs[i]; S->Lpar[x] >= 0; x = S->Lpar[x]) arcs[--pos] = S->Larc[x];
+  }
+}
+
+// Smallest F1 over the OPEN entries of slot s (both tiers; entries of labels
+// that died since they were queued are included, which can only lower it),
+// INT32_MAX when OPEN is empty.  Every label still to be processed has an F1
+// at least this large, and a goal label's F is its cost, so the goal front's
+// vectors whose first objective lies below it are final.  One workgroup.
+__global__ void k_open_min(const Slot* slots, int s, int32_t* out) {
+  const Slot* S = &slots[s];
+  __shared__ int32_t red[1024 / WAVE];
+  int32_t m = INT32_MAX;
+  // F1 = g_1 + h_1 from the label itself (the tiers' key is F1 only in
+  // lexicographic order)
+  const int32_t* nl = pick(S->open_lab, S->open_sel);
+  const int32_t* fl = pick(S->far_lab, S->far_sel);
+  for (int i = threadIdx.x; i < S->open_n + S->far_n; i += blockDim.x) {
+    const int lab = i < S->open_n ? nl[i] : fl[i - S->open_n];
+    m = min(m, S->Lg[lab] + S->h[S->Lnode[lab]]);
+  }
+  m = wave_min(m);
+  if (lane_id() == 0) red[threadIdx.x / WAVE] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < (int)blockDim.x / WAVE; ++w) m = min(m, red[w]);
+    *out = min(m, red[0]);
   }
 }
 
@@ -209,6 +236,33 @@ void launch_slot_init(Slot* slots, int s, const GraphDev& G, hipStream_t st) {
   const int gx = std::min(2048, (G.n + 255) / 256);
   hipLaunchKernelGGL(k_slot_init, dim3(gx), dim3(256), 0, st, slots, s, G);
   hipLaunchKernelGGL(k_slot_seed, dim3(1), dim3(1), 0, st, slots, s, G);
+}
+
+int run_heuristic(Slot* slots, const int32_t* slot_of, int njobs, const GraphDev& G, int32_t* hs,
+                  int32_t* cnt, int32_t* cnt_host, hipStream_t st) {
+  launch_heur_init(slots, slot_of, njobs, G, hs, cnt, st);
+  if (hipGetLastError() != hipSuccess) return -1;
+  const int gx = std::max(1, std::min(512, (G.n / 8 + 255) / 256));
+  const size_t nc = (size_t)njobs * MAXD * 3;
+  for (int r = 0;; ++r) {
+    launch_heur_round(slots, slot_of, njobs, G, hs, cnt, r, gx, st);
+    if ((r & 7) == 7) {
+      if (hipMemcpyAsync(cnt_host, cnt, nc * 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+          hipStreamSynchronize(st) != hipSuccess)
+        return -1;
+      // after round r the worklist of round r + 1 is in counter (r + 1) % 3
+      bool any = false;
+      for (size_t i = (r + 1) % 3; i < nc && !any; i += 3) any = cnt_host[i] > 0;
+      if (!any) break;
+    }
+    if (r > 4 * G.n + 64) return -2;
+  }
+  launch_heur_clamp(slots, slot_of, njobs, G, st);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+void launch_open_min(const Slot* slots, int s, int32_t* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_open_min, dim3(1), dim3(1024), 0, st, slots, s, out);
 }
 
 void launch_path_len(const Slot* slots, int s, const int32_t* labs, int np, int32_t* len,

@@ -97,7 +97,14 @@ struct Slot {
   int32_t heur_factor;  // heuristic radius as a multiple of h(start); 0 = exact everywhere
   int32_t heur_bounded; // set when the radius cut the reverse search (h is then a lower bound outside it)
   int64_t fw_cap;  // words of the frontier region
-  int32_t hn, pad3;  // nodes of the graph (stride of the heuristic planes)
+  int32_t hn;        // nodes of the graph (stride of the heuristic planes)
+  int32_t pop_fifo;  // OPEN order: 0 = lexicographic by F (exact top-B); 1 = by the
+                     // step that generated the label (oldest generation first), a
+                     // relaxed order: the OPEN key is the generating step, not F1
+  int32_t eps_ppm;   // 0 = exact; else tests against the goal front use
+                     // (1 + eps_ppm / 10^6)-dominance (approximate front)
+  int32_t eager_goal;  // 1: labels accepted at the goal join the goal front in the
+                       // next step's goal step instead of waiting in OPEN to be popped
 
   int32_t* h;          // d planes of n: heuristic
   NodeRec* node;       // n
@@ -121,7 +128,9 @@ struct Slot {
   int32_t* reg;        // batch_cap: popped regular labels (ascending label id)
   int32_t* reg_off;    // batch_cap+1: exclusive prefix of their out-degrees
   int32_t* reg_kill;   // batch_cap: popped regular label found dominated by the goal front
-  int32_t* goal_lab;   // batch_cap: popped goal labels
+  int32_t* goal_lab;   // batch_cap + cand_cap: goal labels of this step's goal step
+                       //   (popped ones, then the eager ones of the previous step)
+  int32_t* pgoal;      // cand_cap: eager mode, labels accepted at the goal this step
   int32_t* tie_f1;     // tie_cap (= open_cap): entries of the threshold F1 bin
   int32_t* tie_lab;    // tie_cap
   int32_t* tie_st;     // tie_cap: refinement state of each tie entry
@@ -148,7 +157,8 @@ struct Slot {
   // ---------------- dynamic (device-updated)
   int32_t n_labels, open_n, open_sel, P_n;
   int32_t P_sel, lo, lo_next, P_dead;  // P_dead: removed entries among the first P_n
-  int32_t P_seq, pad4;                  // P_seq: goal-front entries appended so far
+  int32_t P_seq, pgoal_n;               // P_seq: goal-front entries appended so far;
+                                        // pgoal_n: entries of pgoal
   int64_t fw_top;
   int32_t t_star, r_tie, tie_mode, big_work;  // big_work: set at admission
   int32_t batch_n, goal_n, reg_n, cand_n;
@@ -213,6 +223,15 @@ __device__ __forceinline__ int wave_sum(int v) {
 __device__ __forceinline__ int64_t wave_sum64(int64_t v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
   return v;
+}
+
+// x scaled by 1 + eps_ppm / 10^6 and rounded down, so that for an integer p,
+// p <= eps_relax(x) exactly when p <= (1 + eps) x.  Kept below INT32_MAX, the
+// value of removed goal-front entries, which must never pass a test.
+__device__ __forceinline__ int32_t eps_relax(int32_t x, int32_t eps_ppm) {
+  if (eps_ppm == 0 || x == INT32_MAX) return x;
+  const int64_t r = (int64_t)x + ((int64_t)x * eps_ppm) / 1000000;
+  return (int32_t)(r < INT32_MAX - 1 ? r : INT32_MAX - 1);
 }
 
 // a <= b in every one of the d components (weak dominance, equality included).

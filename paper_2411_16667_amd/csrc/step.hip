@@ -42,6 +42,11 @@ static_assert(SPLIT_TILE % NT_TILE == 0, "a split tile is whole chunks of one wo
 
 #define FOR_K(k) _Pragma("unroll") for (int k = 0; k < DM; ++k) if (k < d)
 
+// per goal label flags of the goal step (bits of c_rej, set at the pop)
+constexpr int GF_REJECTED = 1;     // an entry of P or another goal label is <= it
+constexpr int GF_EPS_COVERED = 2;  // approximate mode: an entry of P is <= (1 + eps) it
+constexpr int GF_PRUNER = 4;       // it is strictly below an entry of P
+
 // Exclusive scan of one value per thread across a workgroup of NT threads.
 // Four exclusive scans at once (one set of barriers for all four).
 template <int NT>
@@ -448,7 +453,9 @@ __global__ __launch_bounds__(NT_TILE) void k_open_scatter(Slot* slots) {
       for (int k = 1; k < S.d; ++k)
         S.tie_key[(size_t)(k - 1) * S.tie_cap + p] = S.Lg[(size_t)k * S.pool_cap + lab] +
                                                      S.h[(size_t)k * S.hn + v];
-      S.tie_key[(size_t)(S.d - 1) * S.tie_cap + p] = v;
+      // last key word: the node (unique with F in lexicographic order); the
+      // label id in generation order, where the key does not hold F1
+      S.tie_key[(size_t)(S.d - 1) * S.tie_cap + p] = S.pop_fifo ? lab : v;
     }
     p = pos[2];
     if (to_near && p < S.open_cap) {
@@ -780,6 +787,7 @@ __global__ __launch_bounds__(NT_TILE) void k_split_scan(Slot* slots, GraphDev G)
   constexpr int U = SPLIT_TILE / NT_TILE;
   __shared__ int red[SPLIT_WORDS][GP_WAVES];
   __shared__ int cw[4][U][GP_WAVES];  // per (kind, chunk, wave): goal, regular, degree sum, back
+  __shared__ int sh_goal0;             // first goal-list position of the eager goal labels
   const int wave = threadIdx.x / WAVE, lane = lane_id();
   const int nb0 = S.pop_nb, keep0 = S.pop_keep, items = split_items_total(S);
   const int nt = (items + SPLIT_TILE - 1) / SPLIT_TILE;
@@ -807,23 +815,38 @@ __global__ __launch_bounds__(NT_TILE) void k_split_scan(Slot* slots, GraphDev G)
         a[4] = min(a[4], red[4][x]);
       }
       const int nb = a[0] + a[1], keep_n = keep0 + a[3];
-      Sp->goal_n = a[0];
+      // eager mode: the goal labels accepted last step join the popped ones
+      // (copied below; those the goal-front filter removed since enter as
+      // rejected, counted as labels dropped at their pop)
+      const int eager_n = S.pgoal_n;
+      const int ng = a[0] + eager_n;
+      sh_goal0 = a[0];
+      Sp->pgoal_n = 0;
+      Sp->goal_n = ng;
       Sp->reg_n = a[1];
       Sp->cand_n = a[2];
       Sp->batch_n = nb;
       Sp->keep_n = keep_n;
       if (a[1] <= S.batch_cap) S.reg_off[a[1]] = a[2];
       if (a[4] != INT32_MAX) atomicMin(&Sp->lo_next, a[4]);
-      Sp->st[ST_POPS] += nb;
-      Sp->st[ST_GOAL_POPS] += a[0];
-      if (nb > S.batch_cap || a[2] > S.cand_cap || a[0] > S.cand_cap || keep_n > S.open_cap) {
+      Sp->st[ST_POPS] += nb + eager_n;
+      Sp->st[ST_GOAL_POPS] += ng;
+      if (nb > S.batch_cap || a[2] > S.cand_cap || ng > S.cand_cap || keep_n > S.open_cap) {
         Sp->status = S_OVERFLOW;
         Sp->err_line = __LINE__;
-      } else if (nb == 0 && S.far_n == 0) {
-        Sp->status = S_DONE;  // no live label left in OPEN
+        sh_goal0 = -1;
+      } else if (nb == 0 && S.far_n == 0 && ng == 0) {
+        Sp->status = S_DONE;  // no live label left in OPEN, no goal label waiting
       }
     }
     __syncthreads();
+    const int g0 = sh_goal0;
+    if (g0 >= 0)
+      for (int j = threadIdx.x; j < S.pgoal_n; j += NT_TILE) {
+        const int lab = S.pgoal[j];
+        S.goal_lab[g0 + j] = lab;
+        S.c_rej[g0 + j] = S.Lstate[lab] == L_DEAD ? GF_REJECTED : 0;
+      }
   }
   int32_t* KF = pick(S.open_f1, S.open_sel ^ 1);
   int32_t* KL = pick(S.open_lab, S.open_sel ^ 1);
@@ -1030,14 +1053,25 @@ __global__ __launch_bounds__(NT_TILE) void k_goal_pairs(Slot* slots) {
     int4 G[NW];
     pack_query<DM>(x, G);
     __syncthreads();  // the previous item is done with the LDS tiles
-    bool rej = false;
+    bool rej = false, rej_eps = false;
     if (oc < npc) {
       const int p0 = oc * PCH, npt = min(PCH, np - p0);
 #pragma unroll
       for (int w = 0; w < NW; ++w) mine.w[t][w] = G[w];
       stage_chunk<DM>(other, Pg, Pc, p0, npt, d);
       __syncthreads();
-      if (t < nt) rej = chunk_dominates<DM>(other, G);
+      if (t < nt) {
+        // NotDominated(l, P); in approximate mode also by (1 + eps)-dominance
+        rej = chunk_dominates<DM>(other, G);
+        if (S.eps_ppm && !rej) {
+          int32_t xe[NW * 4];
+#pragma unroll
+          for (int k = 0; k < NW * 4; ++k) xe[k] = eps_relax(x[k], S.eps_ppm);
+          int4 Ge[NW];
+          pack_query<DM>(xe, Ge);
+          rej_eps = chunk_dominates<DM>(other, Ge);
+        }
+      }
       if (t < npt && other.w[t][0].x != INT32_MAX) {
         int4 Q[NW];
 #pragma unroll
@@ -1051,6 +1085,9 @@ __global__ __launch_bounds__(NT_TILE) void k_goal_pairs(Slot* slots) {
           int le, ne;
           le_ne<DM>(R, Q, le, ne);
           hit |= le & ne;
+          // approximate mode: a goal label that removes an entry is kept even
+          // if the front covers it within 1 + eps (it replaces what it removes)
+          if (S.eps_ppm && (le & ne)) atomicOr(&gflag[t0 + r], GF_PRUNER);
         }
         if (hit && atomicExch(&Pg[p0 + t], INT32_MAX) != INT32_MAX) {
           for (int k = 1; k < d; ++k) Pg[(size_t)k * Pc + p0 + t] = INT32_MAX;
@@ -1084,7 +1121,8 @@ __global__ __launch_bounds__(NT_TILE) void k_goal_pairs(Slot* slots) {
       }
       pairs += (int64_t)nt * nu;
     }
-    if (rej) gflag[t0 + t] = 1;
+    if (rej) atomicOr(&gflag[t0 + t], GF_REJECTED);
+    if (rej_eps) atomicOr(&gflag[t0 + t], GF_EPS_COVERED);
   }
   // pairs are block-uniform; tombstones are counted per thread
   const int64_t dsum = wave_sum64(dead);
@@ -1115,7 +1153,8 @@ __global__ __launch_bounds__(NT_SLOT) void k_goal_merge(Slot* slots) {
   int na = 0;
   for (int base = 0; base < ng; base += NT_SLOT) {
     const int i = base + threadIdx.x;
-    const int a = (i < ng && !S.c_rej[i]) ? 1 : 0;
+    const int f = i < ng ? S.c_rej[i] : GF_REJECTED;
+    const int a = !(f & GF_REJECTED) && (!(f & GF_EPS_COVERED) || (f & GF_PRUNER)) ? 1 : 0;
     int tot;
     const int pos = block_exscan<NT_SLOT>(a, &tot, tmp);
     if (a) {
@@ -1170,16 +1209,20 @@ __global__ __launch_bounds__(NT_SLOT) void k_goal_merge(Slot* slots) {
 template <int DM, int L>
 __device__ void tile_vs_frontL(FrontChunk<DM>& ch, const int32_t* Pg, int Pc, int np, int d,
                                int c0, int c1, const bool (&have)[L],
-                               const int4 (&F)[L][FrontChunk<DM>::NW], bool (&dom)[L]) {
+                               const int4 (&F)[L][FrontChunk<DM>::NW], bool (&dom)[L],
+                               int64_t& examined) {
   for (int c = c0; c < c1; ++c) {
     const int p0 = c * PCH;
     __syncthreads();
     stage_chunk<DM>(ch, Pg, Pc, p0, min(PCH, np - p0), d);
     __syncthreads();
-    bool open = false;
+    int nopen = 0;
 #pragma unroll
-    for (int h = 0; h < L; ++h) open = open || (have[h] && !dom[h]);
-    if (open) {
+    for (int h = 0; h < L; ++h) nopen += (have[h] && !dom[h]) ? 1 : 0;
+    // pairs examined: every still-undecided label of this thread against the
+    // chunk's entries (removed entries included: they are compared too)
+    examined += (int64_t)nopen * min(PCH, np - p0);
+    if (nopen) {
       int a[L];
 #pragma unroll
       for (int h = 0; h < L; ++h) a[h] = -1;
@@ -1201,7 +1244,8 @@ template <int DM>
 __device__ void tile_vs_front2(FrontChunk<DM>& ch, const int32_t* Pg, int Pc, int np, int d,
                                int c0, int c1, bool have0, bool have1,
                                const int4 (&F0)[FrontChunk<DM>::NW],
-                               const int4 (&F1)[FrontChunk<DM>::NW], bool& dom0, bool& dom1) {
+                               const int4 (&F1)[FrontChunk<DM>::NW], bool& dom0, bool& dom1,
+                               int64_t& examined) {
   const bool have[2] = {have0, have1};
   int4 F[2][FrontChunk<DM>::NW];
 #pragma unroll
@@ -1210,7 +1254,7 @@ __device__ void tile_vs_front2(FrontChunk<DM>& ch, const int32_t* Pg, int Pc, in
     F[1][w] = F1[w];
   }
   bool dom[2] = {dom0, dom1};
-  tile_vs_frontL<DM, 2>(ch, Pg, Pc, np, d, c0, c1, have, F, dom);
+  tile_vs_frontL<DM, 2>(ch, Pg, Pc, np, d, c0, c1, have, F, dom, examined);
   dom0 = dom[0];
   dom1 = dom[1];
 }
@@ -1245,6 +1289,7 @@ __global__ __launch_bounds__(NT_TILE) void k_popcheck(Slot* slots, GraphDev G) {
   const int32_t* Pg = pick(S.Pg, S.P_sel);
   const int32_t* Ps = pick(S.Pseq, S.P_sel);
   int killed = 0;
+  int64_t examined = 0;
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const int lt = t / ngrp, gi = t - lt * ngrp;
     int ii[2], lab[2] = {0, 0};
@@ -1267,7 +1312,9 @@ __global__ __launch_bounds__(NT_TILE) void k_popcheck(Slot* slots, GraphDev G) {
         const int v = S.Lnode[lab[h]];
 #pragma unroll
         for (int k = 0; k < NW * 4; ++k)
-          f[k] = k < d ? S.Lg[(size_t)k * pc + lab[h]] + S.h[(size_t)k * n + v] : 0;
+          f[k] = k < d ? eps_relax(S.Lg[(size_t)k * pc + lab[h]] + S.h[(size_t)k * n + v],
+                                   S.eps_ppm)
+                       : 0;
       }
 #pragma unroll
       for (int w = 0; w < NW; ++w) F[h][w] = make_int4(f[4 * w], f[4 * w + 1], f[4 * w + 2], f[4 * w + 3]);
@@ -1286,7 +1333,8 @@ __global__ __launch_bounds__(NT_TILE) void k_popcheck(Slot* slots, GraphDev G) {
     __syncthreads();
     const int c0 = max(gi * cpi, sh_first / PCH), c1 = min(npc, (gi + 1) * cpi);
     if (c0 < c1)
-      tile_vs_front2<DM>(ch, Pg, Pc, np, d, c0, c1, have[0], have[1], F[0], F[1], dom[0], dom[1]);
+      tile_vs_front2<DM>(ch, Pg, Pc, np, d, c0, c1, have[0], have[1], F[0], F[1], dom[0], dom[1],
+                         examined);
 #pragma unroll
     for (int h = 0; h < 2; ++h)
       if (have[h] && dom[h] && atomicExch(&S.reg_kill[ii[h]], 1) == 0) {
@@ -1299,6 +1347,8 @@ __global__ __launch_bounds__(NT_TILE) void k_popcheck(Slot* slots, GraphDev G) {
     atomicAdd((unsigned long long*)&Sp->st[ST_KILLED], (unsigned long long)k64);
     atomicAdd((unsigned long long*)&Sp->st[ST_POPS], (unsigned long long)(-k64));
   }
+  const int64_t e64 = wave_sum64(examined);
+  if (lane_id() == 0 && e64) atomicAdd((unsigned long long*)&Sp->st[ST_PPAIRS], (unsigned long long)e64);
 }
 
 // ---------------------------------------------------------------- expand
@@ -1366,8 +1416,6 @@ __global__ __launch_bounds__(NT_TILE) void k_pfilter(Slot* slots, GraphDev G) {
   if (S.status != S_RUN) return;
   const int R = S.accept_n, np = S.P_n, base = S.n_labels;
   if (R == 0 || np == 0) return;
-  if (blockIdx.x == 0 && threadIdx.x == 0)
-    atomicAdd((unsigned long long*)&Sp->st[ST_PPAIRS], (unsigned long long)((int64_t)R * (np - S.P_dead)));
   constexpr int LPT = 4;           // labels per thread
   constexpr int LT = LPT * NT_TILE;  // labels per tile
   const int nlt = (R + LT - 1) / LT, npc = (np + PCH - 1) / PCH;
@@ -1378,6 +1426,7 @@ __global__ __launch_bounds__(NT_TILE) void k_pfilter(Slot* slots, GraphDev G) {
   __shared__ FrontChunk<DM> ch;
   const int d = S.d, pc = S.pool_cap, Pc = S.P_cap, n = G.n;
   const int32_t* Pg = pick(S.Pg, S.P_sel);
+  int64_t examined = 0;
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const int lt = t / ngrp, gi = t - lt * ngrp;
     int ii[LPT];
@@ -1396,12 +1445,14 @@ __global__ __launch_bounds__(NT_TILE) void k_pfilter(Slot* slots, GraphDev G) {
         const int v = S.Lnode[id];
 #pragma unroll
         for (int k = 0; k < NW * 4; ++k)
-          x[k] = k < d ? S.Lg[(size_t)k * pc + id] + S.h[(size_t)k * n + v] : 0;
+          x[k] = k < d ? eps_relax(S.Lg[(size_t)k * pc + id] + S.h[(size_t)k * n + v], S.eps_ppm)
+                       : 0;
       }
 #pragma unroll
       for (int w = 0; w < NW; ++w) F[h][w] = make_int4(x[4 * w], x[4 * w + 1], x[4 * w + 2], x[4 * w + 3]);
     }
-    tile_vs_frontL<DM, LPT>(ch, Pg, Pc, np, d, gi * cpi, min(npc, (gi + 1) * cpi), have, F, dom);
+    tile_vs_frontL<DM, LPT>(ch, Pg, Pc, np, d, gi * cpi, min(npc, (gi + 1) * cpi), have, F, dom,
+                            examined);
 #pragma unroll
     for (int h = 0; h < LPT; ++h)
       if (have[h] && dom[h]) {
@@ -1409,6 +1460,8 @@ __global__ __launch_bounds__(NT_TILE) void k_pfilter(Slot* slots, GraphDev G) {
         S.fw[S.c_fslot[S.order[ii[h]]]] = FW_REMOVED;  // leaves its node's frontier
       }
   }
+  const int64_t e64 = wave_sum64(examined);
+  if (lane_id() == 0 && e64) atomicAdd((unsigned long long*)&Sp->st[ST_PPAIRS], (unsigned long long)e64);
 }
 
 // ---------------------------------------------------------------- group by target node
@@ -1500,9 +1553,18 @@ __global__ __launch_bounds__(NT_TILE) void k_group_scatter(Slot* slots) {
   }
 }
 
-// OPEN tier an accepted candidate joins, by its F1: 1 near (F1 < T), 2 far.
+// OPEN key of a label generated in this step: its F1 in lexicographic order;
+// in generation order the step number (labels of earlier steps first; the
+// start label has key 0).  Either way keys never fall below the smallest key
+// left in OPEN, which the bucket structure of the tiers relies on.
+__device__ __forceinline__ int open_key(const Slot& S, int f1) {
+  return S.pop_fifo ? (int)S.st[ST_STEPS] + 1 : f1;
+}
+
+// OPEN tier an accepted candidate joins, by its key: 1 near (key < T), 2 far.
 __device__ __forceinline__ int open_tier(const Slot& S, int f1) {
-  return (S.t_all || f1 < S.T) ? 1 : 2;
+  const int key = open_key(S, f1);
+  return (S.t_all || key < S.T) ? 1 : 2;
 }
 
 // Take a new frontier block when `need` entries do not fit the node's block.
@@ -2250,11 +2312,15 @@ __global__ __launch_bounds__(NT_TILE) void k_insert(Slot* slots, GraphDev G) {
     S.Lnode[id] = v;
     S.Lpar[id] = S.c_par[f];
     S.Larc[id] = S.c_arc[f];
-    S.Lstate[id] = L_OPEN;
+    // eager mode: a label at the goal goes to the next step's goal step and is
+    // never popped (closed at once, its OPEN entry vanishes at the next pop)
+    const bool eager = S.eager_goal && v == S.goal;
+    S.Lstate[id] = eager ? L_CLOSED : L_OPEN;
+    if (eager) S.pgoal[atomicAdd(&Sp->pgoal_n, 1)] = id;
     S.Lpseq[id] = S.P_seq;  // k_pfilter tests it against every entry appended so far
     FOR_K(k) S.Lg[(size_t)k * pc + id] = S.c_g[(size_t)k * cc + f];
     S.fw[S.c_fslot[f]] = id;
-    const int f1 = S.c_g[f] + S.h[v];
+    const int f1 = open_key(S, S.c_g[f] + S.h[v]);
     const int q = S.c_rej[f];  // rank within its tier
     if (S.c_acc[f] == 1) {
       KF[keep + q] = f1;
@@ -2282,7 +2348,7 @@ __global__ void k_step_end(Slot* slots, int nslots) {
   if (S->open_n > 0) S->lo = S->lo_next;
   S->st[ST_STEPS] += 1;
   S->refill = !S->t_all && S->far_n > 0 && S->open_n < NEAR_LOW * S->B;
-  if (S->open_n == 0 && S->far_n == 0) S->status = S_DONE;
+  if (S->open_n == 0 && S->far_n == 0 && S->pgoal_n == 0) S->status = S_DONE;
 }
 
 // ---------------------------------------------------------------- launchers

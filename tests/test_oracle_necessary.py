@@ -108,3 +108,20 @@ def test_early_stopped_front_prefix_on_a_grid_query(seed):
         bound, rows = oracle.prefix_bound(r)
         want = np.array([y for y in full.costs if oracle.lex_less(y, bound)], np.int64).reshape(-1, 3)
         assert np.array_equal(want, rows), limit
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_first_dominated_is_the_antichain_test(seed):
+    from helpers import is_antichain
+
+    rng = np.random.default_rng(seed)
+    for d in (2, 3, 5):
+        for _ in range(40):
+            a = sort_lex(np.unique(rng.integers(0, 6, (rng.integers(1, 12), d)), axis=0))
+            got = oracle.first_dominated(a)
+            assert (got == -1) == is_antichain(a)
+            if got >= 0:
+                # the reported row really is weakly dominated by an earlier one
+                assert np.any(np.all(a[:got] <= a[got], axis=1))
+    assert oracle.first_dominated(np.array([[1, 2], [1, 2]])) == 1  # duplicates
+    assert oracle.first_dominated(np.array([[2, 1], [1, 2]])) == -2  # not ascending
