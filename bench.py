@@ -64,6 +64,10 @@ def parse():
                          "table at depth; picks the dominant kernel)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="length of the oracle sample for the CPU baseline (0 = skip)")
+    ap.add_argument("--time-to-front", type=int, default=1,
+                    help="1 = also time whole queries with stored oracle fronts to the exact "
+                         "front (routes at Table 2's objective counts, mid-range ship-grid "
+                         "queries); 0 = skip")
     ap.add_argument("--queries", type=int, default=64,
                     help="queries of the batched-vs-plain comparison (0 = skip)")
     ap.add_argument("--qdist", type=int, nargs=2, default=(10, 60),
@@ -198,6 +202,89 @@ def cpu_baseline(g, s, t, seconds):
     return {"value": pairs / secs, "unit": "checks/s", "cores": 1, "kind": "oracle",
             "sample": f"first {secs:.1f} s of the sequential search of the same query "
                       f"({st['pops']} labels processed, {pairs} pair checks)"}
+
+
+def cpu_all_cores(g, S, T, seconds):
+    """The oracle as a pool of one query per host core (threads: the oracle
+    releases the interpreter while it searches) over the same start/goal list
+    as the batched-vs-plain comparison, cycling through it until about
+    `seconds` have passed; queries/s with the core count used."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import oracle
+
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    cores = max(1, min(cores, 16))  # the box's CPU share for one GPU
+    oracle.build()
+    flags = oracle.WEAK_P | oracle.LAZY_PRUNEOPEN
+    stop = time.perf_counter() + seconds
+
+    def worker(w):
+        n, i = 0, w
+        while time.perf_counter() < stop:
+            q = i % len(S)
+            r = oracle.solve(g, int(S[q]), int(T[q]), 3, flags=flags, want_paths=False)
+            assert r.status == "ok"
+            n += 1
+            i += cores
+        return n
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(cores) as ex:
+        done = sum(ex.map(worker, range(cores)))
+    wall = time.perf_counter() - t0
+    return {"value": done / wall, "unit": "queries/s", "cores": cores, "kind": "oracle",
+            "sample": f"{done} solves of the {len(S)} batched-comparison queries in {wall:.1f} s, "
+                      f"one query per core"}
+
+
+def time_to_front(mos, gen):
+    """Whole queries with stored oracle fronts (the five time-expanded routes
+    at Table 2's objective counts, the mid-range ship-grid queries): wall time
+    of mos_solve to the exact front (median of three after an untimed one),
+    checked against the stored front, with the oracle's own pair checks for
+    the same query (recorded when it was stored) over that time: checks/s in
+    the oracle's units."""
+    import glob
+
+    import numpy as np
+
+    work = []
+    for r in sorted(gen.ROUTE_SHAPES):
+        g, s, t = gen.tmplar_route(r, 12, 0)
+        work.append((g, s, t, gen.ROUTE_MAX_OBJECTIVES[r], 16384,
+                     os.path.join(ROOT, "tests", "golden", "routes", f"r{r}.txt.gz")))
+    ship = gen.ship_grid(256, 256, 3, 0)
+    for f in sorted(glob.glob(os.path.join(ROOT, "tests", "golden", "c4mid", "q*.txt.gz"))):
+        h, _ = _stored(f)
+        work.append((ship, int(h["start"]), int(h["goal"]), 3, 4096, f))
+    rows, graphs = [], {}
+    for g, s, t, d, B, ref in work:
+        G = graphs.setdefault(id(g), mos.Graph.from_gen(g))
+        hdr, want = _stored(ref)
+        kw = dict(n_objectives=d, batch_width=B)
+        res = mos.mos_solve(G, s, t, **kw)
+        walls = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            res = mos.mos_solve(G, s, t, **kw)
+            walls.append(time.perf_counter() - t0)
+        wall = float(np.median(walls))
+        row = {"workload": hdr["workload"], "d": d, "batch_width": B, "front": int(want.shape[0]),
+               "seconds": wall, "same_front_as_stored_oracle":
+                   bool(np.array_equal(res.costs.astype(np.int64), want)),
+               "oracle_seconds_when_stored": float(hdr["search_seconds"])}
+        if "pairs" in hdr:
+            row["oracle_pairs"] = int(hdr["pairs"])
+            row["oracle_equivalent_checks_per_s"] = int(hdr["pairs"]) / wall
+        rows.append(row)
+    with_pairs = [r for r in rows if "oracle_pairs" in r]
+    return {"queries": rows,
+            "all_same_fronts": all(r["same_front_as_stored_oracle"] for r in rows),
+            "seconds_total": sum(r["seconds"] for r in rows),
+            "oracle_equivalent_checks_per_s":
+                (sum(r["oracle_pairs"] for r in with_pairs) / sum(r["seconds"] for r in with_pairs)
+                 if with_pairs else None)}
 
 
 def batched_vs_plain(mos, gen, G, a):
@@ -671,8 +758,14 @@ def main():
     sess.close()
     if a.queries > 0:
         out["queries_per_s"] = batched_vs_plain(mos, gen, G, a)
+    if a.time_to_front:
+        out["time_to_exact_front"] = time_to_front(mos, gen)
     if a.cpu_seconds > 0:
         out["cpu_baseline"] = cpu_baseline(g, s, t, a.cpu_seconds)
+        if a.queries > 0:
+            S, T = gen.ship_queries(256, 256, a.queries, seed=1000, dmin=a.qdist[0],
+                                    dmax=a.qdist[1])
+            out["cpu_baseline_all_cores"] = cpu_all_cores(g, S, T, a.cpu_seconds)
     print(json.dumps(out))
 
 

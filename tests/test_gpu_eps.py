@@ -41,8 +41,8 @@ def _valid(g, s, t, d, exact, r, ppm):
         check_paths(g, s, t, r.costs, r.paths, d)
 
 
-@pytest.mark.parametrize("ppm", [0, 5_000, 20_000, 100_000])
-@pytest.mark.parametrize("B", [1, 64, 2048])
+@pytest.mark.parametrize("ppm", [0, 5_000, 100_000])
+@pytest.mark.parametrize("B", [256, 4096])
 def test_grid_queries(mos, ppm, B):
     for seed in (0, 4):
         g, s, t = gen.config1(seed)
