@@ -192,6 +192,26 @@ mos_status mos_solve_batch(const mos_graph* g, int32_t nq, const int32_t* starts
                            const int32_t* goals, const int32_t* n_objectives,
                            const mos_options* opt, mos_result** out, mos_status* st);
 
+/* For callers that cannot allocate device memory (code under stream capture,
+ * serving loops or harnesses that forbid hipMalloc): mos_solve with costs only,
+ * no device allocation and no allocating library call.  All device state comes
+ * from one library-owned array of 256 MiB per GPU (made when the library is
+ * loaded, held until the process ends), so the query's search state -- per-node
+ * arrays of the whole graph plus its labels -- must fit into it:
+ * MOS_E_INVALID_ARG names a graph whose per-node state alone does not fit,
+ * MOS_E_LABEL_LIMIT a search that outgrows the rest.  costs is HOST memory of
+ * cap * d int32 (d = the query's objective count); on MOS_OK it receives the
+ * front, lexicographically ascending, and *size its entry count; a front larger
+ * than cap gives MOS_E_INVALID_ARG (nothing written).  stats may be NULL.
+ * Options as for mos_solve (costs_only, profile_kernels and max_slots are
+ * ignored; mem_budget does not apply); the steps run on opt->stream (NULL = the
+ * null stream), kernels launched one by one.  Calls on one GPU share its array
+ * and would race: the library serialises them per device; the array's contents
+ * do not carry from one call to the next. */
+mos_status mos_solve_noalloc(const mos_graph* g, int32_t start, int32_t goal,
+                             const mos_options* opt, int32_t* costs, int64_t cap, int64_t* size,
+                             mos_stats* stats);
+
 int64_t mos_result_size(const mos_result* r); /* number of front entries (0 for NULL) */
 int32_t mos_result_dim(const mos_result* r);  /* d (0 for NULL) */
 /* out[size*d]: the front, lexicographically ascending. */

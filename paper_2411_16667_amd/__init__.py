@@ -72,6 +72,9 @@ _SIGS = {
                                  ctypes.POINTER(mos_options), ctypes.POINTER(_vp)]),
     "mos_solve_batch": (ctypes.c_int, [_vp, ctypes.c_int32, _i32p, _i32p, _i32p,
                                        ctypes.POINTER(mos_options), ctypes.POINTER(_vp), _i32p]),
+    "mos_solve_noalloc": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32,
+                                         ctypes.POINTER(mos_options), _i32p, ctypes.c_int64,
+                                         _i64p, ctypes.POINTER(mos_stats)]),
     "mos_result_size": (ctypes.c_int64, [_vp]),
     "mos_result_dim": (ctypes.c_int32, [_vp]),
     "mos_result_costs": (ctypes.c_int, [_vp, _i32p]),
@@ -261,6 +264,21 @@ def mos_solve(graph: Graph, start: int, goal: int, **opts) -> Result:
         return _take_result(h, complete=False)
     _check(st, "mos_solve")
     return _take_result(h)
+
+
+def mos_solve_noalloc(graph: Graph, start: int, goal: int, cap: int = 1 << 16, **opts) -> Result:
+    """Costs-only solve with no device allocation (``mos_solve_noalloc``);
+    `cap` bounds the front size the output buffer holds."""
+    o = make_options(**opts)
+    d = graph.D if o.n_objectives == 0 else o.n_objectives
+    buf = np.zeros((max(int(cap), 1), d), dtype=np.int32)
+    n = ctypes.c_int64()
+    s = mos_stats()
+    _check(_lib.mos_solve_noalloc(graph.handle, int(start), int(goal), ctypes.byref(o),
+                                  _p(buf, ctypes.c_int32), int(cap), ctypes.byref(n),
+                                  ctypes.byref(s)), "mos_solve_noalloc")
+    stats = {f: getattr(s, f) for f, _ in mos_stats._fields_}
+    return Result(buf[:n.value].copy(), None, stats)
 
 
 def mos_solve_batch(graph: Graph, starts, goals, n_objectives=None, **opts):
