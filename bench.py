@@ -379,9 +379,9 @@ def served_bench(a):
     t0 = time.perf_counter()
     g, rng, comp = gen.config5_graph(0)
     nq = a.served_queries
-    S, T, D = gen.local_queries(g, comp, 6 * nq, seed=0, radius=a.radius)
+    S, T, D = gen.local_queries(g, comp, 7 * nq, seed=0, radius=a.radius)
     G = mos.Graph.from_gen(g)
-    print(f"served: graph and {6 * nq} queries ready in {time.perf_counter() - t0:.1f} s",
+    print(f"served: graph and {7 * nq} queries ready in {time.perf_counter() - t0:.1f} s",
           file=sys.stderr, flush=True)
     # plain: one query at a time through mos_solve
     npl = min(nq, 200)
@@ -399,7 +399,7 @@ def served_bench(a):
                "p50_ms": 1e3 * float(np.percentile(lat, 50)),
                "p99_ms": 1e3 * float(np.percentile(lat, 99))}]
     print(f"served: saturation {sat:.1f} q/s", file=sys.stderr, flush=True)
-    for k, frac in enumerate((0.25, 0.5, 0.75, 0.9, 1.1)):
+    for k, frac in enumerate((0.1, 0.25, 0.5, 0.75, 0.9, 1.1)):
         rate = frac * sat
         lo = (k + 1) * nq
         arr = gen.poisson_arrivals(nq, rate, seed=k)

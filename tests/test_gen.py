@@ -38,6 +38,20 @@ def test_config3_recipe_counts():
     assert gen.overflow_bound_ok(g)
 
 
+def test_config5_recipe_counts():
+    # the served graph (survey's measured facts for seed 0): 1M points, 8-NN
+    # symmetric edges, one component, 3,968 zero-cost edges, 5 objectives
+    g, _, comp = gen.config5_graph(0)
+    assert g.n == 1_000_000 and g.n_arcs == 9_226_156 and g.D == 5
+    assert int(((g.cost == 0).all(1)).sum()) // 2 == 3968
+    assert np.diff(g.row_ptr).max() == 18
+    assert np.bincount(comp).max() == g.n
+    assert gen.overflow_bound_ok(g)
+    S, T, D = gen.c5_parity_queries(g, comp, 200, seed=0)
+    assert np.all(S != T) and list(D[:6]) == [3, 4, 5, 3, 4, 5]
+    assert np.array_equal(np.bincount(D)[3:], [67, 67, 66])
+
+
 def test_config4_queries():
     g, S, T = gen.config4(0, nq=64)
     rr, cc = np.divmod(np.arange(g.n), 256)

@@ -82,10 +82,19 @@ def test_small_budget_readmits(mos):
     S = np.zeros(4, dtype=np.int32)
     T = np.array([1023, 500, 700, 1000], dtype=np.int32)
     res = mos.mos_solve_batch(G, S, T, batch_width=256, max_slots=4, mem_budget=256 << 20)
+    refs = [oracle.solve(g, int(S[q]), int(T[q]), 3).costs for q in range(4)]
     for q, (st, r) in enumerate(res):
         assert st == mos.MOS_OK, q
-        ref = oracle.solve(g, int(S[q]), int(T[q]), 3)
-        assert np.array_equal(r.costs.astype(np.int64), ref.costs), q
+        assert np.array_equal(r.costs.astype(np.int64), refs[q]), q
+    # the same through the request loop, whose counters show the re-admissions
+    srv = mos.Server(G, mem_budget=96 << 20, max_slots=4)
+    tickets = [srv.submit(int(S[q]), int(T[q]), 3) for q in range(4)]
+    got = [srv.wait(tk) for tk in tickets]
+    c = srv.counters()
+    srv.close()
+    assert c["readmissions"] > 0
+    for q, (st, r) in enumerate(got):
+        assert st == mos.MOS_OK and np.array_equal(r.costs.astype(np.int64), refs[q]), q
 
 
 def test_autotuned_batch_width(mos):

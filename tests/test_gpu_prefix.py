@@ -117,6 +117,13 @@ def _full_size_prefix(mos, name, g, s, t, d, B, max_steps):
           f"{rows.shape[0]} (bound {bound.tolist()}), compared {n}, steps {r.stats['steps']}")
     # the whole oracle prefix lies inside the GPU's exact range
     assert m > bound[0] and n == rows.shape[0] and n > 1000
+    # the run went through the paths only a deep search reaches: frontier
+    # groups split into pair tiles, the far OPEN tier, tie sets refined by
+    # full key beyond the in-LDS ranking
+    st = r.stats
+    assert st["frontier_bytes"] > st["frontier_bytes_onepass"]
+    assert st["far_scanned"] > 0
+    assert st["tie_entries"] > 256 * st["steps"]
     # the compared part is an antichain in ascending order
     part = np.array([y for y in r.costs[r.costs[:, 0] <= bound[0]] if oracle.lex_less(y, bound)])
     assert oracle.first_dominated(part) == -1
