@@ -81,7 +81,7 @@ def test_c5_served_random_pairs(mos):
     S, T, D = gen.c5_parity_queries(g, comp, 200, seed=0)
     assert hdr["graph_sha256_16"] == g.digest() and len(entries) == 200
     G = mos.Graph.from_gen(g)
-    opts = dict(batch_width=4096, step_budget=256, steps_per_poll=16)
+    opts = dict(batch_width=1024, step_budget=64, steps_per_poll=16)
     srv = mos.Server(G, max_slots=64, **opts)
     tickets = [srv.submit(int(S[q]), int(T[q]), int(D[q])) for q in range(200)]
     got = [srv.wait(tk) for tk in tickets]
