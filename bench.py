@@ -83,7 +83,8 @@ def parse():
                          "OPEN order, labels popped and time to the exact front")
     ap.add_argument("--route-width", type=int, default=0,
                     help="routes workload: batch width B (0 = picked per route by the "
-                         "autotuner from 1024, 4096, 16384, 32768)")
+                         "autotuner from 1024, 4096, 16384; the routes at 32768 are kept off "
+                         "the GPU until an unexplained fault is understood)")
     ap.add_argument("--route-repeats", type=int, default=3,
                     help="routes workload: timed solves per route (the median is reported)")
     ap.add_argument("--route-sweep", type=int, nargs="*", default=None, metavar="B",
@@ -449,7 +450,7 @@ def routes_bench(a):
         if B == 0:
             from paper_2411_16667_amd.autotune import tune_batch_width
 
-            B = tune_batch_width(G, [s], [t], n_objectives=[d], widths=(1024, 4096, 16384, 32768),
+            B = tune_batch_width(G, [s], [t], n_objectives=[d], widths=(1024, 4096, 16384),
                                  sample=1, costs_only=False)["batch_width"]
         kw = dict(n_objectives=d, batch_width=B)
         res = mos.mos_solve(G, s, t, **kw)

@@ -83,7 +83,7 @@ def test_far_tier_refills(mos, B):
 
 def test_step_budget_returns_exact_prefixes(mos):
     g = gen.ship_grid(256, 256, 3, 0)
-    S, T = gen.ship_queries(256, 256, 16, seed=404, dmin=30, dmax=75)
+    S, T = gen.ship_queries(256, 256, 16, seed=404, dmin=10, dmax=75)
     G = mos.Graph.from_gen(g)
     res = mos.mos_solve_batch(G, S, T, batch_width=256, max_slots=8, step_budget=24,
                               steps_per_poll=8, mem_budget=8 << 30)
