@@ -353,3 +353,36 @@ def test_pops_are_the_pareto_optimal_labels(seed):
             assert np.array_equal(r.costs, front)
             assert r.stats["pops"] == want, (seed, s, t, mode)
             assert r.stats["goal_pops"] == front.shape[0]
+
+
+@pytest.mark.parametrize("m", [1, 2, 5, 17])
+def test_pair_counters_closed_form_on_a_fan(m):
+    """The work counters the benches compare against, in closed form.  A fan:
+    arcs s -> a_i of cost (i, m-1-i) and a_i -> t of cost (0, 0), i < m.  The
+    m goal costs are mutually non-dominated and reach the goal in
+    lexicographic order, one per two pops, so every count follows by hand from
+    Algorithm 1's procedures (Section 4): the i-th goal candidate meets i
+    labels at t (NotDominated over alpha(t)) and i goal labels in P at
+    insertion; the i-th goal pop runs Prune(P) and NotDominated(P) over i
+    labels each; eager PruneOPEN scans the m-1-i a-labels still open, and the
+    lazy form instead checks each popped label against P (i labels for a_i and
+    for t_i).  Nothing dominates, so no loop breaks early."""
+    n = m + 2
+    s, t = 0, m + 1
+    src = [s] * m + list(range(1, m + 1))
+    dst = list(range(1, m + 1)) + [t] * m
+    cost = [[i, m - 1 - i] for i in range(m)] + [[0, 0]] * m
+    g = gen.graphs.from_arcs(n, np.array(src), np.array(dst), np.array(cost))
+    tri = m * (m - 1) // 2
+    want = {0: dict(frontier_pairs=tri, p_pairs=3 * tri, open_pairs=tri),
+            oracle.LAZY_PRUNEOPEN: dict(frontier_pairs=tri, p_pairs=5 * tri, open_pairs=0)}
+    for mode, counts in want.items():
+        r = oracle.solve(g, s, t, 2, flags=mode)
+        assert np.array_equal(r.costs, np.array(cost[:m], dtype=np.int64))
+        got = {k: r.stats[k] for k in counts}
+        assert got == counts, (m, mode)
+        assert r.stats["pops"] == 2 * m + 1
+        assert r.stats["goal_pops"] == m
+        assert r.stats["candidates"] == 2 * m
+        assert r.stats["killed"] == 0 and r.stats["pruned"] == 0
+        assert r.stats["max_alpha"] == m - 1
