@@ -337,6 +337,11 @@ class Engine {
     // checks above which a group is split into pair tiles
     if (const char* x = std::getenv("MOS_GX")) gx_ = std::max(1, std::min(65535, std::atoi(x)));
     if (const char* x = std::getenv("MOS_BIG_WORK")) big_work_ = std::max(64, std::atoi(x));
+    // tail widening (see widen_slots): a slot's batch capacity is planned for
+    // `widen_` times the batch width; MOS_WIDEN=1 turns it off
+    widen_ = S_ > 1 ? 4 : 1;
+    if (const char* x = std::getenv("MOS_WIDEN")) widen_ = std::max(1, std::min(64, std::atoi(x)));
+    Bplan_ = (int)std::min<int64_t>((int64_t)B_ * widen_, BATCH_MAX);
     HIPCHK(hipEventCreate(&ev0_));
     HIPCHK(hipEventCreate(&ev1_));
     HIPCHK(hipStreamSynchronize(st_));
@@ -393,8 +398,35 @@ class Engine {
     std::vector<int> fresh = admit(pending, done);
     if (!fresh.empty()) run_heuristics(fresh);
     if (busy_count() > 0) {
+      widen_slots(pending.empty());
       advance(K_);
       collect(pending, done);
+    }
+  }
+
+  // Tail widening.  With no query waiting and so few queries resident that
+  // a step pops fewer than kWidenLabels labels in all (a step of that size
+  // costs little more than its fixed sequence of launches), each resident
+  // query pops up to kWidenLabels / busy labels per step (at most its planned
+  // capacity, widen_ times the batch width), so the last queries of a batch
+  // need fewer steps.  The front does not depend on the pop order.  A query
+  // with a step budget keeps the plain width: its exact prefix after that
+  // many steps then does not depend on the other queries.
+  static constexpr int kWidenLabels = 16384;
+  void widen_slots(bool none_waiting) {
+    const int busy = busy_count();
+    if (busy == 0) return;
+    int target = B_;
+    if (none_waiting && (int64_t)busy * B_ < kWidenLabels)
+      target = (int)std::min<int64_t>(std::max(B_, kWidenLabels / busy), Bplan_);
+    for (int s = 0; s < S_; ++s) {
+      if (!sh_[s].busy) continue;
+      const int b = sh_[s].q.step_budget > 0 ? B_ : std::min(target, sh_[s].L.batch_cap);
+      if (hslots_[s].B != b) {
+        hslots_[s].B = b;
+        HIPCHK(hipMemcpyAsync((char*)slots_.p + (size_t)s * sizeof(Slot) + offsetof(Slot, B),
+                              &hslots_[s].B, sizeof(int32_t), hipMemcpyHostToDevice, st_));
+      }
     }
   }
 
@@ -427,7 +459,7 @@ class Engine {
       QueryReq q = pending.front();
       q.reserve = std::min<int64_t>(q.reserve, arena_bytes());
       Layout L;
-      if (!plan_layout(g_, q.d, B_, q.reserve, label_limit_, &L)) {
+      if (!plan_layout(g_, q.d, Bplan_, q.reserve, label_limit_, &L)) {
         pending.pop_front();
         done.push_back({q.id, MOS_E_LABEL_LIMIT, nullptr,
                         "memory budget too small for one query of this graph"});
@@ -457,7 +489,7 @@ class Engine {
       s.start = q.start;
       s.goal = q.goal;
       s.d = q.d;
-      s.B = L.B;
+      s.B = B_;  // widen_slots may raise it up to the planned capacity
       s.big_work = big_work_;
       s.batch_cap = L.batch_cap;
       s.cand_cap = L.cand_cap;
@@ -684,7 +716,7 @@ class Engine {
     a.nslots = S_;
     a.gx = gx_;
     {
-      const int64_t cand = (int64_t)std::min(2 * B_, BATCH_MAX) * std::max(1, g_->maxdeg);
+      const int64_t cand = (int64_t)std::min(2 * Bplan_, BATCH_MAX) * std::max(1, g_->maxdeg);
       a.gc = (int)std::max<int64_t>(1, std::min<int64_t>(gx_, (cand + 255) / 256));
     }
     a.dm = DM_;
@@ -855,6 +887,7 @@ class Engine {
 
   const mos_graph* g_;
   int S_, DM_, B_;
+  int widen_ = 1, Bplan_ = 1;  // tail widening factor; batch width the slot layouts allow
   int64_t label_limit_;
   bool want_paths_;
   int K_;
