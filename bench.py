@@ -13,7 +13,8 @@ against same-step candidates of the same node, and against node frontiers.
 Prints one JSON line.  The search is first taken --depth-steps deep (always,
 whatever --warmup is); a per-kernel table at that depth picks the dominant
 kernel; the timed steps then replay the captured step graph as mos_solve
-does.  Also reports the roofline of the dominant kernel (its durations from
+does, pipelined (the next batch popped beside the current batch's goal-front
+filter; --synchronous for the plain order).  Also reports the roofline of the dominant kernel (its durations from
 HIP events in an event window of the same length right after the timed
 steps, its algorithmic bytes from the search counters of that window, its
 measured HBM traffic from the committed PMC summary when that summary
@@ -75,12 +76,18 @@ def parse():
     ap.add_argument("--query-width", type=int, default=0,
                     help="batch width B of every query in that comparison (0 = picked by "
                          "the autotuner on a sample of the queries)")
-    ap.add_argument("--workload", choices=("steps", "served", "routes", "orders"), default="steps",
+    ap.add_argument("--workload", choices=("steps", "served", "routes", "orders", "pipelined"),
+                    default="steps",
                     help="steps: label steps of the ship-routing query (the headline line); "
                          "served: the request loop on the 1M-node road-like graph; "
                          "routes: whole queries on the time-expanded routes at up to 12 "
                          "objectives; orders: lexicographic against generation (FIFO) "
-                         "OPEN order, labels popped and time to the exact front")
+                         "OPEN order, labels popped and time to the exact front; "
+                         "pipelined: synchronous against pipelined steps, the same measures")
+    ap.add_argument("--synchronous", action="store_true",
+                    help="steps workload: run the label steps synchronously (default: "
+                         "pipelined, the next batch extracted beside the current batch's "
+                         "goal-front filter; 1.07 against 1.12 ms per step at this depth)")
     ap.add_argument("--route-width", type=int, default=0,
                     help="routes workload: batch width B (0 = picked per route by the "
                          "autotuner from 1024, 4096, 16384; the routes at 32768 are kept off "
@@ -551,14 +558,19 @@ def _stored(path):
     return m.read_front(path)
 
 
-def orders_bench(a):
-    """Lexicographic priority order against the relaxed generation (FIFO)
-    order of OPEN, as the paper's Section 7.1 compares a priority queue with a
-    FIFO queue: whole queries with stored oracle fronts (the five time-expanded
-    routes at Table 2's objective counts, the mid-range ship-grid queries),
-    the same batch width for both orders, costs only; labels popped against
-    the sequential oracle's pops, and wall time to the exact front (median of
-    --route-repeats solves after an untimed one)."""
+def compare_bench(a, study):
+    """Two ways of running the same whole queries with stored oracle fronts (the
+    five time-expanded routes at Table 2's objective counts, the mid-range
+    ship-grid queries), at one batch width, costs only: labels popped against
+    the sequential oracle's pops, steps, and wall time to the exact front
+    (median of --route-repeats solves after an untimed one).
+    study "orders": lexicographic priority order against the relaxed
+    generation (FIFO) order of OPEN, as the paper's Section 7.1 compares a
+    priority queue with a FIFO queue; the generation order runs under a step
+    cap of cap_factor times the lexicographic steps.
+    study "pipelined": synchronous steps against pipelined ones (the next
+    batch extracted beside the current batch's goal-front filter, Section
+    5.1's current and next bags)."""
     import glob
 
     import numpy as np
@@ -566,6 +578,14 @@ def orders_bench(a):
     import gen
     import paper_2411_16667_amd as mos
 
+    if study == "orders":
+        variants = [("lexicographic", dict(pop_order="lexicographic")),
+                    ("generation", dict(pop_order="generation"))]
+        metric = "time to the exact front, lexicographic vs generation (FIFO) OPEN order, 1 GPU"
+    else:
+        variants = [("synchronous", {}), ("pipelined", dict(pipelined=True))]
+        metric = "time to the exact front, synchronous vs pipelined steps, 1 GPU"
+    (n0, _), (n1, _) = variants
     work = []
     for r in sorted(gen.ROUTE_SHAPES):
         g, s, t = gen.tmplar_route(r, 12, 0)
@@ -585,11 +605,11 @@ def orders_bench(a):
         row = {"workload": name, "d": d, "batch_width": B, "oracle_pops": int(hdr["pops"]),
                "front": int(want.shape[0])}
         budget = 0
-        for order in ("lexicographic", "generation"):
-            # the generation order gets a step cap of cap_factor times the steps the
-            # lexicographic order needed; a run stopped there reports its exact prefix
-            kw = dict(n_objectives=d, batch_width=B, costs_only=True, pop_order=order,
-                      step_budget=budget)
+        for vname, extra in variants:
+            # the second variant of the orders study gets a step cap of
+            # cap_factor times the steps the first needed; a run stopped there
+            # reports its exact prefix
+            kw = dict(n_objectives=d, batch_width=B, costs_only=True, step_budget=budget, **extra)
             walls = []
             res = None
             try:
@@ -602,7 +622,7 @@ def orders_bench(a):
                         walls.append(time.perf_counter() - t0)
                         break
             except mos.MosError as e:
-                row[order] = {"finished": False, "error": str(e)}
+                row[vname] = {"finished": False, "error": str(e)}
                 continue
             out = {"seconds": float(np.median(walls)), "pops": res.stats["pops"],
                    "steps": res.stats["steps"], "finished": bool(res.complete),
@@ -613,29 +633,29 @@ def orders_bench(a):
             else:
                 out["step_cap"] = budget
                 out["exact_prefix_rows"] = int(res.costs.shape[0])
-            row[order] = out
-            if order == "lexicographic":
+            row[vname] = out
+            if study == "orders" and vname == n0:
                 budget = cap_factor * max(int(res.stats["steps"]), 1)
-        both = all(row[o].get("finished") for o in ("lexicographic", "generation"))
+        both = all(row[v].get("finished") for v, _ in variants)
         if both:
-            row["generation_vs_lexicographic_time"] = (row["generation"]["seconds"]
-                                                       / row["lexicographic"]["seconds"])
+            row[f"{n1}_vs_{n0}_time"] = row[n1]["seconds"] / row[n0]["seconds"]
         rows.append(row)
-        print(f"orders: {row}", file=sys.stderr, flush=True)
-    fin = [r for r in rows if "generation_vs_lexicographic_time" in r]
-    tl = sum(r["lexicographic"]["seconds"] for r in fin)
-    tg = sum(r["generation"]["seconds"] for r in fin)
-    out = {"metric": "time to the exact front, lexicographic vs generation (FIFO) OPEN order, 1 GPU",
-           "value": tg / tl if tl > 0 else None, "unit": "time ratio generation/lexicographic",
-           "higher_is_better": False, "n_gpus": 1, "dtype": "int32", "data": "synthetic",
+        print(f"{study}: {row}", file=sys.stderr, flush=True)
+    fin = [r for r in rows if f"{n1}_vs_{n0}_time" in r]
+    t0_ = sum(r[n0]["seconds"] for r in fin)
+    t1_ = sum(r[n1]["seconds"] for r in fin)
+    out = {"metric": metric, "value": t1_ / t0_ if t0_ > 0 else None,
+           "unit": f"time ratio {n1}/{n0}", "higher_is_better": False, "n_gpus": 1,
+           "dtype": "int32", "data": "synthetic",
            "config": {"workload": "time-expanded routes 1-5 at Table 2's objective counts and the "
                                   "mid-range ship-grid queries with stored oracle fronts",
-                      "batch_width": B, "repeats": a.route_repeats,
-                      "generation_step_cap": f"{cap_factor}x the lexicographic steps"},
-           "value_over": f"{len(fin)} of {len(rows)} queries that both orders finished",
-           "generation_unfinished": [r["workload"] for r in rows
-                                     if not r["generation"].get("finished")],
-           "seconds_lexicographic": tl, "seconds_generation": tg, "queries": rows}
+                      "batch_width": B, "repeats": a.route_repeats},
+           "value_over": f"{len(fin)} of {len(rows)} queries that both finished",
+           f"seconds_{n0}": t0_, f"seconds_{n1}": t1_, "queries": rows}
+    if study == "orders":
+        out["config"]["generation_step_cap"] = f"{cap_factor}x the lexicographic steps"
+        out["generation_unfinished"] = [r["workload"] for r in rows
+                                        if not r["generation"].get("finished")]
     print(json.dumps(out))
 
 
@@ -657,8 +677,8 @@ def main():
     if a.workload == "routes":
         routes_bench(a)
         return
-    if a.workload == "orders":
-        orders_bench(a)
+    if a.workload in ("orders", "pipelined"):
+        compare_bench(a, a.workload)
         return
     if a.copy_calibration > 0:
         import torch
@@ -679,7 +699,8 @@ def main():
     # steps per captured graph: a divisor of the timed step count, so that every
     # timed step is replayed from the captured graph (the form mos_solve uses)
     K = next(k for k in range(min(32, a.steps), 0, -1) if a.steps % k == 0)
-    sess = mos.Session(G, s, t, batch_width=a.batch_width, steps_per_poll=K)
+    sess = mos.Session(G, s, t, batch_width=a.batch_width, steps_per_poll=K,
+                       pipelined=not a.synchronous)
     left = a.depth_steps
     while left > 0:  # in chunks, with a progress line each
         n = min(left, 256)
@@ -770,7 +791,8 @@ def main():
         "config": {"workload": "ship-routing grid 256x256, 8-connected, d=3 smooth-field costs, "
                                "corner to corner; one step = one batched label step",
                    "batch_width": a.batch_width, "label_steps_timed": steps,
-                   "depth_steps": a.depth_steps, "search_finished": bool(done)},
+                   "depth_steps": a.depth_steps, "search_finished": bool(done),
+                   "steps_mode": "synchronous" if a.synchronous else "pipelined"},
         "timed_launches": launch,
         "roofline": roof,
         "kernel_us_per_step": {n: round(1e3 * v[0] / max(v[1], 1), 2)

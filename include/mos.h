@@ -126,6 +126,17 @@ typedef struct {
                               that accepted it, without waiting for its turn in OPEN;
                               the front then prunes the search sooner.  The result is
                               the same front. */
+  int32_t pipelined;        /* 0 (default): each step ends with the goal-front filter of
+                              the labels it inserted.  1: that filter runs at the start
+                              of the next step, on a second stream beside the next
+                              step's pop, so the extraction of the next batch overlaps
+                              the current batch's last stage (the current/next bags of
+                              Section 5.1, Algorithm 2).  A label the filter has not yet
+                              removed when it is popped is dropped by the pop-time
+                              goal-front check instead.  The result is the same front;
+                              with a step budget, the prefix is still exact.  The
+                              engine of a batch or server call runs all its queries in
+                              the mode of that call. */
 } mos_options;
 
 /* Counters of one query (paper, Section 6: label extractions, candidate

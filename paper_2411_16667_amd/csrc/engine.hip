@@ -179,6 +179,7 @@ struct EngineKey {
   int64_t label_limit;
   bool paths;
   int steps;
+  bool pipelined;  // not part of the match: a cached engine switches mode per call
   bool operator==(const EngineKey& o) const {
     return S == o.S && dm == o.dm && budget == o.budget && stream == o.stream && B == o.B &&
            label_limit == o.label_limit && paths == o.paths && steps == o.steps;
@@ -359,6 +360,12 @@ class Engine {
 
   ~Engine() {
     hipStreamSynchronize(st_);
+    if (st2_) {
+      hipStreamSynchronize(st2_);
+      hipStreamDestroy(st2_);
+      hipEventDestroy(fork_);
+      hipEventDestroy(join_);
+    }
     for (auto& e : pev_) hipEventDestroy(e);
     if (graph_exec_) hipGraphExecDestroy(graph_exec_);
 
@@ -374,6 +381,23 @@ class Engine {
     hjob_.reset();
     omin_.reset();
     if (own_stream_) hipStreamDestroy(st_);
+  }
+
+  // Pipelined steps (set while no query is resident): the goal-front filter
+  // of a step's new labels runs beside the next step's pop, on a second
+  // stream.  A change of mode drops the captured step graph.
+  void set_pipelined(bool p) {
+    if (p != pipelined_ && graph_exec_) {
+      HIPCHK(hipGraphExecDestroy(graph_exec_));
+      graph_exec_ = nullptr;
+      graph_failed_ = false;
+    }
+    pipelined_ = p;
+    if (p && !st2_) {
+      HIPCHK(hipStreamCreateWithFlags(&st2_, hipStreamNonBlocking));
+      HIPCHK(hipEventCreateWithFlags(&fork_, hipEventDisableTiming));
+      HIPCHK(hipEventCreateWithFlags(&join_, hipEventDisableTiming));
+    }
   }
 
   int64_t arena_bytes() const { return ra_.total * 256; }
@@ -504,6 +528,7 @@ class Engine {
       s.pop_fifo = q.pop_order == MOS_POP_GENERATION ? 1 : 0;
       s.eps_ppm = q.eps_ppm;
       s.eager_goal = q.eager_goal;
+      s.pipelined = pipelined_ ? 1 : 0;
       carve(s, arena_.as<char>() + off * 256, L, g_->n, q.d);
       HIPCHK(hipMemcpyAsync((char*)slots_.p + (size_t)free_slot * sizeof(Slot), &s, sizeof(Slot),
                             hipMemcpyHostToDevice, st_));
@@ -720,6 +745,10 @@ class Engine {
       a.gc = (int)std::max<int64_t>(1, std::min<int64_t>(gx_, (cand + 255) / 256));
     }
     a.dm = DM_;
+    a.pipelined = pipelined_ ? 1 : 0;
+    a.st2 = st2_;
+    a.fork = fork_;
+    a.join = join_;
     return a;
   }
 
@@ -770,7 +799,7 @@ class Engine {
   // event sets is drained as it wraps and at every poll.
   static constexpr int RING = 32;
   void profiled_step(const StepArgs& a) {
-    constexpr int NE = kStepKernels + 1;
+    constexpr int NE = 2 * kStepKernels + 1;
     if (pev_.empty()) {
       pev_.resize((size_t)RING * NE);
       for (auto& e : pev_) HIPCHK(hipEventCreate(&e));
@@ -783,13 +812,13 @@ class Engine {
     ++direct_steps_;
   }
   void drain_one() {
-    constexpr int NE = kStepKernels + 1;
+    constexpr int NE = 2 * kStepKernels + 1;
     hipEvent_t* set = &pev_[(size_t)ring_head_ * NE];
-    HIPCHK(hipEventSynchronize(set[kStepKernels]));
+    HIPCHK(hipEventSynchronize(set[2 * kStepKernels]));
     for (int i = 0; i < kStepKernels; ++i) {
       if (!((profile_ >> i) & 1u)) continue;
       float ms = 0;
-      HIPCHK(hipEventElapsedTime(&ms, set[i], set[i + 1]));
+      HIPCHK(hipEventElapsedTime(&ms, set[2 * i], set[2 * i + 1]));
       kms_[i] += ms;
       klaunch_[i]++;
     }
@@ -888,6 +917,9 @@ class Engine {
   const mos_graph* g_;
   int S_, DM_, B_;
   int widen_ = 1, Bplan_ = 1;  // tail widening factor; batch width the slot layouts allow
+  bool pipelined_ = false;
+  hipStream_t st2_ = nullptr;  // pipelined steps: the pop's stream
+  hipEvent_t fork_ = nullptr, join_ = nullptr;
   int64_t label_limit_;
   bool want_paths_;
   int K_;
@@ -925,10 +957,13 @@ static Engine* acquire_engine(const mos_graph* gc, const EngineKey& k, int64_t b
       if (g->pool[i].first == k) {
         Engine* e = g->pool[i].second;
         g->pool.erase(g->pool.begin() + i);
+        e->set_pipelined(k.pipelined);
         return e;
       }
   }
-  return new Engine(g, k.S, k.dm, budget, stream, k.B, k.label_limit, k.paths, k.steps);
+  Engine* e = new Engine(g, k.S, k.dm, budget, stream, k.B, k.label_limit, k.paths, k.steps);
+  e->set_pipelined(k.pipelined);
+  return e;
 }
 
 static void release_engine(const mos_graph* gc, const EngineKey& k, Engine* e) {
@@ -974,6 +1009,8 @@ mos_status mos_internal_read_options(const mos_options* o, MosOpts* out) {
       r.eps_ppm = o->epsilon_ppm;
     if (o->struct_size >= offsetof(mos_options, eager_goal) + sizeof(int32_t))
       r.eager_goal = o->eager_goal ? 1 : 0;
+    if (o->struct_size >= offsetof(mos_options, pipelined) + sizeof(int32_t))
+      r.pipelined = o->pipelined ? 1 : 0;
   }
   if (r.B < 1 || r.B > BATCH_MAX)
     return set_err(MOS_E_INVALID_ARG, "batch_width must lie in [1, 32768]");
@@ -1146,7 +1183,7 @@ mos_status mos_solve_batch(const mos_graph* g, int32_t nq, const int32_t* starts
     int S = 1;
     while (S < want) S <<= 1;
     const EngineKey key{S, dm_for(g->D), o.mem_budget, (void*)o.stream, o.B, o.label_limit,
-                        o.want_paths != 0, o.steps};
+                        o.want_paths != 0, o.steps, o.pipelined != 0};
     Engine* ep = acquire_engine(g, key, default_budget(o.mem_budget), (hipStream_t)o.stream);
     std::unique_ptr<Engine> guard(ep);
     Engine& eng = *ep;
@@ -1294,6 +1331,7 @@ mos_status mos_session_create(const mos_graph* g, int32_t start, int32_t goal,
     s->g = g;
     s->eng.reset(new Engine(g, 1, dm_for(d), default_budget(o.mem_budget), (hipStream_t)o.stream, o.B,
                             o.label_limit, o.want_paths != 0, o.steps));
+    s->eng->set_pipelined(o.pipelined != 0);
     s->eng->set_profile(o.profile);
     QueryReq q;
     q.id = 0;
@@ -1530,6 +1568,7 @@ mos_status mos_server_create_ex(const mos_graph* g, int64_t mem_budget, int32_t 
     const int S = max_slots > 0 ? max_slots : 64;
     s->eng.reset(new Engine(g, S, dm_for(g->D), default_budget(mem_budget), nullptr, o.B,
                             o.label_limit, o.want_paths != 0, o.steps));
+    s->eng->set_pipelined(o.pipelined != 0);
     if (const char* x = std::getenv("MOS_SERVER_FAIL_AT_TICK")) s->fail_at_tick = std::atoll(x);
     s->th = std::thread([p = s.get()] { p->loop(); });
     *out = s.release();

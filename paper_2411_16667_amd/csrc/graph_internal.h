@@ -19,6 +19,7 @@ struct MosOpts {
   int32_t pop_order = 0;  // MOS_POP_*
   int32_t eps_ppm = 0;    // approximate mode (0 = exact)
   int32_t eager_goal = 0;
+  int32_t pipelined = 0;
   void* stream = nullptr;  // hipStream_t
 };
 

@@ -15,15 +15,24 @@ struct StepArgs {
   int gx;  // workgroups per slot of the tiled kernels
   int gc;  // workgroups per slot of the per-candidate kernels (enough for one candidate per thread)
   int dm;  // compile-time bound on the objectives of every slot (2,3,4,5,6,8)
+  // pipelined step: the pop runs on st2 beside the previous step's goal-front
+  // filter on the main stream (fork and join through the two events)
+  int pipelined = 0;
+  hipStream_t st2 = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
 };
 
 // Smallest supported compile-time objective bound >= d.
 int dm_for(int d);
 
-// One batched label step over every resident slot: a fixed sequence of
-// kStepKernels kernels.  With ev != nullptr, the kernels i whose bit is set in
-// `mask` are bracketed by events: ev[i] is recorded before kernel i and
-// ev[i + 1] after it; ev[kStepKernels] is always recorded after the last one.
+// One batched label step over every resident slot: a fixed set of
+// kStepKernels kernels.  Synchronous order: pop, goal step, expansion,
+// frontier checks, insertion, goal-front filter of the new labels, step end.
+// Pipelined (a.pipelined): the previous step's goal-front filter runs beside
+// this step's pop (two streams), then the rest in order; in profile mode the
+// same order on one stream.  With ev != nullptr, the kernels i whose bit is set
+// in `mask` are bracketed by events ev[2i] (before) and ev[2i + 1] (after);
+// ev[2 * kStepKernels] is always recorded after the last kernel.
 constexpr int kStepKernels = 23;
 extern const char* const kStepKernelNames[kStepKernels];
 void launch_step(const StepArgs& a, hipStream_t st, hipEvent_t* ev = nullptr,

@@ -140,6 +140,8 @@ __global__ void k_slot_seed(Slot* slots, int s, GraphDev G) {
   S->Lpseq[0] = 0;
   for (int k = 0; k < d; ++k) S->Lg[(size_t)k * S->pool_cap] = 0;
   S->n_labels = 1;
+  S->pf_base = 1;  // no label of a previous step waits for its goal-front filter
+  S->pf_n = 0;
   NodeRec r;
   r.off = 0;
   r.cap = MINCAP;

@@ -105,6 +105,8 @@ struct Slot {
                      // (1 + eps_ppm / 10^6)-dominance (approximate front)
   int32_t eager_goal;  // 1: labels accepted at the goal join the goal front in the
                        // next step's goal step instead of waiting in OPEN to be popped
+  int32_t pipelined;   // 1: the goal-front filter of a step's new labels runs at the
+                       // start of the next step, beside its pop (pf_base, pf_n)
 
   int32_t* h;          // d planes of n: heuristic
   NodeRec* node;       // n
@@ -170,6 +172,8 @@ struct Slot {
   int32_t r_keep, lo_refill, blocks_a, blocks_b;
   int32_t spill_T, spill_on, accept_near, accept_far;
   int32_t pop_nb, pop_keep;      // set by k_batch_finalize: direct pops, near-tier length
+  int32_t pf_base, pf_n;         // set by k_step_end: the labels the step inserted, for a
+                                 // goal-front filter that runs after it (pipelined)
 
   int64_t st[NSTAT];
 };

@@ -1293,7 +1293,7 @@ __global__ __launch_bounds__(NT_TILE) void k_popcheck(Slot* slots, GraphDev G) {
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const int lt = t / ngrp, gi = t - lt * ngrp;
     int ii[2], lab[2] = {0, 0};
-    bool have[2], dom[2] = {false, false};
+    bool have[2], dom[2] = {false, false}, gone[2] = {false, false};
     int4 F[2][NW];
     __syncthreads();  // the previous item is done with sh_first
     if (threadIdx.x == 0) sh_seq = INT32_MAX;
@@ -1308,6 +1308,14 @@ __global__ __launch_bounds__(NT_TILE) void k_popcheck(Slot* slots, GraphDev G) {
       for (int k = 0; k < NW * 4; ++k) f[k] = 0;
       if (have[h]) {
         lab[h] = S.reg[ii[h]];
+        // pipelined steps: the previous step's goal-front filter, which ran
+        // beside this step's pop, may have removed the label after the pop
+        // took it; every other popped label has been tested by that filter
+        // up to its Lpseq mark (the filter finished before this kernel)
+        gone[h] = S.pipelined && S.Lstate[lab[h]] == L_DEAD;
+        have[h] = !gone[h];
+      }
+      if (have[h]) {
         seq = min(seq, S.Lpseq[lab[h]]);
         const int v = S.Lnode[lab[h]];
 #pragma unroll
@@ -1337,7 +1345,7 @@ __global__ __launch_bounds__(NT_TILE) void k_popcheck(Slot* slots, GraphDev G) {
                          examined);
 #pragma unroll
     for (int h = 0; h < 2; ++h)
-      if (have[h] && dom[h] && atomicExch(&S.reg_kill[ii[h]], 1) == 0) {
+      if (((have[h] && dom[h]) || gone[h]) && atomicExch(&S.reg_kill[ii[h]], 1) == 0) {
         S.Lstate[lab[h]] = L_DEAD;
         ++killed;
       }
@@ -1414,7 +1422,10 @@ __global__ __launch_bounds__(NT_TILE) void k_pfilter(Slot* slots, GraphDev G) {
   Slot* Sp = &slots[blockIdx.y];
   const Slot S = *Sp;
   if (S.status != S_RUN) return;
-  const int R = S.accept_n, np = S.P_n, base = S.n_labels;
+  // the labels of this step's insertion, or of the previous step's when the
+  // filter runs beside the next pop (the pop resets accept_n meanwhile)
+  const int R = S.pipelined ? S.pf_n : S.accept_n, np = S.P_n;
+  const int base = S.pipelined ? S.pf_base : S.n_labels;
   if (R == 0 || np == 0) return;
   constexpr int LPT = 4;           // labels per thread
   constexpr int LT = LPT * NT_TILE;  // labels per tile
@@ -2340,6 +2351,8 @@ __global__ void k_step_end(Slot* slots, int nslots) {
   if (s >= nslots) return;
   Slot* S = &slots[s];
   if (S->status != S_RUN) return;
+  S->pf_base = S->n_labels;
+  S->pf_n = S->accept_n;
   S->n_labels += S->accept_n;
   S->st[ST_INSERTED] += S->accept_n;
   S->open_n = S->keep_n + S->accept_near;
@@ -2367,36 +2380,62 @@ static void launch_step_dm(const StepArgs& a, hipStream_t st, hipEvent_t* ev, ui
   // OPEN scans: several entries per thread, so that the per-workgroup appends
   // (one atomic per counter and workgroup) stay few
   const dim3 scan(std::min(a.gx, 256), a.nslots);
-  int i = 0;
-  auto mark = [&]() {
-    const bool need = i == kStepKernels || ((mask >> i) & 1u) || (i > 0 && ((mask >> (i - 1)) & 1u));
-    if (ev && need) hipEventRecord(ev[i], st);
-    ++i;
+  // kernel i on stream s, bracketed by events when profiled
+  auto run = [&](int i, hipStream_t s, auto&& launch) {
+    const bool timed = ev && ((mask >> i) & 1u);
+    if (timed) hipEventRecord(ev[2 * i], s);
+    launch(s);
+    if (timed) hipEventRecord(ev[2 * i + 1], s);
   };
-  mark(); hipLaunchKernelGGL(k_far_hist, refill, dim3(NT_TILE), 0, st, a.slots, a.hist);
-  mark(); hipLaunchKernelGGL(k_far_move, refill, dim3(NT_TILE), 0, st, a.slots);
-  mark(); hipLaunchKernelGGL(k_open_hist, scan, dim3(NT_TILE), 0, st, a.slots, a.hist);
-  mark(); hipLaunchKernelGGL(k_open_threshold, per, dim3(NT_SLOT), 0, st, a.slots, a.hist);
-  mark(); hipLaunchKernelGGL(k_open_scatter, scan, dim3(NT_TILE), 0, st, a.slots);
-  mark(); hipLaunchKernelGGL(k_batch_finalize<DM>, per, dim3(NT_SLOT), 0, st, a.slots, a.G);
-  mark(); hipLaunchKernelGGL(k_split_count, tiled, dim3(NT_TILE), 0, st, a.slots, a.G);
-  mark(); hipLaunchKernelGGL(k_split_scan, tiled, dim3(NT_TILE), 0, st, a.slots, a.G);
-  mark(); hipLaunchKernelGGL(k_goal_pairs<DM>, tiled, dim3(NT_TILE), 0, st, a.slots);
-  mark(); hipLaunchKernelGGL(k_goal_merge<DM>, per, dim3(NT_SLOT), 0, st, a.slots);
-  mark(); hipLaunchKernelGGL(k_popcheck<DM>, tiled, dim3(NT_TILE), 0, st, a.slots, a.G);
-  mark(); hipLaunchKernelGGL(k_expand<DM>, cand, dim3(NT_TILE), 0, st, a.slots, a.G);
-  mark(); hipLaunchKernelGGL(k_group_count, cand, dim3(NT_TILE), 0, st, a.slots);
-  mark(); hipLaunchKernelGGL(k_group_offsets, per, dim3(NT_SLOT), 0, st, a.slots);
-  mark(); hipLaunchKernelGGL(k_group_scatter, cand, dim3(NT_TILE), 0, st, a.slots);
-  mark(); hipLaunchKernelGGL(k_group_process<DM>, tiled, dim3(NT_TILE), 0, st, a.slots);
-  mark(); hipLaunchKernelGGL(k_group_pairs<DM>, tiled, dim3(NT_TILE), 0, st, a.slots);
-  mark(); hipLaunchKernelGGL(k_group_finish<DM>, tiled, dim3(NT_TILE), 0, st, a.slots);
-  mark(); hipLaunchKernelGGL(k_accept_count, cand, dim3(NT_TILE), 0, st, a.slots);
-  mark(); hipLaunchKernelGGL(k_accept_scan, cand, dim3(NT_TILE), 0, st, a.slots);
-  mark(); hipLaunchKernelGGL(k_insert<DM>, cand, dim3(NT_TILE), 0, st, a.slots, a.G);
-  mark(); hipLaunchKernelGGL(k_pfilter<DM>, tiled, dim3(NT_TILE), 0, st, a.slots, a.G);
-  mark(); hipLaunchKernelGGL(k_step_end, dim3((a.nslots + 63) / 64), dim3(64), 0, st, a.slots, a.nslots);
-  mark();
+  auto pop = [&](hipStream_t s) {
+    run(0, s, [&](hipStream_t q) { hipLaunchKernelGGL(k_far_hist, refill, dim3(NT_TILE), 0, q, a.slots, a.hist); });
+    run(1, s, [&](hipStream_t q) { hipLaunchKernelGGL(k_far_move, refill, dim3(NT_TILE), 0, q, a.slots); });
+    run(2, s, [&](hipStream_t q) { hipLaunchKernelGGL(k_open_hist, scan, dim3(NT_TILE), 0, q, a.slots, a.hist); });
+    run(3, s, [&](hipStream_t q) { hipLaunchKernelGGL(k_open_threshold, per, dim3(NT_SLOT), 0, q, a.slots, a.hist); });
+    run(4, s, [&](hipStream_t q) { hipLaunchKernelGGL(k_open_scatter, scan, dim3(NT_TILE), 0, q, a.slots); });
+    run(5, s, [&](hipStream_t q) { hipLaunchKernelGGL(k_batch_finalize<DM>, per, dim3(NT_SLOT), 0, q, a.slots, a.G); });
+    run(6, s, [&](hipStream_t q) { hipLaunchKernelGGL(k_split_count, tiled, dim3(NT_TILE), 0, q, a.slots, a.G); });
+    run(7, s, [&](hipStream_t q) { hipLaunchKernelGGL(k_split_scan, tiled, dim3(NT_TILE), 0, q, a.slots, a.G); });
+  };
+  auto pfilter = [&](hipStream_t s) {
+    run(21, s, [&](hipStream_t q) { hipLaunchKernelGGL(k_pfilter<DM>, tiled, dim3(NT_TILE), 0, q, a.slots, a.G); });
+  };
+  if (!a.pipelined) {
+    pop(st);
+  } else if (ev || !a.st2) {
+    pfilter(st);
+    pop(st);
+  } else {
+    // the previous step's filter beside this step's pop: they touch disjoint
+    // state (the filter reads the goal front, the previous step's candidates
+    // and pf_base/pf_n; the pop rewrites OPEN and the batch); label states
+    // are read by the pop and set dead by the filter, and a label popped
+    // before the filter marks it is caught by the pop-time goal-front check
+    hipEventRecord(a.fork, st);
+    hipStreamWaitEvent(a.st2, a.fork, 0);
+    pop(a.st2);
+    pfilter(st);
+    hipEventRecord(a.join, a.st2);
+    hipStreamWaitEvent(st, a.join, 0);
+  }
+  run(8, st, [&](hipStream_t q) { hipLaunchKernelGGL(k_goal_pairs<DM>, tiled, dim3(NT_TILE), 0, q, a.slots); });
+  run(9, st, [&](hipStream_t q) { hipLaunchKernelGGL(k_goal_merge<DM>, per, dim3(NT_SLOT), 0, q, a.slots); });
+  run(10, st, [&](hipStream_t q) { hipLaunchKernelGGL(k_popcheck<DM>, tiled, dim3(NT_TILE), 0, q, a.slots, a.G); });
+  run(11, st, [&](hipStream_t q) { hipLaunchKernelGGL(k_expand<DM>, cand, dim3(NT_TILE), 0, q, a.slots, a.G); });
+  run(12, st, [&](hipStream_t q) { hipLaunchKernelGGL(k_group_count, cand, dim3(NT_TILE), 0, q, a.slots); });
+  run(13, st, [&](hipStream_t q) { hipLaunchKernelGGL(k_group_offsets, per, dim3(NT_SLOT), 0, q, a.slots); });
+  run(14, st, [&](hipStream_t q) { hipLaunchKernelGGL(k_group_scatter, cand, dim3(NT_TILE), 0, q, a.slots); });
+  run(15, st, [&](hipStream_t q) { hipLaunchKernelGGL(k_group_process<DM>, tiled, dim3(NT_TILE), 0, q, a.slots); });
+  run(16, st, [&](hipStream_t q) { hipLaunchKernelGGL(k_group_pairs<DM>, tiled, dim3(NT_TILE), 0, q, a.slots); });
+  run(17, st, [&](hipStream_t q) { hipLaunchKernelGGL(k_group_finish<DM>, tiled, dim3(NT_TILE), 0, q, a.slots); });
+  run(18, st, [&](hipStream_t q) { hipLaunchKernelGGL(k_accept_count, cand, dim3(NT_TILE), 0, q, a.slots); });
+  run(19, st, [&](hipStream_t q) { hipLaunchKernelGGL(k_accept_scan, cand, dim3(NT_TILE), 0, q, a.slots); });
+  run(20, st, [&](hipStream_t q) { hipLaunchKernelGGL(k_insert<DM>, cand, dim3(NT_TILE), 0, q, a.slots, a.G); });
+  if (!a.pipelined) pfilter(st);
+  run(22, st, [&](hipStream_t q) {
+    hipLaunchKernelGGL(k_step_end, dim3((a.nslots + 63) / 64), dim3(64), 0, q, a.slots, a.nslots);
+  });
+  if (ev) hipEventRecord(ev[2 * kStepKernels], st);
 }
 
 int dm_for(int d) {
