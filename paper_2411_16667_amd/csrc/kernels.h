@@ -33,7 +33,7 @@ int dm_for(int d);
 // same order on one stream.  With ev != nullptr, the kernels i whose bit is set
 // in `mask` are bracketed by events ev[2i] (before) and ev[2i + 1] (after);
 // ev[2 * kStepKernels] is always recorded after the last kernel.
-constexpr int kStepKernels = 23;
+constexpr int kStepKernels = 22 + NPASS;
 extern const char* const kStepKernelNames[kStepKernels];
 void launch_step(const StepArgs& a, hipStream_t st, hipEvent_t* ev = nullptr,
                  uint32_t mask = 0xffffffffu);

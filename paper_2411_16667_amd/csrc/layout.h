@@ -27,7 +27,8 @@ inline int64_t fixed_bytes(int64_t n, int d, int batch_cap, int cand_cap, int ti
   b += al(4 * d * n) + al(16 * n) + 2 * al(4 * n);                   // h, node, grp
   b += 3 * al(4 * (int64_t)batch_cap) + al(4 * ((int64_t)batch_cap + 1));  // batch, reg, kill, reg_off
   b += al(4 * ((int64_t)batch_cap + cand_cap)) + al(4 * (int64_t)cand_cap);  // goal list, pending goals
-  b += 13 * al(4 * ((int64_t)cand_cap + 1)) + al(4 * (int64_t)d * cand_cap) + al(8 * (int64_t)cand_cap);
+  b += 12 * al(4 * ((int64_t)cand_cap + 1)) + al(4 * (int64_t)NPASS * ((int64_t)cand_cap + 1));
+  b += al(4 * (int64_t)d * cand_cap) + al(8 * (int64_t)cand_cap);
   b += al(8 * ((int64_t)cand_cap / ACC_TILE + 2));  // per-tile accept counts
   return b + 64 * 256;
 }
@@ -100,7 +101,7 @@ inline bool carve_slot(Slot& s, char* base, const Layout& L, int64_t n, int d) {
   s.grp_off = (int32_t*)take(4 * cc);
   s.small_list = (int32_t*)take(4 * (cc + 1));
   s.big_list = (int32_t*)take(4 * (cc + 1));
-  s.big_toff = (int32_t*)take(4 * (cc + 1));
+  s.big_toff = (int32_t*)take(4 * (int64_t)NPASS * (cc + 1));
   s.c_g = (int32_t*)take(4 * (int64_t)d * cc);
   s.c_fslot = (int64_t*)take(8 * cc);
   s.acc_tile = (int32_t*)take(8 * (cc / ACC_TILE + 2));

@@ -22,6 +22,12 @@ constexpr int TIECAP = 256;       // tie sets up to this size are ranked in LDS;
                                   // are first narrowed by exact radix refinement
 constexpr int MINCAP = 8;         // smallest frontier block, in entries
 constexpr int BATCH_MAX = 32768;  // largest popped batch
+// Pair tiles of large groups run in NPASS launches: pass p covers frontier
+// tiles [pass_lo(p), pass_lo(p + 1)) of every group (pass 0 also the tiles of
+// candidates against candidates); a later pass skips candidates an earlier
+// one rejected.
+constexpr int NPASS = 2;
+__host__ __device__ constexpr int pass_lo(int p) { return p <= 0 ? 0 : (p == 1 ? 1 : 1 << 30); }
 // near-tier sizing, in multiples of B: refill below LOW, refill up to TARGET,
 // spill to far above HIGH (keeping TARGET)
 constexpr int NEAR_LOW = 4, NEAR_TARGET = 16, NEAR_HIGH = 48;
@@ -153,7 +159,8 @@ struct Slot {
   int32_t* grp_off;    // cand_cap: first position of each group in `order`
   int32_t* small_list; // cand_cap: groups handled by one wave in one pass
   int32_t* big_list;   // cand_cap: groups split into pair tiles across waves
-  int32_t* big_toff;   // cand_cap+1: exclusive prefix of the pair tiles of big groups
+  int32_t* big_toff;   // NPASS planes of cand_cap+1: per pass of the pair tiles, the
+                       //   exclusive prefix of the big groups' tiles in that pass
   int32_t* fw;         // frontier words
 
   // ---------------- dynamic (device-updated)
@@ -166,6 +173,7 @@ struct Slot {
   int32_t batch_n, goal_n, reg_n, cand_n;
   int32_t ngroups, tie_n, keep_n, accept_n;
   int32_t nsmall, nbig, big_tiles, err_line;
+  int32_t big_tiles_pass[4];  // pair tiles of each pass (NPASS <= 4)
   // two-tier OPEN: near holds F1 < T (all of OPEN while t_all), far holds F1 >= T
   int32_t far_n, far_sel, T, t_all;
   int32_t refill, r_T, r_all, r_moved;  // refill of near from far, decided per step

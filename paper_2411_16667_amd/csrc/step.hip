@@ -37,6 +37,7 @@ constexpr int PCH = 256;       // goal-front entries per LDS chunk (one per tile
 constexpr int BT_U = 4;        // frontier entries per lane in a pair tile of a large group
 constexpr int BT_ENTRIES = BT_U * WAVE;
 static_assert(PCH == NT_TILE, "goal tiles map one label to one thread");
+static_assert(kStepKernels == 22 + NPASS, "one kernel-name entry per pair pass");
 static_assert(ACC_TILE % NT_TILE == 0, "an accept tile is whole chunks of one workgroup");
 static_assert(SPLIT_TILE % NT_TILE == 0, "a split tile is whole chunks of one workgroup");
 
@@ -1512,8 +1513,8 @@ __global__ __launch_bounds__(NT_SLOT) void k_group_offsets(Slot* slots) {
   const Slot S = *Sp;
   if (S.status != S_RUN) return;
   __shared__ int4 tmp4[NT_SLOT / WAVE];
-  const int ng = S.ngroups;
-  int carry = 0, ns = 0, nb = 0, nt = 0;
+  const int ng = S.ngroups, cc = S.cand_cap;
+  int carry = 0, ns = 0, nb = 0, nt[NPASS] = {};
   for (int base = 0; base < ng; base += NT_SLOT) {
     const int i = base + threadIdx.x;
     int sz = 0, cnt = 0;
@@ -1525,30 +1526,51 @@ __global__ __launch_bounds__(NT_SLOT) void k_group_offsets(Slot* slots) {
     const bool big = i < ng && (sz > WAVE || (int64_t)sz * (cnt + sz) > S.big_work);
     const bool small = i < ng && !big;
     const int nct = (sz + WAVE - 1) / WAVE, nft = (cnt + BT_ENTRIES - 1) / BT_ENTRIES;
-    const int tiles = big ? nct * nct + nft * nct : 0;
+    // pair tiles per pass: pass 0 takes the candidate tiles against each
+    // other and the first frontier tiles; later passes the following ones
+    int tp[NPASS];
+#pragma unroll
+    for (int p = 0; p < NPASS; ++p)
+      tp[p] = big ? (min(nft, pass_lo(p + 1)) - min(nft, pass_lo(p))) * nct + (p ? 0 : nct * nct) : 0;
     int4 tot4;
-    const int4 pre = block_exscan4<NT_SLOT>(make_int4(sz, small ? 1 : 0, big ? 1 : 0, tiles),
+    const int4 pre = block_exscan4<NT_SLOT>(make_int4(sz, small ? 1 : 0, big ? 1 : 0, tp[0]),
                                             &tot4, tmp4);
-    const int ex = pre.x, ps = pre.y, pb = pre.z, pt = pre.w;
-    const int tot = tot4.x, ts = tot4.y, tb = tot4.z, tt = tot4.w;
+    const int ex = pre.x, ps = pre.y, pb = pre.z;
+    const int tot = tot4.x, ts = tot4.y, tb = tot4.z;
+    static_assert(NPASS <= 4, "one scan for the later passes");
+    int4 totp;
+    const int4 prep = block_exscan4<NT_SLOT>(
+        make_int4(NPASS > 1 ? tp[NPASS > 1 ? 1 : 0] : 0, NPASS > 2 ? tp[NPASS > 2 ? 2 : 0] : 0,
+                  NPASS > 3 ? tp[NPASS > 3 ? 3 : 0] : 0, 0),
+        &totp, tmp4);
+    const int pt[4] = {pre.w, prep.x, prep.y, prep.z};
+    const int ttot[4] = {tot4.w, totp.x, totp.y, totp.z};
     if (i < ng) S.grp_off[i] = carry + ex;
     if (small) S.small_list[ns + ps] = i;
     if (big) {
       S.big_list[nb + pb] = i;
-      S.big_toff[nb + pb] = nt + pt;
+#pragma unroll
+      for (int p = 0; p < NPASS; ++p) S.big_toff[(size_t)p * (cc + 1) + nb + pb] = nt[p] + pt[p];
     }
     carry += tot;
     ns += ts;
     nb += tb;
-    nt += tt;
+#pragma unroll
+    for (int p = 0; p < NPASS; ++p) nt[p] += ttot[p];
   }
   if (threadIdx.x == 0) {
+    int all = 0;
+#pragma unroll
+    for (int p = 0; p < NPASS; ++p) {
+      S.big_toff[(size_t)p * (cc + 1) + nb] = nt[p];
+      Sp->big_tiles_pass[p] = nt[p];
+      all += nt[p];
+    }
     Sp->st[ST_T0 + 6] += nb;
-    Sp->st[ST_T0 + 7] += nt;
-    S.big_toff[nb] = nt;
+    Sp->st[ST_T0 + 7] += all;
     Sp->nsmall = ns;
     Sp->nbig = nb;
-    Sp->big_tiles = nt;
+    Sp->big_tiles = all;
     Sp->st[ST_GROUPS] += ng;
   }
 }
@@ -1843,11 +1865,13 @@ __global__ __launch_bounds__(NT_TILE) void k_group_process(Slot* slots) {
 // Rejections are idempotent stores; a prune sets PRUNED_BIT in the entry's
 // label-id slot with an atomic OR, and the first setter marks the label dead.
 template <int DM>
-__global__ __launch_bounds__(NT_TILE) void k_group_pairs(Slot* slots) {
+__global__ __launch_bounds__(NT_TILE) void k_group_pairs(Slot* slots, int pass) {
   Slot* Sp = &slots[blockIdx.y];
   const Slot S = *Sp;
   if (S.status != S_RUN) return;
-  const int total = S.big_tiles, nbig = S.nbig;
+  const int total = Sp->big_tiles_pass[pass], nbig = S.nbig;
+  const int32_t* toff = S.big_toff + (size_t)pass * (S.cand_cap + 1);
+  const int lvl0 = pass_lo(pass);
   const int wave = threadIdx.x / WAVE, lane = lane_id();
   const int d = S.d, cc = S.cand_cap;
   int32_t* fw = S.fw;
@@ -1858,16 +1882,17 @@ __global__ __launch_bounds__(NT_TILE) void k_group_pairs(Slot* slots) {
     int lo_i = 0, hi_i = nbig - 1;  // big group owning tile tt
     while (lo_i < hi_i) {
       const int mid = (lo_i + hi_i + 1) >> 1;
-      if (S.big_toff[mid] <= tt) lo_i = mid; else hi_i = mid - 1;
+      if (toff[mid] <= tt) lo_i = mid; else hi_i = mid - 1;
     }
     const int gid = S.big_list[lo_i];
-    const int local = tt - S.big_toff[lo_i];
+    const int local = tt - toff[lo_i];
     const int v = S.grp_node[gid];
     const int k = S.grp_cnt[v];
     const int32_t* ord = S.order + S.grp_off[gid];
     const int nct = (k + WAVE - 1) / WAVE;
-    const bool is_a = local < nct * nct;
-    const int rest = is_a ? local : local - nct * nct;
+    // pass 0: A-tiles first; then frontier tiles from the pass's first level
+    const bool is_a = !pass && local < nct * nct;
+    const int rest = is_a ? local : (pass ? local : local - nct * nct) + lvl0 * nct;
     const int I = rest / nct, J = rest % nct;
     // candidate tile J, one candidate per lane
     const int j = J * WAVE + lane;
@@ -1932,8 +1957,12 @@ __global__ __launch_bounds__(NT_TILE) void k_group_pairs(Slot* slots) {
       int pacc[BT_U];
 #pragma unroll
       for (int u = 0; u < BT_U; ++u) pacc[u] = 0;
-#pragma unroll 4
-      for (int jj = 0; jj < nj; ++jj) {
+      // a candidate already rejected (by the first pass, or by another tile)
+      // can prune no live entry (the frontier is an antichain, and a candidate
+      // below it prunes the same entries), so its row is skipped
+      const uint64_t live = ballot(hj && !S.c_rej[fj]);
+      for (uint64_t m = live; m; m &= m - 1) {
+        const int jj = __ffsll((long long)m) - 1;
         int4 cw[NW];
 #pragma unroll
         for (int w = 0; w < NW; ++w) cw[w] = cstage[wave][jj][w];
@@ -2369,8 +2398,8 @@ const char* const kStepKernelNames[kStepKernels] = {
     "k_far_hist",      "k_far_move",      "k_open_hist",     "k_open_threshold", "k_open_scatter",
     "k_batch_finalize", "k_split_count",  "k_split_scan",    "k_goal_pairs",   "k_goal_merge",    "k_popcheck",       "k_expand",
     "k_group_count",   "k_group_offsets", "k_group_scatter", "k_group_process",  "k_group_pairs",
-    "k_group_finish",  "k_accept_count",  "k_accept_scan",   "k_insert",         "k_pfilter",
-    "k_step_end"};
+    "k_group_pairs2",  "k_group_finish",  "k_accept_count",  "k_accept_scan",    "k_insert",
+    "k_pfilter",       "k_step_end"};
 
 template <int DM>
 static void launch_step_dm(const StepArgs& a, hipStream_t st, hipEvent_t* ev, uint32_t mask) {
@@ -2398,7 +2427,7 @@ static void launch_step_dm(const StepArgs& a, hipStream_t st, hipEvent_t* ev, ui
     run(7, s, [&](hipStream_t q) { hipLaunchKernelGGL(k_split_scan, tiled, dim3(NT_TILE), 0, q, a.slots, a.G); });
   };
   auto pfilter = [&](hipStream_t s) {
-    run(21, s, [&](hipStream_t q) { hipLaunchKernelGGL(k_pfilter<DM>, tiled, dim3(NT_TILE), 0, q, a.slots, a.G); });
+    run(20 + NPASS, s, [&](hipStream_t q) { hipLaunchKernelGGL(k_pfilter<DM>, tiled, dim3(NT_TILE), 0, q, a.slots, a.G); });
   };
   if (!a.pipelined) {
     pop(st);
@@ -2426,13 +2455,14 @@ static void launch_step_dm(const StepArgs& a, hipStream_t st, hipEvent_t* ev, ui
   run(13, st, [&](hipStream_t q) { hipLaunchKernelGGL(k_group_offsets, per, dim3(NT_SLOT), 0, q, a.slots); });
   run(14, st, [&](hipStream_t q) { hipLaunchKernelGGL(k_group_scatter, cand, dim3(NT_TILE), 0, q, a.slots); });
   run(15, st, [&](hipStream_t q) { hipLaunchKernelGGL(k_group_process<DM>, tiled, dim3(NT_TILE), 0, q, a.slots); });
-  run(16, st, [&](hipStream_t q) { hipLaunchKernelGGL(k_group_pairs<DM>, tiled, dim3(NT_TILE), 0, q, a.slots); });
-  run(17, st, [&](hipStream_t q) { hipLaunchKernelGGL(k_group_finish<DM>, tiled, dim3(NT_TILE), 0, q, a.slots); });
-  run(18, st, [&](hipStream_t q) { hipLaunchKernelGGL(k_accept_count, cand, dim3(NT_TILE), 0, q, a.slots); });
-  run(19, st, [&](hipStream_t q) { hipLaunchKernelGGL(k_accept_scan, cand, dim3(NT_TILE), 0, q, a.slots); });
-  run(20, st, [&](hipStream_t q) { hipLaunchKernelGGL(k_insert<DM>, cand, dim3(NT_TILE), 0, q, a.slots, a.G); });
+  for (int p = 0; p < NPASS; ++p)
+    run(16 + p, st, [&](hipStream_t q) { hipLaunchKernelGGL(k_group_pairs<DM>, tiled, dim3(NT_TILE), 0, q, a.slots, p); });
+  run(16 + NPASS, st, [&](hipStream_t q) { hipLaunchKernelGGL(k_group_finish<DM>, tiled, dim3(NT_TILE), 0, q, a.slots); });
+  run(17 + NPASS, st, [&](hipStream_t q) { hipLaunchKernelGGL(k_accept_count, cand, dim3(NT_TILE), 0, q, a.slots); });
+  run(18 + NPASS, st, [&](hipStream_t q) { hipLaunchKernelGGL(k_accept_scan, cand, dim3(NT_TILE), 0, q, a.slots); });
+  run(19 + NPASS, st, [&](hipStream_t q) { hipLaunchKernelGGL(k_insert<DM>, cand, dim3(NT_TILE), 0, q, a.slots, a.G); });
   if (!a.pipelined) pfilter(st);
-  run(22, st, [&](hipStream_t q) {
+  run(21 + NPASS, st, [&](hipStream_t q) {
     hipLaunchKernelGGL(k_step_end, dim3((a.nslots + 63) / 64), dim3(64), 0, q, a.slots, a.nslots);
   });
   if (ev) hipEventRecord(ev[2 * kStepKernels], st);

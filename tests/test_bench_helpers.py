@@ -56,9 +56,11 @@ def test_every_step_kernel_has_byte_accounting():
     src = open(os.path.join(ROOT, "paper_2411_16667_amd", "csrc", "step.hip")).read()
     table = src[src.index("kStepKernelNames[kStepKernels] = {"):]
     names = re.findall(r'"(k_\w+)"', table[:table.index("};")])
-    n = int(re.search(r"kStepKernels\s*=\s*(\d+)",
-                      open(os.path.join(ROOT, "paper_2411_16667_amd", "csrc", "kernels.h")).read())
-            .group(1))
+    csrc = os.path.join(ROOT, "paper_2411_16667_amd", "csrc")
+    n = int(re.search(r"kStepKernels\s*=\s*(\d+) \+ NPASS",
+                      open(os.path.join(csrc, "kernels.h")).read()).group(1))
+    n += int(re.search(r"constexpr int NPASS = (\d+);",
+                       open(os.path.join(csrc, "mos_core.h")).read()).group(1))
     assert len(names) == n == len(set(names))
     c = {k: 1 for k in ("pops", "killed", "candidates", "inserted", "frontier_bytes",
                         "frontier_bytes_onepass", "far_scanned", "near_scanned", "tie_entries",
@@ -68,6 +70,7 @@ def test_every_step_kernel_has_byte_accounting():
     for k in names:
         assert bench.kernel_bytes(k, c, 3, 1) > 0 or k == "k_step_end", k
     assert bench.kernel_ops("k_group_pairs", c, 3) > 0
+    assert bench.kernel_ops(bench.PAIR_UNIT, c, 3) > 0
 
 
 def test_cpu_baseline_fields():
