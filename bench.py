@@ -792,6 +792,12 @@ def main():
                                       "right after the timed steps"}
     roof["bytes_per_launch"] = nbytes / max(launches, 1)
     roof["intensity_ops_per_byte"] = intensity
+    if dom == PAIR_UNIT:
+        roof["ops_model"] = ("2d int32 ops per (candidate, frontier entry or candidate) pair of "
+                             "the large groups that the two pair passes decide, over their summed "
+                             "duration per step; the second pass skips the rows of candidates "
+                             "already rejected, so the vector units execute fewer (SQ instruction "
+                             "counters of both passes in profiles/)")
 
     out = {
         "metric": METRIC,
