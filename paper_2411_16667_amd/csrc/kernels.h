@@ -46,8 +46,11 @@ void launch_heur_clamp(Slot* slots, const int32_t* slot_of, int njobs, const Gra
                        hipStream_t st);
 void launch_slot_init(Slot* slots, int s, const GraphDev& G, hipStream_t st);
 // The whole heuristic of the slots slot_of[0 .. njobs): init, relaxation
-// rounds until no worklist is left (the host reads the counters every 8
-// rounds into cnt_host[njobs * MAXD * 3]), clamp.  hs: njobs * MAXD * 3 * n
+// rounds until no worklist is left, clamp.  The rounds run in one workgroup
+// per (query, objective) instance; one whose worklist outgrows its workgroup
+// continues in grid-wide rounds (the host reads the counters into
+// cnt_host[njobs * MAXD * 3] after the workgroups and every 8 grid-wide
+// rounds).  hs: njobs * MAXD * 3 * n
 // ints of device scratch; cnt: njobs * MAXD * 3 device ints.  0 on success,
 // -1 on a HIP error, -2 if the rounds did not converge.
 int run_heuristic(Slot* slots, const int32_t* slot_of, int njobs, const GraphDev& G, int32_t* hs,

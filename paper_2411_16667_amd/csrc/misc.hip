@@ -6,7 +6,8 @@
 // relaxation over the reversed arcs from the goal.  Each round relaxes the
 // arcs entering the nodes improved in the previous round; a round stamp per
 // node keeps every worklist duplicate-free.  All (query, objective) instances
-// of an admission wave run in the same launches.
+// of an admission wave run in the same launches: one workgroup each, handing
+// an instance over to grid-wide rounds when its worklist grows wide.
 #include "kernels.h"
 
 namespace mos {
@@ -74,6 +75,77 @@ __global__ void k_heur_round(Slot* slots, const int32_t* slot_of, GraphDev G, in
         }
       }
     }
+  }
+}
+
+// Persistent form of the same search: one workgroup runs the rounds of one
+// (query, objective) instance, the worklist lengths in LDS and a workgroup
+// barrier between rounds, so a round costs no launch and no host poll.  The
+// rounds, relaxations and stamps are those of k_heur_round; the lengths are
+// read after a barrier, so every thread leaves the loop together.  On exit the
+// instance's counters say where it stopped:
+//   finished          c = {0, 0, 0}
+//   handed over       c = {r + 1, 0, len}: at an even round r the worklist (in
+//                     list A) held len > limit nodes; the grid-wide rounds
+//                     carry on from there
+//   no convergence    c[1] = 1 (after 4n + 64 rounds; the host fails it)
+constexpr int NT_HP = 1024;
+__global__ __launch_bounds__(NT_HP) void k_heur_persistent(Slot* slots, const int32_t* slot_of,
+                                                          GraphDev G, int32_t* hs, int32_t* cnt,
+                                                          int limit) {
+  const int j = blockIdx.z, k = blockIdx.y;
+  Slot* S = &slots[slot_of[j]];
+  if (k >= S->d) return;
+  const int n = G.n;
+  int32_t* h = S->h + (size_t)k * n;
+  int32_t* base = hs + ((size_t)j * MAXD + k) * 3 * n;
+  int32_t* stamp = base + 2 * (size_t)n;
+  int32_t* c = cnt + ((size_t)j * MAXD + k) * 3;
+  const int32_t* cost = G.cost + (size_t)k * G.m;
+  __shared__ int len[2];  // worklist lengths: list r & 1 is this round's, the other the next's
+  if (threadIdx.x == 0) {
+    len[0] = 1;  // k_heur_init put the goal in list 0
+    len[1] = 0;
+  }
+  __syncthreads();
+  for (int r = 0;; ++r) {
+    const int ncur = len[r & 1];
+    if (ncur == 0) {
+      if (threadIdx.x == 0) c[0] = c[2] = 0;
+      break;
+    }
+    if (ncur > limit && !(r & 1)) {
+      if (threadIdx.x == 0) {
+        c[0] = r + 1;
+        c[2] = ncur;
+      }
+      break;
+    }
+    if (r > 4 * n + 64) {
+      if (threadIdx.x == 0) c[1] = 1;
+      break;
+    }
+    const int32_t* cur = base + (size_t)(r & 1) * n;
+    int32_t* nxt = base + (size_t)((r + 1) & 1) * n;
+    const int h0 = h[S->start];
+    const int64_t cut = (S->heur_factor > 0 && h0 != UNREACH) ? (int64_t)S->heur_factor * h0
+                                                              : INT64_MAX;
+    for (int i = threadIdx.x; i < ncur; i += NT_HP) {
+      const int v = cur[i];
+      const int dv = h[v];
+      for (int p = G.rrow[v]; p < G.rrow[v + 1]; ++p) {
+        const int u = G.rsrc[p];
+        const int nd = dv + cost[G.rarc[p]];
+        if (nd < h[u]) {
+          const int old = atomicMin(&h[u], nd);
+          if (nd < old && nd <= cut && atomicMax(&stamp[u], r + 1) < r + 1)
+            nxt[atomicAdd(&len[(r + 1) & 1], 1)] = u;
+        }
+      }
+    }
+    __syncthreads();  // the round is done and every thread has read len[r & 1]
+    if (threadIdx.x == 0) len[r & 1] = 0;
+    __syncthreads();
   }
 }
 
@@ -244,20 +316,49 @@ int run_heuristic(Slot* slots, const int32_t* slot_of, int njobs, const GraphDev
                   int32_t* cnt, int32_t* cnt_host, hipStream_t st) {
   launch_heur_init(slots, slot_of, njobs, G, hs, cnt, st);
   if (hipGetLastError() != hipSuccess) return -1;
-  const int gx = std::max(1, std::min(512, (G.n / 8 + 255) / 256));
+  // Every instance starts in its own workgroup.  One whose worklist outgrows
+  // a few wavefronts' worth is handed to the grid-wide rounds, which spread a
+  // wide front over many CUs; on a small graph with enough instances to fill
+  // the chip, every instance instead runs to the end in its workgroup (its
+  // arrays stay cache-resident and the round launches would dominate).
   const size_t nc = (size_t)njobs * MAXD * 3;
-  for (int r = 0;; ++r) {
-    launch_heur_round(slots, slot_of, njobs, G, hs, cnt, r, gx, st);
-    if ((r & 7) == 7) {
-      if (hipMemcpyAsync(cnt_host, cnt, nc * 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
-          hipStreamSynchronize(st) != hipSuccess)
-        return -1;
-      // after round r the worklist of round r + 1 is in counter (r + 1) % 3
-      bool any = false;
-      for (size_t i = (r + 1) % 3; i < nc && !any; i += 3) any = cnt_host[i] > 0;
-      if (!any) break;
+  const bool whole = (int64_t)njobs * G.D >= 16 && G.n <= (1 << 18);
+  const int limit = whole ? INT32_MAX : 256;
+  hipLaunchKernelGGL(k_heur_persistent, dim3(1, MAXD, njobs), dim3(NT_HP), 0, st, slots, slot_of,
+                     G, hs, cnt, limit);
+  if (hipGetLastError() != hipSuccess ||
+      hipMemcpyAsync(cnt_host, cnt, nc * 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return -1;
+  int r0 = -1;  // the latest hand-over round (even, so every list is list A)
+  for (size_t i = 0; i < nc; i += 3) {
+    if (cnt_host[i + 1]) return -2;
+    if (cnt_host[i] > 0) r0 = std::max(r0, cnt_host[i] - 1);
+  }
+  if (r0 >= 0) {
+    // the grid-wide rounds resume at round r0 for all handed-over instances:
+    // the count of round r0 sits in counter r0 % 3, the other two are zero;
+    // the stamps left behind are all <= r0, so no node is kept out of a list
+    for (size_t i = 0; i < nc; i += 3) {
+      const int32_t len = cnt_host[i] > 0 ? cnt_host[i + 2] : 0;
+      cnt_host[i] = cnt_host[i + 1] = cnt_host[i + 2] = 0;
+      cnt_host[i + r0 % 3] = len;
     }
-    if (r > 4 * G.n + 64) return -2;
+    if (hipMemcpyAsync(cnt, cnt_host, nc * 4, hipMemcpyHostToDevice, st) != hipSuccess) return -1;
+    const int gx = std::max(1, std::min(512, (G.n / 8 + 255) / 256));
+    for (int r = r0;; ++r) {
+      launch_heur_round(slots, slot_of, njobs, G, hs, cnt, r, gx, st);
+      if ((r & 7) == 7) {
+        if (hipMemcpyAsync(cnt_host, cnt, nc * 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+          return -1;
+        // after round r the worklist of round r + 1 is in counter (r + 1) % 3
+        bool any = false;
+        for (size_t i = (r + 1) % 3; i < nc && !any; i += 3) any = cnt_host[i] > 0;
+        if (!any) break;
+      }
+      if (r > 4 * G.n + 64) return -2;
+    }
   }
   launch_heur_clamp(slots, slot_of, njobs, G, st);
   return hipGetLastError() == hipSuccess ? 0 : -1;
