@@ -84,6 +84,10 @@ def parse():
                          "objectives; orders: lexicographic against generation (FIFO) "
                          "OPEN order, labels popped and time to the exact front; "
                          "pipelined: synchronous against pipelined steps, the same measures")
+    ap.add_argument("--persistent-query", action="store_true",
+                    help="queries leg and served workload: every query runs its steps in "
+                         "one workgroup of its own (mos_options.persistent_query), against "
+                         "the default multi-kernel step")
     ap.add_argument("--synchronous", action="store_true",
                     help="steps workload: run the label steps synchronously (default: "
                          "pipelined, the next batch extracted beside the current batch's "
@@ -326,19 +330,21 @@ def batched_vs_plain(mos, gen, G, a):
         B = tuned["batch_width"]
     # engines are cached per (slot count, width, ...): one untimed call of each
     # form first, so that both timed forms reuse their engine
-    mos.mos_solve_batch(G, S, T, batch_width=B)
-    mos.mos_solve(G, int(S[0]), int(T[0]), batch_width=B)
+    pq = a.persistent_query
+    mos.mos_solve_batch(G, S, T, batch_width=B, persistent_query=pq)
+    mos.mos_solve(G, int(S[0]), int(T[0]), batch_width=B, persistent_query=pq)
     t0 = time.perf_counter()
-    res = mos.mos_solve_batch(G, S, T, batch_width=B)
+    res = mos.mos_solve_batch(G, S, T, batch_width=B, persistent_query=pq)
     t_batched = time.perf_counter() - t0
     t0 = time.perf_counter()
-    plain = [mos.mos_solve(G, int(S[q]), int(T[q]), batch_width=B) for q in range(len(S))]
+    plain = [mos.mos_solve(G, int(S[q]), int(T[q]), batch_width=B, persistent_query=pq)
+             for q in range(len(S))]
     t_plain = time.perf_counter() - t0
     same = all(st == mos.MOS_OK and np.array_equal(r.costs, p.costs)
                for (st, r), p in zip(res, plain))
     fronts = [len(p.costs) for p in plain]
     return {"queries": len(S), "manhattan_distance": list(a.qdist), "batch_width": B,
-            "autotune": tuned,
+            "autotune": tuned, "persistent_query": bool(pq),
             "batched_qps": len(S) / t_batched, "plain_qps": len(S) / t_plain,
             "speedup": t_plain / t_batched, "same_fronts": bool(same),
             "front_sizes": {"min": min(fronts), "median": int(np.median(fronts)), "max": max(fronts)}}
@@ -407,12 +413,15 @@ def served_bench(a):
           file=sys.stderr, flush=True)
     # plain: one query at a time through mos_solve
     npl = min(nq, 200)
-    mos.mos_solve(G, int(S[0]), int(T[0]), n_objectives=int(D[0]))
+    pq = a.persistent_query
+    mos.mos_solve(G, int(S[0]), int(T[0]), n_objectives=int(D[0]), persistent_query=pq)
     tp = time.perf_counter()
-    plain = [mos.mos_solve(G, int(S[i]), int(T[i]), n_objectives=int(D[i])) for i in range(npl)]
+    plain = [mos.mos_solve(G, int(S[i]), int(T[i]), n_objectives=int(D[i]), persistent_query=pq)
+             for i in range(npl)]
     plain_qps = npl / (time.perf_counter() - tp)
     print(f"served: plain {plain_qps:.1f} q/s", file=sys.stderr, flush=True)
-    srv = mos.Server(G, max_slots=a.slots)
+    srv = mos.Server(G, max_slots=a.slots, persistent_query=True) if pq else \
+        mos.Server(G, max_slots=a.slots)
     lat, wall, res = run_stream(srv, S[:nq], T[:nq], D[:nq], np.zeros(nq))
     sat = nq / wall
     same = all(r is not None and r[0] == mos.MOS_OK and np.array_equal(r[1].costs, p.costs)
@@ -440,7 +449,8 @@ def served_bench(a):
            "dtype": "int32", "data": "synthetic",
            "config": {"workload": f"1M-node 8-NN geometric graph, 5 stored objectives, d~U{{3,4,5}}, "
                                   f"goals within {a.radius} of the start", "slots": a.slots,
-                      "batch_width": 256, "queries_per_point": nq},
+                      "batch_width": 256, "queries_per_point": nq,
+                      "persistent_query": bool(pq)},
            "plain_qps": plain_qps, "served_vs_plain": sat / plain_qps,
            "same_fronts_as_plain": bool(same), "points": points, "server_counters": c,
            "front_sizes": {"min": min(fronts), "median": int(np.median(fronts)),

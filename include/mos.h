@@ -137,6 +137,20 @@ typedef struct {
                               with a step budget, the prefix is still exact.  The
                               engine of a batch or server call runs all its queries in
                               the mode of that call. */
+  int32_t persistent_query; /* 0 (default): every step of every resident query is the
+                              fixed sequence of grid-wide kernels.  1 (mos_solve,
+                              mos_solve_batch, the server): each query runs its steps
+                              inside one workgroup of its own, many steps per launch
+                              with workgroup barriers between the phases of a step
+                              (the batch is every OPEN label below an F1 bound; a
+                              label reaching the goal joins the goal front at once).
+                              For short queries, whose steps cannot fill the GPU.  The
+                              result is the same front; the witness path of a front
+                              vector reached by several equal-cost paths may differ
+                              from mode 0's.  Ignored (mode 0) with a step budget, the
+                              generation order, epsilon_ppm > 0 or a graph with an
+                              out-degree above 1024; a query whose smallest-F1 labels
+                              exceed one batch is moved to mode 0 and run again. */
 } mos_options;
 
 /* Counters of one query (paper, Section 6: label extractions, candidate

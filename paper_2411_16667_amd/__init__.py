@@ -45,7 +45,8 @@ class mos_options(ctypes.Structure):
                 ("steps_per_poll", ctypes.c_int32), ("profile_kernels", ctypes.c_int32),
                 ("heuristic_radius", ctypes.c_int32), ("step_budget", ctypes.c_int64),
                 ("pop_order", ctypes.c_int32), ("epsilon_ppm", ctypes.c_int32),
-                ("eager_goal", ctypes.c_int32), ("pipelined", ctypes.c_int32)]
+                ("eager_goal", ctypes.c_int32), ("pipelined", ctypes.c_int32),
+                ("persistent_query", ctypes.c_int32)]
 
 
 class mos_stats(ctypes.Structure):
@@ -234,7 +235,7 @@ def make_options(n_objectives=0, batch_width=0, max_slots=0, label_limit=0, mem_
                  stream=None, costs_only=False, steps_per_poll=0,
                  profile_kernels=False, heuristic_radius=0, step_budget=0,
                  pop_order="lexicographic", epsilon_ppm=0, eager_goal=False,
-                 pipelined=False) -> mos_options:
+                 pipelined=False, persistent_query=False) -> mos_options:
     o = mos_options()
     o.struct_size = ctypes.sizeof(mos_options)
     o.n_objectives = int(n_objectives)
@@ -253,6 +254,7 @@ def make_options(n_objectives=0, batch_width=0, max_slots=0, label_limit=0, mem_
     o.epsilon_ppm = int(epsilon_ppm)
     o.eager_goal = 1 if eager_goal else 0
     o.pipelined = 1 if pipelined else 0
+    o.persistent_query = 1 if persistent_query else 0
     return o
 
 

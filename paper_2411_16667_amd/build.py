@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmos.so")
-SOURCES = ["step.hip", "misc.hip", "front.hip", "engine.hip", "noalloc.hip"]
+SOURCES = ["step.hip", "solo.hip", "misc.hip", "front.hip", "engine.hip", "noalloc.hip"]
 ARCH = os.environ.get("MOS_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
          # no packed-FP32 instructions anywhere in the device code

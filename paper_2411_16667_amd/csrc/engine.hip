@@ -291,6 +291,7 @@ struct QueryReq {
   int32_t pop_order = 0;    // MOS_POP_*
   int32_t eps_ppm = 0;      // approximate mode (0 = exact)
   int32_t eager_goal = 0;
+  int32_t solo = 0;         // steps run in one workgroup of its own (persistent_query)
 };
 
 struct Finished {
@@ -437,6 +438,8 @@ class Engine {
   // with a step budget keeps the plain width: its exact prefix after that
   // many steps then does not depend on the other queries.
   static constexpr int kWidenLabels = 16384;
+  // steps a one-workgroup query runs per launch (at least the steps per poll)
+  static constexpr int kSoloSteps = 32;
   void widen_slots(bool none_waiting) {
     const int busy = busy_count();
     if (busy == 0) return;
@@ -529,6 +532,7 @@ class Engine {
       s.eps_ppm = q.eps_ppm;
       s.eager_goal = q.eager_goal;
       s.pipelined = pipelined_ ? 1 : 0;
+      s.solo = q.solo;
       carve(s, arena_.as<char>() + off * 256, L, g_->n, q.d);
       HIPCHK(hipMemcpyAsync((char*)slots_.p + (size_t)free_slot * sizeof(Slot), &s, sizeof(Slot),
                             hipMemcpyHostToDevice, st_));
@@ -557,7 +561,16 @@ class Engine {
     for (int s = 0; s < S_; ++s) {
       if (!sh_[s].busy) continue;
       const Slot& d = hslots_[s];
-      if (d.status == S_RUN) {
+      if (d.status == S_SOLO_QUIT) {
+        // more labels of one F1 than a one-workgroup batch holds: run again by
+        // the multi-kernel step
+        QueryReq q = sh_[s].q;
+        release(s);
+        q.solo = 0;
+        pending.push_front(q);
+        continue;
+      }
+      if (d.status == S_RUN || d.status == S_SOLO) {
         const int64_t budget = sh_[s].q.step_budget;
         if (budget > 0 && d.st[ST_STEPS] >= budget) {
           Finished f{sh_[s].q.id, MOS_E_STEP_LIMIT, nullptr,
@@ -772,6 +785,15 @@ class Engine {
   // launched directly, and so is every step in profile mode.
   void launch_steps(int64_t n) {
     const StepArgs a = step_args();
+    int nsolo = 0, nreg = 0;
+    for (int s = 0; s < S_; ++s)
+      if (sh_[s].busy) (sh_[s].q.solo ? nsolo : nreg)++;
+    if (nsolo > 0) {
+      // each such query advances up to this many steps in its own workgroup
+      launch_solo(slots_.as<Slot>(), S_, a.G, DM_, (int)std::max<int64_t>(n, kSoloSteps), st_);
+      HIPCHK(hipGetLastError());
+    }
+    if (nreg == 0) return;
     if (profile_) {
       // events bracketing kernels are not timed when recorded inside a
       // captured graph on this runtime, so profiled steps launch directly
@@ -1011,6 +1033,8 @@ mos_status mos_internal_read_options(const mos_options* o, MosOpts* out) {
       r.eager_goal = o->eager_goal ? 1 : 0;
     if (o->struct_size >= offsetof(mos_options, pipelined) + sizeof(int32_t))
       r.pipelined = o->pipelined ? 1 : 0;
+    if (o->struct_size >= offsetof(mos_options, persistent_query) + sizeof(int32_t))
+      r.persistent_query = o->persistent_query ? 1 : 0;
   }
   if (r.B < 1 || r.B > BATCH_MAX)
     return set_err(MOS_E_INVALID_ARG, "batch_width must lie in [1, 32768]");
@@ -1158,6 +1182,18 @@ void mos_graph_destroy(mos_graph* g) {
 }
 
 
+// Whether a query of these options runs its steps in one workgroup of its own
+// (mos_options.persistent_query): not with a step budget (its exact prefix
+// is defined by the multi-kernel step's pops), the generation order or the
+// approximate mode, nor on a graph whose out-degree exceeds the one-workgroup
+// candidate sort.
+static int32_t solo_for(const mos_graph* g, const Opts& o) {
+  return o.persistent_query && o.step_budget == 0 && o.pop_order == MOS_POP_LEXICOGRAPHIC &&
+                 o.eps_ppm == 0 && g->maxdeg <= kSoloMaxDeg
+             ? 1
+             : 0;
+}
+
 mos_status mos_solve_batch(const mos_graph* g, int32_t nq, const int32_t* starts,
                            const int32_t* goals, const int32_t* n_objectives,
                            const mos_options* opt, mos_result** out, mos_status* st) {
@@ -1199,6 +1235,7 @@ mos_status mos_solve_batch(const mos_graph* g, int32_t nq, const int32_t* starts
       q.pop_order = o.pop_order;
       q.eps_ppm = o.eps_ppm;
       q.eager_goal = o.eager_goal;
+      q.solo = solo_for(g, o);
       q.reserve = eng.default_reserve();
       pending.push_back(q);
       out[i] = nullptr;
@@ -1457,6 +1494,7 @@ struct mos_server {
   int32_t pop_order = 0;
   int32_t eps_ppm = 0;
   int32_t eager_goal = 0;
+  int32_t solo = 0;
 
   // The loop cannot go on (a device error): every query that has not been
   // reported yet -- finished this tick, resident in a slot, queued here or
@@ -1565,6 +1603,7 @@ mos_status mos_server_create_ex(const mos_graph* g, int64_t mem_budget, int32_t 
     s->pop_order = o.pop_order;
     s->eps_ppm = o.eps_ppm;
     s->eager_goal = o.eager_goal;
+    s->solo = solo_for(g, o);
     const int S = max_slots > 0 ? max_slots : 64;
     s->eng.reset(new Engine(g, S, dm_for(g->D), default_budget(mem_budget), nullptr, o.B,
                             o.label_limit, o.want_paths != 0, o.steps));
@@ -1599,6 +1638,7 @@ mos_status mos_server_submit(mos_server* s, int32_t start, int32_t goal, int32_t
   q.pop_order = s->pop_order;
   q.eps_ppm = s->eps_ppm;
   q.eager_goal = s->eager_goal;
+  q.solo = s->solo;
   q.reserve = s->eng->default_reserve();
   s->inbox.push_back(q);
   s->known[(uint64_t)q.id] = false;

@@ -20,6 +20,7 @@ struct MosOpts {
   int32_t eps_ppm = 0;    // approximate mode (0 = exact)
   int32_t eager_goal = 0;
   int32_t pipelined = 0;
+  int32_t persistent_query = 0;
   void* stream = nullptr;  // hipStream_t
 };
 

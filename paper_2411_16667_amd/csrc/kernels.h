@@ -38,6 +38,13 @@ extern const char* const kStepKernelNames[kStepKernels];
 void launch_step(const StepArgs& a, hipStream_t st, hipEvent_t* ev = nullptr,
                  uint32_t mask = 0xffffffffu);
 
+// Per-query persistent step: one workgroup per slot runs up to max_steps label
+// steps of its query (slots in state S_SOLO only; the others are left alone).
+// Queries of a graph whose out-degree exceeds kSoloMaxDeg are not run this way.
+constexpr int kSoloMaxDeg = 1024;
+void launch_solo(Slot* slots, int nslots, const GraphDev& G, int dm, int max_steps,
+                 hipStream_t st);
+
 void launch_heur_init(Slot* slots, const int32_t* slot_of, int njobs, const GraphDev& G,
                       int32_t* hs, int32_t* cnt, hipStream_t st);
 void launch_heur_round(Slot* slots, const int32_t* slot_of, int njobs, const GraphDev& G,

@@ -236,7 +236,7 @@ __global__ void k_slot_seed(Slot* slots, int s, GraphDev G) {
   S->blocks_b = 0;
   S->lo = key0;
   S->st[ST_INSERTED] = 1;
-  S->status = S_RUN;
+  S->status = S->solo ? S_SOLO : S_RUN;
 }
 
 // Witness paths (paper, Section 3: parent pointers allow path reconstruction)

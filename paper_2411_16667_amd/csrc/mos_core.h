@@ -45,6 +45,8 @@ enum SlotStatus : int32_t {
   S_RUN = 1,
   S_DONE = 2,
   S_OVERFLOW = 3,  // a capacity of the reservation was exceeded
+  S_SOLO = 4,      // running: the query's steps run in one workgroup of its own
+  S_SOLO_QUIT = 5, // left the one-workgroup step: to be run by the multi-kernel step
 };
 
 enum LabelState : uint8_t { L_OPEN = 0, L_CLOSED = 1, L_DEAD = 2 };
@@ -113,6 +115,7 @@ struct Slot {
                        // next step's goal step instead of waiting in OPEN to be popped
   int32_t pipelined;   // 1: the goal-front filter of a step's new labels runs at the
                        // start of the next step, beside its pop (pf_base, pf_n)
+  int32_t solo;        // 1: the query's steps run in one workgroup of its own (S_SOLO)
 
   int32_t* h;          // d planes of n: heuristic
   NodeRec* node;       // n

@@ -85,3 +85,27 @@ def test_no_device_reported_cleanly(mos):
     st, _ = _create(mos, g.n, g.row_ptr, g.col, g.cost, 3)
     assert st == mos.MOS_E_NO_DEVICE
     assert b"device" in mos.raw.mos_last_error()
+
+
+def _header_struct_fields(name):
+    """(type, field) of each member of `typedef struct { ... } name;` in mos.h,
+    comments removed."""
+    import re
+
+    txt = open(__import__("paper_2411_16667_amd").HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    end = re.search(r"\}\s*" + name + r";", txt).start()
+    body = txt[txt.rindex("typedef struct {", 0, end) + len("typedef struct {"):end]
+    return re.findall(r"(u?int(?:32|64)_t|void\s*\*|double)\s*(\w+)\s*;", body)
+
+
+@pytest.mark.parametrize("name,cls", [("mos_options", "mos_options"), ("mos_stats", "mos_stats")])
+def test_binding_structs_follow_the_header(mos, name, cls):
+    """The ctypes mirrors of the option and statistics structs list the
+    header's members in the same order with the same widths."""
+    fields = _header_struct_fields(name)
+    mirror = getattr(mos, cls)._fields_
+    assert [f for _, f in fields] == [f for f, _ in mirror]
+    width = {"int32_t": 4, "uint32_t": 4, "int64_t": 8, "uint64_t": 8, "double": 8}
+    for (t, f), (_, ct) in zip(fields, mirror):
+        assert ctypes.sizeof(ct) == width.get(t.replace(" ", ""), ctypes.sizeof(ctypes.c_void_p)), f
