@@ -890,14 +890,21 @@ class Engine {
     std::unique_ptr<mos_result> r(new mos_result());
     const int dd = d.d;
     const int nall = d.P_n;
-    DevBuf fsw, rows, labs;
+    // read-out scratch, carved from a grow-only buffer of the engine (results
+    // are read out one at a time on the engine's stream)
+    const auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t b_fsw = al(front_sort_scratch_bytes(std::max(nall, 1)));
+    const size_t b_rows = al((size_t)std::max(nall, 1) * dd * 4), b_labs = al((size_t)std::max(nall, 1) * 4);
+    const size_t b_len = b_labs, b_off = al(((size_t)std::max(nall, 1) + 1) * 8);
+    char* hv = (char*)grow(hv_, b_fsw + b_rows + b_labs + b_len + b_off);
+    void* fsw = hv;
+    int32_t* rows = (int32_t*)(hv + b_fsw);
+    int32_t* labs = (int32_t*)(hv + b_fsw + b_rows);
+    int32_t* lenp = (int32_t*)(hv + b_fsw + b_rows + b_labs);
+    int64_t* offp = (int64_t*)(hv + b_fsw + b_rows + b_labs + b_len);
     int np = 0;
     if (nall > 0) {
-      fsw.alloc(front_sort_scratch_bytes(nall), st_);
-      rows.alloc((size_t)nall * dd * 4, st_);
-      labs.alloc((size_t)nall * 4, st_);
-      np = front_sort(d.Pg[d.P_sel], d.P_cap, d.Plab[d.P_sel], dd, nall, fsw.p, rows.as<int32_t>(),
-                      labs.as<int32_t>(), st_);
+      np = front_sort(d.Pg[d.P_sel], d.P_cap, d.Plab[d.P_sel], dd, nall, fsw, rows, labs, st_);
       if (np < 0) HIPCHK(hipGetLastError());
       if (np < 0) throw MosError(MOS_E_DEVICE, "front sort failed");
     }
@@ -905,27 +912,23 @@ class Engine {
     r->size = np;
     r->costs.resize((size_t)np * dd);
     if (np > 0)
-      HIPCHK(hipMemcpyAsync(r->costs.data(), rows.p, (size_t)np * dd * 4, hipMemcpyDeviceToHost,
+      HIPCHK(hipMemcpyAsync(r->costs.data(), rows, (size_t)np * dd * 4, hipMemcpyDeviceToHost,
                             st_));
     HIPCHK(hipStreamSynchronize(st_));
     if (want_paths_ && np > 0) {
-      DevBuf len, off, arcs;
-      len.alloc(np * 4, st_);
-      launch_path_len(slots_.as<Slot>(), s, labs.as<int32_t>(), (int)np, len.as<int32_t>(), st_);
+      launch_path_len(slots_.as<Slot>(), s, labs, (int)np, lenp, st_);
       std::vector<int32_t> hl(np);
-      HIPCHK(hipMemcpyAsync(hl.data(), len.p, np * 4, hipMemcpyDeviceToHost, st_));
+      HIPCHK(hipMemcpyAsync(hl.data(), lenp, np * 4, hipMemcpyDeviceToHost, st_));
       HIPCHK(hipStreamSynchronize(st_));
       r->path_off.assign(np + 1, 0);
       for (int64_t i = 0; i < np; ++i) r->path_off[i + 1] = r->path_off[i] + hl[i];
       const int64_t tot = r->path_off[np];
       r->arcs.resize(tot);
       if (tot > 0) {
-        off.alloc((np + 1) * 8, st_);
-        arcs.alloc(tot * 4, st_);
-        HIPCHK(hipMemcpyAsync(off.p, r->path_off.data(), (np + 1) * 8, hipMemcpyHostToDevice, st_));
-        launch_path_write(slots_.as<Slot>(), s, labs.as<int32_t>(), (int)np, off.as<int64_t>(),
-                          arcs.as<int32_t>(), st_);
-        HIPCHK(hipMemcpyAsync(r->arcs.data(), arcs.p, tot * 4, hipMemcpyDeviceToHost, st_));
+        int32_t* arcs = (int32_t*)grow(ha_, (size_t)tot * 4);
+        HIPCHK(hipMemcpyAsync(offp, r->path_off.data(), (np + 1) * 8, hipMemcpyHostToDevice, st_));
+        launch_path_write(slots_.as<Slot>(), s, labs, (int)np, offp, arcs, st_);
+        HIPCHK(hipMemcpyAsync(r->arcs.data(), arcs, tot * 4, hipMemcpyDeviceToHost, st_));
       }
       HIPCHK(hipStreamSynchronize(st_));
     } else if (want_paths_) {
@@ -948,6 +951,13 @@ class Engine {
   hipStream_t st_ = nullptr;
   bool own_stream_ = false;
   DevBuf arena_, slots_, hist_, hscr_, hcnt_, hjob_, omin_;
+  DevBuf hv_, ha_;  // result read-out scratch (front sort, rows, path offsets; path arcs)
+  // b with at least n bytes (grown by doubling; the engine's stream is idle
+  // between read-outs, so the old contents need not survive)
+  void* grow(DevBuf& b, size_t n) {
+    if (b.bytes < n) b.alloc(std::max(n, 2 * b.bytes), st_);
+    return b.p;
+  }
   Slot* hslots_ = nullptr;
   RangeAlloc ra_;
   std::vector<SlotHost> sh_;
