@@ -94,3 +94,43 @@ def test_server_cancel_and_poll(mos, road):
     with pytest.raises(mos.MosError):
         srv.poll(tks[0])  # a ticket is collected once
     srv.close()
+
+
+def test_loop_failure_reports_every_query():
+    """A failure of the request loop, forced from the host by a test hook that
+    throws before a given tick (no device fault), ends every query not yet
+    reported -- finished that tick, resident, queued or still in the inbox --
+    with the error, so that a wait without a time limit returns; a submit
+    afterwards fails with the same status.  Run in a child process with a time
+    limit, so that a regression (a wait that never returns) fails the test
+    instead of hanging the run."""
+    import os
+    import subprocess
+    import sys
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = r"""
+import gen
+import paper_2411_16667_amd as mos
+g, s, t = gen.config1(0)
+srv = mos.Server(mos.Graph.from_gen(g), max_slots=2, batch_width=64)
+tickets = [srv.submit(a, 1023, 3) for a in range(16)]
+print("STATUSES", " ".join(str(srv.wait(tk)[0]) for tk in tickets), flush=True)
+try:
+    srv.submit(0, 1023, 3)
+    print("SUBMIT ok")
+except mos.MosError as e:
+    print("SUBMIT", e.status)
+srv.close()
+"""
+    env = dict(os.environ, MOS_SERVER_FAIL_AT_TICK="3", PYTHONPATH=root)
+    r = subprocess.run([sys.executable, "-c", code], cwd=root, env=env, capture_output=True,
+                       text=True, timeout=240)
+    assert r.returncode == 0, r.stderr[-2000:]
+    lines = dict(line.split(" ", 1) for line in r.stdout.splitlines() if " " in line)
+    import paper_2411_16667_amd as mos
+
+    sts = [int(x) for x in lines["STATUSES"].split()]
+    assert len(sts) == 16
+    assert set(sts) <= {mos.MOS_OK, mos.MOS_E_DEVICE} and mos.MOS_E_DEVICE in sts, sts
+    assert lines["SUBMIT"] == str(mos.MOS_E_DEVICE)
