@@ -39,8 +39,8 @@ def test_config3_recipe_counts():
 
 
 def test_config5_recipe_counts():
-    # the served graph (survey's measured facts for seed 0): 1M points, 8-NN
-    # symmetric edges, one component, 3,968 zero-cost edges, 5 objectives
+    # the served graph's recipe facts for seed 0: 1M points, 8-NN symmetric
+    # edges, one component, 3,968 zero-cost edges, 5 objectives
     g, _, comp = gen.config5_graph(0)
     assert g.n == 1_000_000 and g.n_arcs == 9_226_156 and g.D == 5
     assert int(((g.cost == 0).all(1)).sum()) // 2 == 3968
