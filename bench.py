@@ -76,14 +76,21 @@ def parse():
     ap.add_argument("--query-width", type=int, default=0,
                     help="batch width B of every query in that comparison (0 = picked by "
                          "the autotuner on a sample of the queries)")
-    ap.add_argument("--workload", choices=("steps", "served", "routes", "orders", "pipelined"),
+    ap.add_argument("--workload", choices=("steps", "served", "routes", "orders", "pipelined",
+                                           "c4"),
                     default="steps",
                     help="steps: label steps of the ship-routing query (the headline line); "
                          "served: the request loop on the 1M-node road-like graph; "
                          "routes: whole queries on the time-expanded routes at up to 12 "
                          "objectives; orders: lexicographic against generation (FIFO) "
                          "OPEN order, labels popped and time to the exact front; "
-                         "pipelined: synchronous against pipelined steps, the same measures")
+                         "pipelined: synchronous against pipelined steps, the same measures; "
+                         "c4: the 512 uneven queries of the batched configuration in one "
+                         "batched call under a step budget, against the plain path on a sample")
+    ap.add_argument("--c4-budget", type=int, default=256,
+                    help="c4 workload: steps per query (a query still running returns the "
+                         "exact part of its front)")
+    ap.add_argument("--c4-width", type=int, default=1024, help="c4 workload: batch width")
     ap.add_argument("--persistent-query", action="store_true",
                     help="queries leg and served workload: every query runs its steps in "
                          "one workgroup of its own (mos_options.persistent_query), against "
@@ -391,6 +398,53 @@ def run_stream(srv, S, T, D, arrivals):
     wall = max(done_at) - t0
     lat = [done_at[i] - (t0 + arrivals[i]) for i in range(n)]
     return lat, wall, res
+
+
+def c4_bench(a):
+    """The batched configuration as generated: 512 start/goal pairs on the 256x256
+    ship grid with Manhattan distance uniform in [10, 400] (fronts from a few
+    vectors to beyond 10^4), one mos_solve_batch call with 256 resident slots.
+    The largest of these queries do not finish in a bench's time, so every
+    query runs under a step budget: one still running then returns the exact
+    part of its front (the entries below its OPEN bound).  The plain path
+    (mos_solve one query at a time, the same budget and width) runs on the first
+    64 queries; both rates count queries returned per second."""
+    import numpy as np
+
+    import gen
+    import paper_2411_16667_amd as mos
+
+    g, S, T = gen.config4(0)
+    G = mos.Graph.from_gen(g)
+    kw = dict(batch_width=a.c4_width, step_budget=a.c4_budget, steps_per_poll=16)
+    mos.mos_solve_batch(G, S[:8], T[:8], max_slots=256, **kw)  # engine and kernels warm
+    t0 = time.perf_counter()
+    res = mos.mos_solve_batch(G, S, T, max_slots=256, **kw)
+    tb = time.perf_counter() - t0
+    complete = sum(1 for st, _ in res if st == mos.MOS_OK)
+    assert all(st in (mos.MOS_OK, mos.MOS_E_STEP_LIMIT) for st, _ in res)
+    vectors = sum(int(r.costs.shape[0]) for _, r in res)
+    print(f"c4: batched call {tb:.1f} s, {complete} complete fronts", file=sys.stderr, flush=True)
+    npl = 64
+    mos.mos_solve(G, int(S[0]), int(T[0]), **kw)
+    t0 = time.perf_counter()
+    plain = [mos.mos_solve(G, int(S[q]), int(T[q]), **kw) for q in range(npl)]
+    tp = time.perf_counter() - t0
+    same = all(np.array_equal(p.costs, r.costs) for p, (_, r) in zip(plain, res[:npl]))
+    fronts = [int(r.costs.shape[0]) for st, r in res if st == mos.MOS_OK]
+    out = {"metric": "queries/s of the 512-query batched configuration (step-budgeted, exact "
+                     "fronts or exact prefixes), batched vs plain, 1 GPU",
+           "value": len(S) / tb, "unit": "queries/s", "n_gpus": 1, "higher_is_better": True,
+           "dtype": "int32", "data": "synthetic",
+           "config": {"workload": "512 queries, 256x256 ship grid d=3, Manhattan distance "
+                                  "U[10,400]", "batch_width": a.c4_width, "slots": 256,
+                      "step_budget": a.c4_budget},
+           "seconds": tb, "complete_fronts": complete, "prefixes": len(S) - complete,
+           "vectors_returned": vectors,
+           "complete_front_sizes": {"median": int(np.median(fronts)) if fronts else 0,
+                                    "max": max(fronts) if fronts else 0},
+           "plain_qps_first_64": npl / tp, "same_output_as_plain_first_64": bool(same)}
+    print(json.dumps(out))
 
 
 def served_bench(a):
@@ -703,6 +757,9 @@ def main():
         return
     if a.workload in ("orders", "pipelined"):
         compare_bench(a, a.workload)
+        return
+    if a.workload == "c4":
+        c4_bench(a)
         return
     if a.copy_calibration > 0:
         import torch
