@@ -47,7 +47,7 @@ namespace mos {
 constexpr int SO_NT = 1024;
 constexpr int SO_WAVES = SO_NT / WAVE;
 constexpr int SO_BINS = 2048;   // F1 histogram bins of the batch threshold
-constexpr int SO_SORT = 8192;   // largest candidate set of one step
+constexpr int SO_CANDS = 8192;   // largest candidate set of one step
 
 #define SFOR_K(k) _Pragma("unroll") for (int k = 0; k < DM; ++k) if (k < d)
 
@@ -141,7 +141,7 @@ __global__ __launch_bounds__(SO_NT) void k_solo(Slot* slots, GraphDev G, int max
   if (Sp->status != S_SOLO) return;
 
   __shared__ int hist[SO_BINS];
-  __shared__ uint8_t acc8[SO_SORT];  // large groups: survivor flag per grouped candidate position
+  __shared__ uint8_t acc8[SO_CANDS];  // large groups: survivor flag per grouped candidate position
   __shared__ int wsum[SO_WAVES];
   __shared__ int s_open_n, s_sel, s_keep, s_nb, s_nvalid, s_nlab, s_flag, s_ng, s_ni;
   __shared__ int s_pick[2];
@@ -175,7 +175,7 @@ __global__ __launch_bounds__(SO_NT) void k_solo(Slot* slots, GraphDev G, int max
   const int maxdeg = max(1, G.maxdeg);
   // batch width: one popped label per thread, and every candidate of the step
   // within the grouping limit and the slot's candidate arrays
-  const int bcap = min(min(min(Sp->B, Sp->batch_cap), SO_NT), min(SO_SORT, cand_cap) / maxdeg);
+  const int bcap = min(min(min(Sp->B, Sp->batch_cap), SO_NT), min(SO_CANDS, cand_cap) / maxdeg);
   const int ln = lane_id(), wv = threadIdx.x / WAVE;
 
   if (threadIdx.x == 0) {
@@ -372,7 +372,7 @@ __global__ __launch_bounds__(SO_NT) void k_solo(Slot* slots, GraphDev G, int max
       deg = G.row_ptr[v + 1] - rb;
     }
     int nc = 0;
-    const int coff = so_exscan(deg, wsum, &nc);  // nc <= bcap * maxdeg <= SO_SORT
+    const int coff = so_exscan(deg, wsum, &nc);  // nc <= bcap * maxdeg <= SO_CANDS
     int nvalid_t = 0;
     for (int q = 0; q < deg; ++q) {
       const int j = coff + q, e = rb + q, w = G.col[e];
