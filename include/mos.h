@@ -149,8 +149,10 @@ typedef struct {
                               vector reached by several equal-cost paths may differ
                               from mode 0's.  Ignored (mode 0) with a step budget, the
                               generation order, epsilon_ppm > 0 or a graph with an
-                              out-degree above 1024; a query whose smallest-F1 labels
-                              exceed one batch is moved to mode 0 and run again. */
+                              out-degree above 1024; a query with one node holding
+                              more labels of the smallest F1 than one batch is moved
+                              to mode 0 and run again.  Slower than mode 0 on every
+                              workload measured (one compute unit per query). */
 } mos_options;
 
 /* Counters of one query (paper, Section 6: label extractions, candidate
