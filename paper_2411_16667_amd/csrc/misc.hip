@@ -296,7 +296,8 @@ void launch_heur_init(Slot* slots, const int32_t* slot_of, int njobs, const Grap
 
 void launch_heur_round(Slot* slots, const int32_t* slot_of, int njobs, const GraphDev& G,
                        int32_t* hs, int32_t* cnt, int r, int gx, hipStream_t st) {
-  hipLaunchKernelGGL(k_heur_round, dim3(gx, MAXD, njobs), dim3(NT_H), 0, st, slots, slot_of, G,
+  // objectives beyond the graph's D belong to no query
+  hipLaunchKernelGGL(k_heur_round, dim3(gx, G.D, njobs), dim3(NT_H), 0, st, slots, slot_of, G,
                      hs, cnt, r);
 }
 
@@ -324,7 +325,7 @@ int run_heuristic(Slot* slots, const int32_t* slot_of, int njobs, const GraphDev
   const size_t nc = (size_t)njobs * MAXD * 3;
   const bool whole = (int64_t)njobs * G.D >= 16 && G.n <= (1 << 18);
   const int limit = whole ? INT32_MAX : 256;
-  hipLaunchKernelGGL(k_heur_persistent, dim3(1, MAXD, njobs), dim3(NT_HP), 0, st, slots, slot_of,
+  hipLaunchKernelGGL(k_heur_persistent, dim3(1, G.D, njobs), dim3(NT_HP), 0, st, slots, slot_of,
                      G, hs, cnt, limit);
   if (hipGetLastError() != hipSuccess ||
       hipMemcpyAsync(cnt_host, cnt, nc * 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
@@ -339,13 +340,22 @@ int run_heuristic(Slot* slots, const int32_t* slot_of, int njobs, const GraphDev
     // the grid-wide rounds resume at round r0 for all handed-over instances:
     // the count of round r0 sits in counter r0 % 3, the other two are zero;
     // the stamps left behind are all <= r0, so no node is kept out of a list
+    int maxlen = 0;
     for (size_t i = 0; i < nc; i += 3) {
       const int32_t len = cnt_host[i] > 0 ? cnt_host[i + 2] : 0;
       cnt_host[i] = cnt_host[i + 1] = cnt_host[i + 2] = 0;
       cnt_host[i + r0 % 3] = len;
+      maxlen = std::max(maxlen, len);
     }
     if (hipMemcpyAsync(cnt, cnt_host, nc * 4, hipMemcpyHostToDevice, st) != hipSuccess) return -1;
-    const int gx = std::max(1, std::min(512, (G.n / 8 + 255) / 256));
+    // workgroups per instance: one worklist node per thread for four times the
+    // longest worklist the host last saw (a round's grid-stride loop covers
+    // any length; the size only sets the parallelism until the next look)
+    const int gmax = std::max(1, std::min(512, (G.n / 8 + 255) / 256));
+    const auto gx_for = [&](int64_t len) {
+      return (int)std::max<int64_t>(1, std::min<int64_t>(gmax, (4 * len + NT_H - 1) / NT_H));
+    };
+    int gx = gx_for(maxlen);
     for (int r = r0;; ++r) {
       launch_heur_round(slots, slot_of, njobs, G, hs, cnt, r, gx, st);
       if ((r & 7) == 7) {
@@ -353,9 +363,10 @@ int run_heuristic(Slot* slots, const int32_t* slot_of, int njobs, const GraphDev
             hipStreamSynchronize(st) != hipSuccess)
           return -1;
         // after round r the worklist of round r + 1 is in counter (r + 1) % 3
-        bool any = false;
-        for (size_t i = (r + 1) % 3; i < nc && !any; i += 3) any = cnt_host[i] > 0;
-        if (!any) break;
+        maxlen = 0;
+        for (size_t i = (r + 1) % 3; i < nc; i += 3) maxlen = std::max(maxlen, cnt_host[i]);
+        if (maxlen == 0) break;
+        gx = gx_for(maxlen);
       }
       if (r > 4 * G.n + 64) return -2;
     }
