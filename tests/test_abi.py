@@ -109,3 +109,18 @@ def test_binding_structs_follow_the_header(mos, name, cls):
     width = {"int32_t": 4, "uint32_t": 4, "int64_t": 8, "uint64_t": 8, "double": 8}
     for (t, f), (_, ct) in zip(fields, mirror):
         assert ctypes.sizeof(ct) == width.get(t.replace(" ", ""), ctypes.sizeof(ctypes.c_void_p)), f
+
+
+def test_status_names_follow_the_header(mos):
+    """The binding's status names and values are the header's enum, in order."""
+    import re
+
+    txt = open(mos.HEADER).read()
+    body = txt[txt.index("typedef enum {"):txt.index("} mos_status;")]
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    pairs = [(n, int(v)) for n, v in re.findall(r"(MOS_[A-Z_]+)\s*=\s*(\d+)", body)]
+    assert [n for n, _ in pairs] == mos.STATUS_NAMES
+    assert [v for _, v in pairs] == list(range(len(pairs)))
+    for n, v in pairs:
+        assert getattr(mos, n) == v
+        assert mos.raw.mos_status_string(v)
